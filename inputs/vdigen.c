@@ -1,0 +1,474 @@
+/*
+ * Seeded synthetic volumes and VDI generation (input generator).
+ *
+ * This file produces the *inputs* of the VDI renderer: a seeded volume, a
+ * transfer function, and the VDI generated from it by the method of the
+ * paper's Section 3 (homogeneity criterion tau of Eq. 1, per-ray sensitivity
+ * gamma found by the bisection of supplement Algorithm S1).  It holds none of
+ * the renderer's arithmetic (list traversal, supersegment search, the opacity
+ * correction of Eq. 2 applied to intersection lengths, compositing of a novel
+ * view).  Both the FP64 oracle and the HIP renderer consume its output as
+ * plain arrays; neither links this file.
+ *
+ * Conventions (shared with the consumers only as data):
+ *   - World is right-handed, y up.  The volume's AABB is centred at the origin
+ *     and its longest side is 1.  Voxels are cell-centred; sampling is
+ *     trilinear with clamp-to-edge.
+ *   - Camera basis F = normalize(target-eye), R = normalize(F x up), U = R x F.
+ *     Pixel (px, py) has its centre at NDC (-1 + (2px+1)/w, -1 + (2py+1)/h),
+ *     py = 0 is the bottom row; fov is vertical.
+ *   - Stored depths are linear view depth z = F.(P - eye) of the generating
+ *     view (monotone in the NDC depth the paper compares, Section 4.2).
+ *   - Host layout is slot-major: depth[NS][H][W][2] = (f, b),
+ *     rgba[NS][H][W][4] = straight colour + accumulated opacity, count[H][W].
+ *
+ * Build: gcc -O2 -fopenmp -shared -fPIC (driven by inputs/__init__.py).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------ */
+/* SplitMix64 (Steele, Lea, Flood 2014): the published 64-bit mixer.   */
+/* ------------------------------------------------------------------ */
+static inline uint64_t sm64(uint64_t z)
+{
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* U[0,1) lattice value for (seed, octave, i, j, k); each index < 2^16. */
+static inline double lattice(uint64_t seedmix, int o, int i, int j, int k)
+{
+    uint64_t idx = ((uint64_t)o << 48) ^ ((uint64_t)(uint32_t)k << 32) ^
+                   ((uint64_t)(uint32_t)j << 16) ^ (uint64_t)(uint32_t)i;
+    return (double)(sm64(seedmix ^ idx) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+/* Value noise: trilinear interpolation of lattice values; p in lattice units. */
+static double vnoise(uint64_t seedmix, int o, double px, double py, double pz)
+{
+    double fx = floor(px), fy = floor(py), fz = floor(pz);
+    int i = (int)fx, j = (int)fy, k = (int)fz;
+    double ux = px - fx, uy = py - fy, uz = pz - fz;
+    double c000 = lattice(seedmix, o, i, j, k), c100 = lattice(seedmix, o, i + 1, j, k);
+    double c010 = lattice(seedmix, o, i, j + 1, k), c110 = lattice(seedmix, o, i + 1, j + 1, k);
+    double c001 = lattice(seedmix, o, i, j, k + 1), c101 = lattice(seedmix, o, i + 1, j, k + 1);
+    double c011 = lattice(seedmix, o, i, j + 1, k + 1), c111 = lattice(seedmix, o, i + 1, j + 1, k + 1);
+    double x00 = c000 + ux * (c100 - c000), x10 = c010 + ux * (c110 - c010);
+    double x01 = c001 + ux * (c101 - c001), x11 = c011 + ux * (c111 - c011);
+    double y0 = x00 + uy * (x10 - x00), y1 = x01 + uy * (x11 - x01);
+    return y0 + uz * (y1 - y0);
+}
+
+static inline double clamp01(double v) { return v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v); }
+
+/* ------------------------------------------------------------------ */
+/* Volumes                                                              */
+/* ------------------------------------------------------------------ */
+
+/* Sum of Gaussian blobs in voxel-index coordinates, clamped to [0,1]. */
+void vg_volume_blobs(int nx, int ny, int nz, int nblob, const double *centres,
+                     const double *sigmas, const double *amps, float *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                double v = 0.0;
+                for (int b = 0; b < nblob; ++b) {
+                    double dx = i - centres[3 * b], dy = j - centres[3 * b + 1], dz = k - centres[3 * b + 2];
+                    double s = sigmas[b];
+                    v += amps[b] * exp(-(dx * dx + dy * dy + dz * dz) / (2.0 * s * s));
+                }
+                out[((size_t)k * ny + j) * nx + i] = (float)clamp01(v);
+            }
+}
+
+/* Mixing-layer slab: fractal value noise (6 octaves, persistence 0.5,
+ * lacunarity 2, base 4 lattice cells per side) times a Gaussian profile in y,
+ * quantised to uint16. */
+void vg_volume_slab_u16(int nx, int ny, int nz, uint64_t seed, uint16_t *out)
+{
+    uint64_t sm = sm64(seed);
+    const int oct = 6;
+    double norm = 0.0;
+    for (int o = 0; o < oct; ++o) norm += ldexp(1.0, -o);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j) {
+            double y = (j + 0.5) / ny, z = (k + 0.5) / nz;
+            double prof = exp(-((y - 0.5) / 0.3) * ((y - 0.5) / 0.3));
+            for (int i = 0; i < nx; ++i) {
+                double x = (i + 0.5) / nx, s = 0.0;
+                for (int o = 0; o < oct; ++o) {
+                    double f = 4.0 * ldexp(1.0, o);
+                    s += ldexp(1.0, -o) * vnoise(sm, o, f * x, f * y, f * z);
+                }
+                double v = clamp01(s / norm * prof);
+                out[((size_t)k * ny + j) * nx + i] = (uint16_t)lround(65535.0 * v);
+            }
+        }
+}
+
+/* Turbulence (8 octaves of |2 vnoise - 1|) restricted to a thick ellipsoidal
+ * shell with a turbulent boundary, values below 0.2 set to zero. */
+void vg_volume_shell_f32(int nx, int ny, int nz, uint64_t seed, float *out)
+{
+    uint64_t sm = sm64(seed);
+    const int oct = 8;
+    double norm = 0.0;
+    for (int o = 0; o < oct; ++o) norm += ldexp(1.0, -o);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j) {
+            double y = (j + 0.5) / ny, z = (k + 0.5) / nz;
+            double ry = (y - 0.5) / 0.5, rz = (z - 0.5) / 0.5;
+            for (int i = 0; i < nx; ++i) {
+                double x = (i + 0.5) / nx, rx = (x - 0.5) / 0.5;
+                double r = sqrt(rx * rx + ry * ry + rz * rz);
+                /* The shell's half-thickness is at most 0.2 + 0.05: skip the noise far away. */
+                if (fabs(r - 0.75) >= 0.25) { out[((size_t)k * ny + j) * nx + i] = 0.0f; continue; }
+                double s = 0.0;
+                for (int o = 0; o < oct; ++o) {
+                    double f = 4.0 * ldexp(1.0, o);
+                    s += ldexp(1.0, -o) * fabs(2.0 * vnoise(sm, o, f * x, f * y, f * z) - 1.0);
+                }
+                double turb = s / norm;
+                double v = (fabs(r - 0.75) < 0.2 + 0.1 * (turb - 0.5)) ? turb : 0.0;
+                if (v < 0.2) v = 0.0;
+                out[((size_t)k * ny + j) * nx + i] = (float)v;
+            }
+        }
+}
+
+/* ------------------------------------------------------------------ */
+/* Transfer functions                                                    */
+/* ------------------------------------------------------------------ */
+enum { TF_RAMP = 0, TF_KNOTS4 = 1 };
+
+static inline void tf_eval(int tf, double v, double *c, double *a)
+{
+    if (tf == TF_RAMP) {
+        c[0] = v;
+        c[1] = 0.25 + 0.5 * v;
+        c[2] = 1.0 - v;
+        *a = 0.2 * clamp01((v - 0.05) / 0.95);
+        return;
+    }
+    static const double kv[4] = {0.0, 0.25, 0.55, 1.0};
+    static const double ka[4] = {0.0, 0.0, 0.04, 0.12};
+    static const double kc[4][3] = {{0.1, 0.2, 0.8}, {0.1, 0.7, 0.9}, {0.95, 0.9, 0.3}, {0.9, 0.15, 0.1}};
+    v = clamp01(v);
+    int s = v < kv[1] ? 0 : (v < kv[2] ? 1 : 2);
+    double u = (v - kv[s]) / (kv[s + 1] - kv[s]);
+    for (int m = 0; m < 3; ++m) c[m] = kc[s][m] + u * (kc[s + 1][m] - kc[s][m]);
+    *a = ka[s] + u * (ka[s + 1] - ka[s]);
+}
+
+/* ------------------------------------------------------------------ */
+/* Volume sampling                                                       */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int nx, ny, nz, is_u16;
+    const void *data;
+    double bmin[3], bmax[3];
+} volume_t;
+
+static inline double voxel(const volume_t *v, int i, int j, int k)
+{
+    size_t o = ((size_t)k * v->ny + j) * v->nx + i;
+    return v->is_u16 ? ((const uint16_t *)v->data)[o] * (1.0 / 65535.0) : (double)((const float *)v->data)[o];
+}
+
+static inline int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
+
+static double sample_tri(const volume_t *v, const double *P)
+{
+    double u[3];
+    int n[3] = {v->nx, v->ny, v->nz};
+    for (int a = 0; a < 3; ++a) u[a] = (P[a] - v->bmin[a]) / (v->bmax[a] - v->bmin[a]) * n[a] - 0.5;
+    int i0[3], i1[3];
+    double w[3];
+    for (int a = 0; a < 3; ++a) {
+        double f = floor(u[a]);
+        w[a] = u[a] - f;
+        i0[a] = clampi((int)f, 0, n[a] - 1);
+        i1[a] = clampi((int)f + 1, 0, n[a] - 1);
+    }
+    double c00 = voxel(v, i0[0], i0[1], i0[2]) * (1 - w[0]) + voxel(v, i1[0], i0[1], i0[2]) * w[0];
+    double c10 = voxel(v, i0[0], i1[1], i0[2]) * (1 - w[0]) + voxel(v, i1[0], i1[1], i0[2]) * w[0];
+    double c01 = voxel(v, i0[0], i0[1], i1[2]) * (1 - w[0]) + voxel(v, i1[0], i0[1], i1[2]) * w[0];
+    double c11 = voxel(v, i0[0], i1[1], i1[2]) * (1 - w[0]) + voxel(v, i1[0], i1[1], i1[2]) * w[0];
+    double c0 = c00 * (1 - w[1]) + c10 * w[1], c1 = c01 * (1 - w[1]) + c11 * w[1];
+    return c0 * (1 - w[2]) + c1 * w[2];
+}
+
+/* ------------------------------------------------------------------ */
+/* Generating rays (one per V_O pixel centre)                             */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    double eye[3], F[3], R[3], U[3], tanh_, aspect, near_;
+    int W, H;
+} gcam_t;
+
+static void g_norm(double *v)
+{
+    double n = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    v[0] /= n; v[1] /= n; v[2] /= n;
+}
+
+static void g_cross(const double *a, const double *b, double *o)
+{
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static void g_camera(const double *cam11, int W, int H, gcam_t *c)
+{
+    /* cam11 = eye[3], target[3], up[3], fov_y_deg, near */
+    for (int a = 0; a < 3; ++a) { c->eye[a] = cam11[a]; c->F[a] = cam11[3 + a] - cam11[a]; }
+    g_norm(c->F);
+    g_cross(c->F, cam11 + 6, c->R);
+    g_norm(c->R);
+    g_cross(c->R, c->F, c->U);
+    c->tanh_ = tan(cam11[9] * M_PI / 360.0);
+    c->aspect = (double)W / (double)H;
+    c->near_ = cam11[10];
+    c->W = W;
+    c->H = H;
+}
+
+/* Ray of pixel (px,py): unit direction d; returns cos(theta) = F.d. */
+static double g_ray(const gcam_t *c, int px, int py, double *d)
+{
+    double xc = -1.0 + (2.0 * px + 1.0) / c->W, yc = -1.0 + (2.0 * py + 1.0) / c->H;
+    for (int a = 0; a < 3; ++a)
+        d[a] = c->F[a] + xc * c->tanh_ * c->aspect * c->R[a] + yc * c->tanh_ * c->U[a];
+    g_norm(d);
+    return c->F[0] * d[0] + c->F[1] * d[1] + c->F[2] * d[2];
+}
+
+/* [t0,t1] = ray ∩ AABB ∩ {z >= near}; returns 0 if empty. */
+static int g_clip(const gcam_t *c, const double *bmin, const double *bmax, const double *d, double cth,
+                  double *t0, double *t1)
+{
+    double lo = c->near_ / cth, hi = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        if (fabs(d[a]) < 1e-300) {
+            if (c->eye[a] < bmin[a] || c->eye[a] > bmax[a]) return 0;
+            continue;
+        }
+        double ta = (bmin[a] - c->eye[a]) / d[a], tb = (bmax[a] - c->eye[a]) / d[a];
+        if (ta > tb) { double t = ta; ta = tb; tb = t; }
+        if (ta > lo) lo = ta;
+        if (tb < hi) hi = tb;
+    }
+    *t0 = lo;
+    *t1 = hi;
+    return hi > lo;
+}
+
+/* ------------------------------------------------------------------ */
+/* Supersegment formation (Eq. 1) over a ray's cached samples             */
+/* ------------------------------------------------------------------ */
+typedef struct { double c[3], a; } smp_t;          /* straight colour, length-adjusted opacity */
+typedef struct { double ts, te, C[3], A; } seg_t;  /* t-range, premultiplied colour, opacity */
+
+/*
+ * Split the samples of one ray into supersegments with sensitivity gamma.
+ * cap == 0: count only (no limit, no output).  cap > 0: at most cap
+ * supersegments; once cap-1 are closed, the last one absorbs every remaining
+ * non-transparent sample, across gaps ("smearing").
+ * Eq. 1 compares premultiplied colours: the open supersegment's straight
+ * colour times its opacity normalised to one sample length, against the next
+ * sample's colour times its opacity.
+ */
+static int split_ray(const smp_t *s, int ns, double t0, double len, double gamma, int cap, seg_t *out)
+{
+    int nclosed = 0, open = 0;
+    seg_t cur;
+    memset(&cur, 0, sizeof cur);
+    for (int q = 0; q < ns; ++q) {
+        int last = cap > 0 && nclosed == cap - 1;
+        if (s[q].a == 0.0) {
+            if (open && !last) {
+                if (out) out[nclosed] = cur;
+                ++nclosed;
+                open = 0;
+            }
+            continue;
+        }
+        double qs = t0 + q * len, qe = t0 + (q + 1) * len;
+        if (open && !last) {
+            double lenS = cur.te - cur.ts;
+            double abar = 1.0 - pow(1.0 - cur.A, len / lenS);
+            double d2 = 0.0;
+            for (int m = 0; m < 3; ++m) {
+                double e = cur.C[m] / cur.A * abar - s[q].c[m] * s[q].a;
+                d2 += e * e;
+            }
+            if (sqrt(d2) >= gamma) {
+                if (out) out[nclosed] = cur;
+                ++nclosed;
+                open = 0;
+            }
+        }
+        if (!open) {
+            cur.ts = qs;
+            cur.te = qe;
+            cur.A = s[q].a;
+            for (int m = 0; m < 3; ++m) cur.C[m] = s[q].a * s[q].c[m];
+            open = 1;
+            continue;
+        }
+        for (int m = 0; m < 3; ++m) cur.C[m] += (1.0 - cur.A) * s[q].a * s[q].c[m];
+        cur.A += (1.0 - cur.A) * s[q].a;
+        cur.te = qe;
+    }
+    if (open) {
+        if (out) out[nclosed] = cur;
+        ++nclosed;
+    }
+    return nclosed;
+}
+
+/*
+ * Generate a VDI.
+ *   vol: nx,ny,nz, is_u16, data; AABB bmin/bmax (3 each).
+ *   cam11: V_O camera (eye, target, up, fov_y_deg, near).
+ *   W,H,NS: VDI resolution and max supersegments per list.
+ *   tf: TF_RAMP or TF_KNOTS4.
+ *   gamma_fixed > 0: fixed sensitivity; else per-ray bisection (Alg. S1) with
+ *   gamma0 = 1e-5, [0, sqrt 3], delta = floor(0.15 NS), eps = 1e-6, <= 25 iters.
+ * Outputs (caller-allocated, zero-filled here):
+ *   count[H*W] u8, depth[NS*H*W*2] f32, rgba[NS*H*W*4] f32,
+ *   dvr[H*W*4] f64 (FP64 DVR composite of the same samples, premultiplied RGB + A; may be NULL),
+ *   gamma_out[H*W] f64 (may be NULL), nuncapped[H*W] i32 (uncapped count at the final gamma; may be NULL).
+ * Returns the total number of supersegments.
+ */
+int64_t vg_generate(int nx, int ny, int nz, int is_u16, const void *data, const double *bmin, const double *bmax,
+                    const double *cam11, int W, int H, int NS, int tf, double gamma_fixed, uint8_t *count,
+                    float *depth, float *rgba, double *dvr, double *gamma_out, int32_t *nuncapped)
+{
+    volume_t vol = {nx, ny, nz, is_u16, data, {bmin[0], bmin[1], bmin[2]}, {bmax[0], bmax[1], bmax[2]}};
+    gcam_t cam;
+    g_camera(cam11, W, H, &cam);
+    int nmax = nx > ny ? nx : ny;
+    if (nz > nmax) nmax = nz;
+    double ext = 0.0;
+    for (int a = 0; a < 3; ++a) ext = fmax(ext, bmax[a] - bmin[a]);
+    const double ds = ext / nmax; /* one voxel of the longest axis */
+    const int maxs = 2 * nmax + 8;
+    const int delta = (int)floor(0.15 * NS);
+    const size_t plane = (size_t)W * H;
+    memset(count, 0, plane);
+    memset(depth, 0, plane * NS * 2 * sizeof(float));
+    memset(rgba, 0, plane * NS * 4 * sizeof(float));
+    int64_t total = 0;
+
+#pragma omp parallel reduction(+ : total)
+    {
+        smp_t *sm = (smp_t *)malloc(sizeof(smp_t) * maxs);
+        seg_t *sg = (seg_t *)malloc(sizeof(seg_t) * (NS + 1));
+#pragma omp for schedule(dynamic, 1)
+        for (int py = 0; py < H; ++py)
+            for (int px = 0; px < W; ++px) {
+                size_t li = (size_t)py * W + px;
+                double d[3], t0, t1;
+                double cth = g_ray(&cam, px, py, d);
+                if (dvr) dvr[4 * li] = dvr[4 * li + 1] = dvr[4 * li + 2] = dvr[4 * li + 3] = 0.0;
+                if (gamma_out) gamma_out[li] = 0.0;
+                if (nuncapped) nuncapped[li] = 0;
+                if (!g_clip(&cam, bmin, bmax, d, cth, &t0, &t1)) continue;
+                int N = (int)ceil((t1 - t0) / ds - 1e-9);
+                if (N < 1) N = 1;
+                if (N > maxs) N = maxs;
+                double len = (t1 - t0) / N;
+                /* Sample at midpoints, front to back, with early termination. */
+                double T = 1.0, acc[3] = {0, 0, 0};
+                int ns = 0;
+                for (int q = 0; q < N; ++q) {
+                    double tm = t0 + (q + 0.5) * len, P[3];
+                    for (int a = 0; a < 3; ++a) P[a] = cam.eye[a] + tm * d[a];
+                    double v = sample_tri(&vol, P), c[3], atf;
+                    tf_eval(tf, v, c, &atf);
+                    double ap = atf > 0.0 ? 1.0 - pow(1.0 - atf, len / ds) : 0.0;
+                    sm[ns].c[0] = c[0]; sm[ns].c[1] = c[1]; sm[ns].c[2] = c[2];
+                    sm[ns].a = ap;
+                    ++ns;
+                    for (int m = 0; m < 3; ++m) acc[m] += T * ap * c[m];
+                    T *= 1.0 - ap;
+                    if (T <= 1e-5) break;
+                }
+                if (dvr) {
+                    dvr[4 * li] = acc[0]; dvr[4 * li + 1] = acc[1]; dvr[4 * li + 2] = acc[2];
+                    dvr[4 * li + 3] = 1.0 - T;
+                }
+                double gamma;
+                if (gamma_fixed > 0.0) {
+                    gamma = gamma_fixed;
+                } else {
+                    double low = 0.0, high = sqrt(3.0);
+                    gamma = 1e-5;
+                    int first = 1;
+                    for (int it = 0;; ++it) {
+                        int n = split_ray(sm, ns, t0, len, gamma, 0, NULL);
+                        int found = 0;
+                        if (fabs(high - low) < 1e-6) {
+                            found = 1;
+                            gamma = (n == 0) ? low : high;
+                        } else if (n > NS) {
+                            low = gamma;
+                        } else if (n < NS - delta) {
+                            high = gamma;
+                        } else {
+                            found = 1;
+                        }
+                        if (first) {
+                            first = 0;
+                            if (n < NS) found = 1;
+                        }
+                        if (found) break;
+                        if (it + 1 >= 25) { gamma = high; break; }
+                        gamma = 0.5 * (low + high);
+                    }
+                }
+                if (gamma_out) gamma_out[li] = gamma;
+                if (nuncapped) nuncapped[li] = split_ray(sm, ns, t0, len, gamma, 0, NULL);
+                int n = split_ray(sm, ns, t0, len, gamma, NS, sg);
+                count[li] = (uint8_t)n;
+                total += n;
+                for (int j = 0; j < n; ++j) {
+                    float f = (float)(sg[j].ts * cth), b = (float)(sg[j].te * cth);
+                    if (!(b > f)) b = nextafterf(f, INFINITY);
+                    size_t o = (size_t)j * plane + li;
+                    depth[2 * o] = f;
+                    depth[2 * o + 1] = b;
+                    double A = sg[j].A;
+                    for (int m = 0; m < 3; ++m) rgba[4 * o + m] = (float)(sg[j].C[m] / A);
+                    rgba[4 * o + 3] = (float)A;
+                }
+            }
+        free(sm);
+        free(sg);
+    }
+    return total;
+}
+
+/* Number of OpenMP threads the generator will use. */
+int vg_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
