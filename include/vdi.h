@@ -1,0 +1,244 @@
+/*
+ * vdi.h -- C ABI of libvdi, a raycaster for Volumetric Depth Images (VDIs) on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * A VDI (Frey et al.; Gupta et al., "Efficient Raycasting of Volumetric Depth
+ * Images for Remote Visualization of Large Volumes at High Frame Rates",
+ * Section 2.3) stores, for every pixel i of the generating view V_O, a list L_i
+ * of up to N_S supersegments S_ij, each with front and back depth f, b and
+ * the colour and opacity accumulated between them.  This library keeps VDIs
+ * resident in device memory and renders them from a new viewpoint V_N
+ * (Section 4), either exactly or as the subsampled preview of Section 4.4.
+ *
+ * Conventions (all entry points):
+ *   - World space is right-handed with y up.  Camera basis:
+ *     F = normalize(target - eye), R = normalize(F x up), U = R x F; the field
+ *     of view is vertical; aspect = image width / height.
+ *   - NDC follows OpenGL: [-1, 1] on both axes; pixel (px, py) has its centre
+ *     at (-1 + (2 px + 1)/w, -1 + (2 py + 1)/h); row 0 is the bottom row
+ *     (y_ndc = -1).  Lists form a regular grid of 2/w x 2/h cells (Fig. 3).
+ *   - Depths are linear view depth of V_O, z = F.(P - eye).  The paper
+ *     compares NDC depths (supplement Alg. S2); NDC depth is monotone in z,
+ *     so every comparison, and the result, is the same.
+ *   - Every call returns VDI_OK (0) or a negative error code; the reason is
+ *     available from vdi_last_error() on the calling thread.  No C++
+ *     exception crosses this interface.
+ */
+#ifndef VDI_H
+#define VDI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Error codes. */
+#define VDI_OK 0
+#define VDI_ERR_ARG (-1)    /* invalid argument (null, size, range, non-finite, invalid VDI) */
+#define VDI_ERR_OOM (-2)    /* device allocation failed */
+#define VDI_ERR_HIP (-3)    /* a HIP runtime call failed */
+#define VDI_ERR_BUDGET (-4) /* serving: request does not fit the memory budget or slots now */
+#define VDI_ERR_STATE (-5)  /* call not valid in the object's current state */
+
+/* Colour storage formats of supersegment RGBA. */
+#define VDI_F32 0  /* 4 x float32, 16 bytes per supersegment */
+#define VDI_F16 1  /* 4 x IEEE binary16 (round to nearest even), 8 bytes */
+#define VDI_BF16 2 /* 4 x bfloat16 (round to nearest even), 8 bytes */
+
+/* First-supersegment search (Section 4.2; all three give the same image). */
+#define VDI_SEARCH_SEEDED 0 /* seeded by the index found in the previous list (supplement Alg. S2) */
+#define VDI_SEARCH_BINARY 1 /* binary search over the whole list, from the middle */
+#define VDI_SEARCH_LINEAR 2 /* linear scan from the list's near end */
+
+#define VDI_MAX_SUPERSEGMENTS 255
+#define VDI_MAX_GRID_NZ 64
+#define VDI_MAX_GRID_K 16
+
+typedef struct vdi_s *vdi_t;
+
+/* Pinhole camera.  fov_y_deg in (0, 180); near_plane > 0. */
+typedef struct {
+    float eye[3];
+    float target[3];
+    float up[3];
+    float fov_y_deg;
+    float near_plane;
+} vdi_camera;
+
+/*
+ * Description of a VDI held in host memory (Section 2.3; Section 5 gives the
+ * paper's texture layout, re-laid out here as slot-major planes).
+ *   width, height       V_O viewport resolution = number of lists (N_L = w h).
+ *   max_supersegments   N_S, 1..255.
+ *   camera_VO           the generating view.
+ *   aabb_min/max        volume bounding box; rays are clipped to it (Section 4.1).
+ *   count   [height][width] uint8, supersegments in each list (<= N_S).
+ *   depth   [N_S][height][width][2] float32, (f, b) of each slot, linear V_O depth.
+ *   rgba    [N_S][height][width][4], straight (non-premultiplied) colour and the
+ *           opacity accumulated over [f, b]; float32 when rgba_fmt_in == VDI_F32,
+ *           16-bit values when VDI_F16 / VDI_BF16.
+ *   rgba_fmt_store      format kept in device memory (conversion from float32
+ *                       rounds to nearest even).
+ *   grid_k, grid_nz     empty-space grid (Section 4.3): cells of grid_k x grid_k
+ *                       lists by one depth slice; grid_k 1..16, grid_nz 1..64.
+ *   grid_z  [grid_nz + 1] increasing float32 slice boundaries (linear V_O depth),
+ *           or NULL to use grid_nz equal slices over the AABB corners' depth range.
+ *   validate  non-zero: check every list (f < b, sorted, non-overlapping,
+ *           count <= N_S, opacity in [0, 1], finite values) before upload.
+ * Slots at index >= count of their list are ignored.
+ */
+typedef struct {
+    int32_t width, height, max_supersegments;
+    vdi_camera camera_VO;
+    float aabb_min[3], aabb_max[3];
+    const uint8_t *count;
+    const float *depth;
+    const void *rgba;
+    int32_t rgba_fmt_in, rgba_fmt_store;
+    int32_t grid_k, grid_nz;
+    const float *grid_z;
+    int32_t validate;
+} vdi_desc;
+
+/* Per-call options of vdi_render_ex.  Neither option changes the image. */
+typedef struct {
+    int32_t ess;    /* 1: empty-space skipping through the count grid (Section 4.3); 0: off */
+    int32_t search; /* VDI_SEARCH_* */
+} vdi_render_opts;
+
+/* Sizes of a resident VDI. */
+typedef struct {
+    int32_t width, height, max_supersegments, rgba_fmt;
+    int32_t grid_k, grid_nz, grid_w, grid_h;
+    uint64_t device_bytes; /* count + depth + colour planes + grid */
+    uint64_t supersegments; /* sum of count */
+} vdi_info_t;
+
+/*
+ * Upload a VDI and build its count grid (Section 4.3: per grid cell, the
+ * number of supersegments of its lists whose [f, b] overlaps the cell's depth
+ * slice with positive length).  Copies every host array: the caller may free
+ * them on return.  Synchronous.  Writes *out only on success.
+ * Errors: VDI_ERR_ARG (null pointers, sizes, N_S or grid shape out of range,
+ * non-finite camera or AABB, formats, and with validate != 0 an invalid list),
+ * VDI_ERR_OOM, VDI_ERR_HIP.
+ */
+int vdi_create(const vdi_desc *desc, vdi_t *out);
+
+/*
+ * Render the VDI from camera cam_VN into out_rgba (Section 4; Eq. 2).
+ *   width, height  output image; aspect = width/height.
+ *   D_I >= 1       image downsampling factor: rays are cast on a
+ *                  round(width/D_I) x round(height/D_I) grid with the same
+ *                  camera and bilinearly upsampled (Section 4.4; the paper's
+ *                  fraction D_I = 0.5 is factor 2 here).
+ *   D_R >= 0       0: exact mode.  > 0: along-ray subsampling (Section 4.4):
+ *                  in each non-empty grid cell a ray takes
+ *                  ceil(((length in cell)/(slice depth)) (count/k^2) / D_R)
+ *                  point samples at regular spacing (the paper's thinning
+ *                  rate is 1/D_R).
+ *   out_rgba       DEVICE pointer owned by the caller, >= width*height*16
+ *                  bytes, receives premultiplied RGB and opacity (float32) over
+ *                  transparent black, row-major, row 0 at the bottom.
+ *   hip_stream     hipStream_t to run on (NULL: the null stream).
+ * Asynchronous with respect to the host.  Reads but never writes the VDI, so
+ * renders of one VDI on several streams may overlap.  The result is
+ * deterministic: the same call gives the same bits.
+ * Errors: VDI_ERR_ARG (null, width/height < 1 or > 16384, D_I < 1, D_R < 0,
+ * non-finite values, fov out of range), VDI_ERR_OOM (preview scratch), VDI_ERR_HIP.
+ */
+int vdi_render(vdi_t v, const vdi_camera *cam_VN, int32_t width, int32_t height, float D_I, float D_R,
+               float *out_rgba, void *hip_stream);
+
+/* vdi_render with explicit options (opts NULL = defaults: ESS on, seeded search). */
+int vdi_render_ex(vdi_t v, const vdi_camera *cam_VN, int32_t width, int32_t height, float D_I, float D_R,
+                  const vdi_render_opts *opts, float *out_rgba, void *hip_stream);
+
+/*
+ * Instrumented exact render (same image as vdi_render with D_I = 1, D_R = 0)
+ * that also records what the rays touched, to measure the algorithmic bytes
+ * of a frame: touched_lists [H_O][W_O] uint8 and touched_slots [N_S][H_O][W_O]
+ * uint8 (device pointers, zeroed by the caller) receive 1 for each list a ray
+ * entered before terminating and each supersegment it composited;
+ * ray_stats [height][width][2] int32 (device, may be NULL) receive per ray
+ * (lists entered, supersegment pieces composited).  Slower than vdi_render.
+ */
+int vdi_render_counters(vdi_t v, const vdi_camera *cam_VN, int32_t width, int32_t height,
+                        const vdi_render_opts *opts, float *out_rgba, uint8_t *touched_lists,
+                        uint8_t *touched_slots, int32_t *ray_stats, void *hip_stream);
+
+/* Copy the count grid, uint32 [grid_nz][grid_h][grid_w], to host memory. */
+int vdi_get_grid(vdi_t v, uint32_t *host_out, size_t capacity_elems);
+
+/* Sizes of a resident VDI. */
+int vdi_get_info(vdi_t v, vdi_info_t *info);
+
+/*
+ * Synchronize outstanding work on the device, then free the VDI's device
+ * memory.  NULL is a no-op.  Destroying the same handle twice is undefined.
+ */
+int vdi_destroy(vdi_t v);
+
+/* Image size used for downsampling factor D_I (round half up, at least 1). */
+int vdi_lowres_size(int32_t width, int32_t height, float D_I, int32_t *w, int32_t *h);
+
+/* Device bytes of the count, depth and colour planes for a w x h x n_s VDI. */
+uint64_t vdi_plane_bytes(int32_t width, int32_t height, int32_t n_s, int32_t rgba_fmt);
+
+/* Reason for the last error on this thread ("" if none). */
+const char *vdi_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Serving (continuous batching).  A server owns one persistent kernel that
+ * renders requests for any number of resident VDIs.  Requests are admitted
+ * while slots and the device-memory budget allow; the work of admitted
+ * requests of different resolution, viewpoint and preview level is spread over
+ * the same running kernel as it arrives, and each request completes on its
+ * own.  A request's image is identical to vdi_render's with the same arguments.
+ * ------------------------------------------------------------------------ */
+typedef struct vdi_server_s *vdi_server_t;
+
+typedef struct {
+    uint64_t submitted, completed, rejected_budget, rejected_slots;
+    uint64_t bytes_in_flight, peak_bytes_in_flight;
+    int32_t inflight, peak_inflight;
+    int32_t kernel_running; /* 1 while the persistent kernel is resident */
+} vdi_server_stats;
+
+/*
+ * Create a server on the current device.
+ *   hbm_budget_bytes  admission budget for the memory of requests in flight
+ *                     (output images plus preview scratch), > 0.
+ *   max_inflight      request slots, 1..4096.
+ *   workers           workgroups of the persistent kernel (0: one per compute unit x 4).
+ * The kernel is launched on a stream of its own and runs until vdi_server_destroy.
+ */
+int vdi_server_create(uint64_t hbm_budget_bytes, int32_t max_inflight, int32_t workers, vdi_server_t *out);
+
+/*
+ * Submit a render request (same arguments as vdi_render).  Returns VDI_OK with
+ * *ticket set, or VDI_ERR_BUDGET when the request does not fit the budget or
+ * the free slots right now (nothing is queued; submit again later).  `out` is
+ * a device pointer the caller keeps alive until the request is done.
+ */
+int vdi_server_submit(vdi_server_t s, vdi_t v, const vdi_camera *cam_VN, int32_t width, int32_t height, float D_I,
+                      float D_R, float *out, uint64_t *ticket);
+
+/* *done = 1 once the request's image is complete and visible to later work. */
+int vdi_server_poll(vdi_server_t s, uint64_t ticket, int *done);
+
+/* Block until all admitted requests are done. */
+int vdi_server_drain(vdi_server_t s);
+
+int vdi_server_get_stats(vdi_server_t s, vdi_server_stats *stats);
+
+/* Drain, stop the persistent kernel, free everything.  NULL is a no-op. */
+int vdi_server_destroy(vdi_server_t s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VDI_H */

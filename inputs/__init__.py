@@ -121,6 +121,9 @@ class VDI:
     name: str = ""
 
     def __post_init__(self):
+        # The bounds travel as float32 through the C ABI; keep exactly those values.
+        self.bmin = tuple(float(np.float32(x)) for x in self.bmin)
+        self.bmax = tuple(float(np.float32(x)) for x in self.bmax)
         if self.grid_z is None:
             self.grid_z = grid_z_for(self.camera, self.bmin, self.bmax, self.grid_nz)
 

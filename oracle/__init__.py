@@ -54,8 +54,8 @@ def _load():
         P = ctypes.c_void_p
         I = ctypes.c_int
         I64 = ctypes.c_int64
-        lib.or_render_exact.argtypes = [P, P, I, I, I64, P, P, P, P, P, I]
-        lib.or_render_preview.argtypes = [P, P, I, I, ctypes.c_double, I64, P, P, P, P, I]
+        lib.or_render_exact.argtypes = [P, P, I, I, ctypes.c_double, I64, P, P, P, P, P, I]
+        lib.or_render_preview.argtypes = [P, P, I, I, ctypes.c_double, ctypes.c_double, I64, P, P, P, P, I]
         lib.or_upsample.argtypes = [P, P, I, I, I, I, P, P]
         lib.or_upsample.restype = None
         lib.or_count_grid.argtypes = [P, P]
@@ -100,7 +100,7 @@ def threads() -> int:
 
 
 def render_exact(vdi, camera, width: int, height: int, pixels=None, rgba: Optional[np.ndarray] = None,
-                 stats: bool = False, touched: bool = False, nthreads: int = 0):
+                 stats: bool = False, touched: bool = False, nthreads: int = 0, aspect: float = 0.0):
     """Exact FP64 render.  Returns out [H, W, 4] (or [npix, 4] for a pixel
     list of row-major indices py*W+px), premultiplied RGB + alpha.
     With stats=True also returns int64 [.., 2] = (lists entered, pieces
@@ -115,8 +115,8 @@ def render_exact(vdi, camera, width: int, height: int, pixels=None, rgba: Option
     st = np.zeros((n, 2), dtype=np.int64) if stats else None
     tl = np.zeros((vdi.height, vdi.width), dtype=np.uint8) if touched else None
     ts = np.zeros((vdi.ns, vdi.height, vdi.width), dtype=np.uint8) if touched else None
-    lib.or_render_exact(ctypes.byref(b.c), _p(cam), width, height, n, _p(pix), _p(out), _p(st), _p(tl), _p(ts),
-                        nthreads)
+    lib.or_render_exact(ctypes.byref(b.c), _p(cam), width, height, float(aspect), n, _p(pix), _p(out), _p(st),
+                        _p(tl), _p(ts), nthreads)
     if pix is None:
         out = out.reshape(height, width, 4)
         if st is not None:
@@ -145,9 +145,10 @@ def lowres_size(width: int, height: int, d_i: float):
 
 
 def render_preview(vdi, camera, w: int, h: int, d_r: float, pixels=None, grid: Optional[np.ndarray] = None,
-                   rgba: Optional[np.ndarray] = None, nthreads: int = 0, samples: bool = False):
-    """Along-ray subsampled render of a w x h image (D_R > 0).  Returns
-    (out [h, w, 4], flags [h, w] u8) or per-pixel arrays for a pixel list."""
+                   rgba: Optional[np.ndarray] = None, nthreads: int = 0, samples: bool = False, aspect: float = 0.0):
+    """Along-ray subsampled render of a w x h image (D_R > 0); aspect 0
+    means w/h.  Returns (out [h, w, 4], flags [h, w] u8) or per-pixel arrays
+    for a pixel list."""
     lib = _load()
     if grid is None:
         grid = count_grid(vdi)
@@ -158,8 +159,8 @@ def render_preview(vdi, camera, w: int, h: int, d_r: float, pixels=None, grid: O
     out = np.zeros((n, 4), dtype=np.float64)
     flags = np.zeros(n, dtype=np.uint8)
     ns = np.zeros(n, dtype=np.int64)
-    rc = lib.or_render_preview(ctypes.byref(b.c), _p(cam), w, h, float(d_r), n, _p(pix), _p(out), _p(flags), _p(ns),
-                               nthreads)
+    rc = lib.or_render_preview(ctypes.byref(b.c), _p(cam), w, h, float(aspect), float(d_r), n, _p(pix), _p(out),
+                               _p(flags), _p(ns), nthreads)
     if rc != 0:
         raise ValueError("render_preview needs D_R > 0")
     if pix is None:
@@ -181,13 +182,15 @@ def upsample(lo: np.ndarray, width: int, height: int, lo_flags: Optional[np.ndar
 def render(vdi, camera, width: int, height: int, d_i: float = 1.0, d_r: float = 0.0,
            rgba: Optional[np.ndarray] = None, nthreads: int = 0):
     """The full render: exact (D_R = 0) or along-ray subsampled (D_R > 0) at
-    round(W/D_I) x round(H/D_I), then bilinear upsampling to W x H when D_I > 1.
+    round(W/D_I) x round(H/D_I) with the display's aspect W/H, then bilinear
+    upsampling to W x H when D_I > 1 (Section 4.4).
     Returns (out [H, W, 4] float64, flags [H, W] uint8)."""
     w, h = lowres_size(width, height, d_i)
+    aspect = width / height
     if d_r > 0.0:
-        lo, fl = render_preview(vdi, camera, w, h, d_r, rgba=rgba, nthreads=nthreads)
+        lo, fl = render_preview(vdi, camera, w, h, d_r, rgba=rgba, nthreads=nthreads, aspect=aspect)
     else:
-        lo = render_exact(vdi, camera, w, h, rgba=rgba, nthreads=nthreads)
+        lo = render_exact(vdi, camera, w, h, rgba=rgba, nthreads=nthreads, aspect=aspect)
         fl = np.zeros((h, w), dtype=np.uint8)
     if (w, h) == (width, height):
         return lo, fl

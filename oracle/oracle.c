@@ -85,7 +85,8 @@ static void cross3(const double *a, const double *b, double *o)
     o[2] = a[0] * b[1] - a[1] * b[0];
 }
 
-static void ocam_init(ocam_t *c, const float *cam, int W, int H)
+/* aspect <= 0: W / H. */
+static void ocam_init(ocam_t *c, const float *cam, int W, int H, double aspect)
 {
     double up[3];
     for (int a = 0; a < 3; ++a) {
@@ -98,7 +99,7 @@ static void ocam_init(ocam_t *c, const float *cam, int W, int H)
     unit3(c->R);
     cross3(c->R, c->F, c->U);
     c->th = tan((double)cam[9] * M_PI / 360.0);
-    c->aspect = (double)W / (double)H;
+    c->aspect = aspect > 0.0 ? aspect : (double)W / (double)H;
     c->near_ = cam[10];
     c->W = W;
     c->H = H;
@@ -311,16 +312,18 @@ static void exact_pixel(const or_vdi_t *v, const ocam_t *cO, const ocam_t *cN, d
 static int max_breaks(const or_vdi_t *v) { return v->W + v->H + v->grid_nz + 8; }
 
 /*
- * Exact render.  If pix is NULL, renders all W*H pixels of V_N (row-major,
+ * Exact render.  aspect <= 0 means W/H (a downsampled render passes the
+ * display's).  If pix is NULL, renders all W*H pixels of V_N (row-major,
  * row 0 = bottom) into out[H*W*4]; else renders the npix pixel indices
  * (py*W + px) into out[npix*4].  stats (optional) [npix or W*H][2] = lists, pieces.
  */
-int or_render_exact(const or_vdi_t *v, const float *camN, int W, int H, int64_t npix, const int64_t *pix,
-                    double *out, int64_t *stats, uint8_t *touched_lists, uint8_t *touched_S, int nthreads)
+int or_render_exact(const or_vdi_t *v, const float *camN, int W, int H, double aspect, int64_t npix,
+                    const int64_t *pix, double *out, int64_t *stats, uint8_t *touched_lists, uint8_t *touched_S,
+                    int nthreads)
 {
     ocam_t cO, cN;
-    ocam_init(&cO, v->cam, v->W, v->H);
-    ocam_init(&cN, camN, W, H);
+    ocam_init(&cO, v->cam, v->W, v->H, 0.0);
+    ocam_init(&cN, camN, W, H, aspect);
     if (!pix) npix = (int64_t)W * H;
     int nb = max_breaks(v);
     int maxp = nb * (v->NS + 1);
@@ -421,16 +424,16 @@ done:
 
 /*
  * Along-ray subsampled render (D_R > 0) of a w x h image with V_N's camera
- * (aspect w/h).  pix / npix as in or_render_exact.  flags[npix] receive the
+ * (aspect <= 0: w/h; a downsampled render passes the display's W/H).  pix / npix as in or_render_exact.  flags[npix] receive the
  * tie flags; nsamp[npix] (optional) the number of point samples taken.
  */
-int or_render_preview(const or_vdi_t *v, const float *camN, int w, int h, double DR, int64_t npix, const int64_t *pix,
-                      double *out, uint8_t *flags, int64_t *nsamp, int nthreads)
+int or_render_preview(const or_vdi_t *v, const float *camN, int w, int h, double aspect, double DR, int64_t npix,
+                      const int64_t *pix, double *out, uint8_t *flags, int64_t *nsamp, int nthreads)
 {
     if (!(DR > 0.0) || !v->grid) return -1;
     ocam_t cO, cN;
-    ocam_init(&cO, v->cam, v->W, v->H);
-    ocam_init(&cN, camN, w, h);
+    ocam_init(&cO, v->cam, v->W, v->H, 0.0);
+    ocam_init(&cN, camN, w, h, aspect);
     if (!pix) npix = (int64_t)w * h;
     int nb = max_breaks(v);
 #ifdef _OPENMP
@@ -505,8 +508,8 @@ int or_march(const or_vdi_t *v, const float *camN, int W, int H, int64_t npix, c
              double *out, int nthreads)
 {
     ocam_t cO, cN;
-    ocam_init(&cO, v->cam, v->W, v->H);
-    ocam_init(&cN, camN, W, H);
+    ocam_init(&cO, v->cam, v->W, v->H, 0.0);
+    ocam_init(&cN, camN, W, H, 0.0);
     const size_t plane = (size_t)v->W * v->H;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
