@@ -134,7 +134,7 @@ int vdi_create(const vdi_desc *desc, vdi_t *out);
  *                  round(width/D_I) x round(height/D_I) grid with the same
  *                  camera and bilinearly upsampled (Section 4.4; the paper's
  *                  fraction D_I = 0.5 is factor 2 here).
- *   D_R >= 0       0: exact mode.  > 0: along-ray subsampling (Section 4.4):
+ *   D_R            0: exact mode.  >= 1e-4: along-ray subsampling (Section 4.4):
  *                  in each non-empty grid cell a ray takes
  *                  ceil(((length in cell)/(slice depth)) (count/k^2) / D_R)
  *                  point samples at regular spacing (the paper's thinning
@@ -147,7 +147,8 @@ int vdi_create(const vdi_desc *desc, vdi_t *out);
  * renders of one VDI on several streams may overlap.  The result is
  * deterministic: the same call gives the same bits.
  * Errors: VDI_ERR_ARG (null, width/height < 1 or > 16384, D_I < 1, D_R < 0,
- * non-finite values, fov out of range), VDI_ERR_OOM (preview scratch), VDI_ERR_HIP.
+ * 0 < D_R < 1e-4, non-finite values, fov out of range), VDI_ERR_OOM (preview
+ * scratch), VDI_ERR_HIP.
  */
 int vdi_render(vdi_t v, const vdi_camera *cam_VN, int32_t width, int32_t height, float D_I, float D_R,
                float *out_rgba, void *hip_stream);

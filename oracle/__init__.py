@@ -234,3 +234,40 @@ def b_alg(vdi, touched_lists: np.ndarray, touched_s: np.ndarray, out_pixels: int
     n = vdi.count.astype(np.int64)
     lists = touched_lists.astype(bool)
     return int(lists.sum() + 8 * n[lists].sum() + colour_bytes * int(touched_s.astype(bool).sum()) + 16 * out_pixels)
+
+
+def render_points(vdi, camera, width: int, height: int, d_i: float, d_r: float, pixels,
+                  rgba: Optional[np.ndarray] = None, nthreads: int = 0):
+    """Selected output pixels (row-major indices) of `render`: the low-res
+    texels each one's bilinear filter reads are rendered one by one and
+    combined with the same weights as `upsample`.  Returns (values [n, 4],
+    flags [n])."""
+    pixels = np.asarray(pixels, dtype=np.int64)
+    w, h = lowres_size(width, height, d_i)
+    aspect = width / height
+
+    def lo_render(pix):
+        if d_r > 0.0:
+            return render_preview(vdi, camera, w, h, d_r, pixels=pix, rgba=rgba, nthreads=nthreads, aspect=aspect)
+        return render_exact(vdi, camera, w, h, pixels=pix, rgba=rgba, nthreads=nthreads, aspect=aspect), \
+            np.zeros(len(pix), np.uint8)
+
+    if (w, h) == (width, height):
+        return lo_render(pixels)
+    x, y = pixels % width, pixels // width
+    sx = np.clip((x + 0.5) * w / width - 0.5, 0.0, w - 1)
+    sy = np.clip((y + 0.5) * h / height - 0.5, 0.0, h - 1)
+    x0, y0 = np.floor(sx).astype(np.int64), np.floor(sy).astype(np.int64)
+    x1, y1 = np.minimum(x0 + 1, w - 1), np.minimum(y0 + 1, h - 1)
+    fx, fy = sx - x0, sy - y0
+    taps = [y0 * w + x0, y0 * w + x1, y1 * w + x0, y1 * w + x1]
+    need, inv = np.unique(np.concatenate(taps), return_inverse=True)
+    vals, fl = lo_render(need)
+    n = len(pixels)
+    a, b, c, d = (vals[inv[k * n:(k + 1) * n]] for k in range(4))
+    out = (a * (1 - fx)[:, None] + b * fx[:, None]) * (1 - fy)[:, None] + \
+          (c * (1 - fx)[:, None] + d * fx[:, None]) * fy[:, None]
+    flags = np.zeros(n, np.uint8)
+    for k in range(4):
+        flags |= fl[inv[k * n:(k + 1) * n]]
+    return out, flags

@@ -1,0 +1,453 @@
+// Host side of the libvdi C ABI (include/vdi.h): argument checking, device
+// residency of VDIs, per-frame set-up in double precision, kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "vdi_internal.h"
+
+struct vdi_s {
+    vdi::DevVDI dev;
+    vdi_camera cam_o;
+    float bmin[3], bmax[3];
+    int device;
+    uint8_t *d_count = nullptr;
+    float2 *d_depth = nullptr;
+    void *d_rgba = nullptr;
+    uint32_t *d_grid = nullptr;
+    float *d_gz = nullptr;
+    uint64_t device_bytes = 0, supersegments = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(e == hipErrorOutOfMemory ? VDI_ERR_OOM : VDI_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_OR_FAIL(expr, what)                   \
+    do {                                          \
+        hipError_t e_ = (expr);                   \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+bool finite3(const float *v) { return isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]); }
+
+struct Basis {
+    double eye[3], F[3], R[3], U[3], th;
+};
+
+void cross(const double *a, const double *b, double *o)
+{
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+double norm(const double *v) { return sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); }
+
+// Camera basis F = normalize(target - eye), R = normalize(F x up), U = R x F.
+int make_basis(const vdi_camera &c, Basis &b)
+{
+    if (!finite3(c.eye) || !finite3(c.target) || !finite3(c.up) || !isfinite(c.fov_y_deg) || !isfinite(c.near_plane))
+        return fail(VDI_ERR_ARG, "camera has a non-finite value");
+    if (!(c.fov_y_deg > 0.0f && c.fov_y_deg < 180.0f)) return fail(VDI_ERR_ARG, "fov_y_deg must be in (0, 180)");
+    if (!(c.near_plane > 0.0f)) return fail(VDI_ERR_ARG, "near_plane must be > 0");
+    double up[3];
+    for (int a = 0; a < 3; ++a) {
+        b.eye[a] = c.eye[a];
+        b.F[a] = (double)c.target[a] - (double)c.eye[a];
+        up[a] = c.up[a];
+    }
+    double n = norm(b.F);
+    if (!(n > 0.0)) return fail(VDI_ERR_ARG, "camera target equals eye");
+    for (double &x : b.F) x /= n;
+    cross(b.F, up, b.R);
+    n = norm(b.R);
+    if (!(n > 1e-12)) return fail(VDI_ERR_ARG, "camera up is parallel to the view direction");
+    for (double &x : b.R) x /= n;
+    cross(b.R, b.F, b.U);
+    b.th = tan((double)c.fov_y_deg * M_PI / 360.0);
+    return VDI_OK;
+}
+
+double dot(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+// Frame constants for rays on a w x h grid with aspect `aspect`.
+int make_frame(const vdi_s *v, const vdi_camera &cam, int w, int h, double aspect, vdi::Frame &f)
+{
+    Basis o, n;
+    int rc = make_basis(v->cam_o, o);
+    if (rc) return rc;
+    rc = make_basis(cam, n);
+    if (rc) return rc;
+    memset(&f, 0, sizeof f);
+    const double aspect_o = (double)v->dev.WO / (double)v->dev.HO;
+    for (int a = 0; a < 3; ++a) {
+        f.FO[a] = o.F[a];
+        f.RO[a] = o.R[a];
+        f.UO[a] = o.U[a];
+        f.eyeN[a] = n.eye[a];
+        f.FN[a] = n.F[a];
+        f.RN[a] = n.R[a];
+        f.UN[a] = n.U[a];
+        f.bmin[a] = v->bmin[a];
+        f.bmax[a] = v->bmax[a];
+    }
+    f.sx_o = 1.0 / (o.th * aspect_o);
+    f.sy_o = 1.0 / o.th;
+    f.near_o = v->cam_o.near_plane;
+    double rel[3];
+    for (int a = 0; a < 3; ++a) rel[a] = n.eye[a] - o.eye[a];
+    f.X0 = dot(o.R, rel) * f.sx_o;
+    f.Y0 = dot(o.U, rel) * f.sy_o;
+    f.Z0 = dot(o.F, rel);
+    f.tx_n = n.th * aspect;
+    f.ty_n = n.th;
+    f.near_n = cam.near_plane;
+    f.W = w;
+    f.H = h;
+    f.ess = 1;
+    f.search = VDI_SEARCH_SEEDED;
+    return VDI_OK;
+}
+
+int check_opts(const vdi_render_opts *opts, vdi::Frame &f)
+{
+    if (!opts) return VDI_OK;
+    if (opts->ess != 0 && opts->ess != 1) return fail(VDI_ERR_ARG, "opts.ess must be 0 or 1");
+    if (opts->search < VDI_SEARCH_SEEDED || opts->search > VDI_SEARCH_LINEAR)
+        return fail(VDI_ERR_ARG, "opts.search must be a VDI_SEARCH_* value");
+    f.ess = opts->ess;
+    f.search = opts->search;
+    return VDI_OK;
+}
+
+int lowres(int32_t W, int32_t H, float D_I, int32_t *w, int32_t *h)
+{
+    *w = std::max(1, (int32_t)floor((double)W / (double)D_I + 0.5));
+    *h = std::max(1, (int32_t)floor((double)H / (double)D_I + 0.5));
+    return VDI_OK;
+}
+
+int check_render_args(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, float D_I, float D_R, const float *out)
+{
+    if (!v) return fail(VDI_ERR_ARG, "null VDI handle");
+    if (!cam) return fail(VDI_ERR_ARG, "null camera");
+    if (!out) return fail(VDI_ERR_ARG, "null output pointer");
+    if (W < 1 || H < 1 || W > 16384 || H > 16384) return fail(VDI_ERR_ARG, "image size %dx%d out of range", W, H);
+    if (!isfinite(D_I) || D_I < 1.0f) return fail(VDI_ERR_ARG, "D_I must be a finite value >= 1");
+    if (!isfinite(D_R) || D_R < 0.0f || (D_R > 0.0f && D_R < 1e-4f))
+        return fail(VDI_ERR_ARG, "D_R must be 0 or a finite value >= 1e-4");
+    return VDI_OK;
+}
+
+// Renders into `out` (W x H); uses stream-ordered scratch for D_I > 1.
+int render_impl(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, float D_I, float D_R,
+                const vdi_render_opts *opts, float *out, hipStream_t s)
+{
+    int rc = check_render_args(v, cam, W, H, D_I, D_R, out);
+    if (rc) return rc;
+    int32_t w, h;
+    lowres(W, H, D_I, &w, &h);
+    vdi::Frame f;
+    rc = make_frame(v, *cam, w, h, (double)W / (double)H, f);
+    if (rc) return rc;
+    rc = check_opts(opts, f);
+    if (rc) return rc;
+    HIP_OR_FAIL(hipSetDevice(v->device), "hipSetDevice");
+    const bool down = (w != W || h != H);
+    float4 *lo = nullptr;
+    if (down) HIP_OR_FAIL(hipMallocAsync((void **)&lo, (size_t)w * h * sizeof(float4), s), "preview scratch");
+    f.out = down ? lo : reinterpret_cast<float4 *>(out);
+    f.DR = D_R;
+    hipError_t e = D_R > 0.0f ? vdi::launch_render_preview(v->dev, f, s) : vdi::launch_render_exact(v->dev, f, false, s);
+    if (e == hipSuccess && down) e = vdi::launch_upsample(lo, w, h, reinterpret_cast<float4 *>(out), W, H, s);
+    if (down) {
+        hipError_t e2 = hipFreeAsync(lo, s);
+        if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return hip_fail(e, "render launch");
+    return VDI_OK;
+}
+
+// Host-side validation of every list (optional at create).
+int validate_lists(const vdi_desc *d)
+{
+    const uint64_t plane = (uint64_t)d->width * d->height;
+    for (uint64_t li = 0; li < plane; ++li) {
+        const int n = d->count[li];
+        if (n > d->max_supersegments) return fail(VDI_ERR_ARG, "list %llu: count %d > N_S", (unsigned long long)li, n);
+        float prev_b = -INFINITY;
+        for (int j = 0; j < n; ++j) {
+            const uint64_t o = (uint64_t)j * plane + li;
+            const float f = d->depth[2 * o], b = d->depth[2 * o + 1];
+            if (!isfinite(f) || !isfinite(b) || !(f < b))
+                return fail(VDI_ERR_ARG, "list %llu slot %d: need finite f < b", (unsigned long long)li, j);
+            if (f < prev_b)
+                return fail(VDI_ERR_ARG, "list %llu slot %d: supersegments unsorted or overlapping",
+                            (unsigned long long)li, j);
+            prev_b = b;
+            if (d->rgba_fmt_in == VDI_F32) {
+                const float *c = static_cast<const float *>(d->rgba) + 4 * o;
+                if (!isfinite(c[0]) || !isfinite(c[1]) || !isfinite(c[2]) || !(c[3] >= 0.0f && c[3] <= 1.0f))
+                    return fail(VDI_ERR_ARG, "list %llu slot %d: colour not finite or opacity outside [0, 1]",
+                                (unsigned long long)li, j);
+            }
+        }
+    }
+    return VDI_OK;
+}
+
+void free_vdi(vdi_s *v)
+{
+    if (!v) return;
+    hipFree(v->d_count);
+    hipFree(v->d_depth);
+    hipFree(v->d_rgba);
+    hipFree(v->d_grid);
+    hipFree(v->d_gz);
+    delete v;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *vdi_last_error(void) { return g_err.c_str(); }
+
+uint64_t vdi_plane_bytes(int32_t width, int32_t height, int32_t n_s, int32_t fmt)
+{
+    if (width < 1 || height < 1 || n_s < 1) return 0;
+    const uint64_t plane = (uint64_t)width * height;
+    const uint64_t colour = fmt == VDI_F32 ? 16 : 8;
+    return plane + plane * (uint64_t)n_s * (8 + colour);
+}
+
+int vdi_lowres_size(int32_t width, int32_t height, float D_I, int32_t *w, int32_t *h)
+{
+    if (!w || !h) return fail(VDI_ERR_ARG, "null output");
+    if (width < 1 || height < 1 || !isfinite(D_I) || D_I < 1.0f) return fail(VDI_ERR_ARG, "invalid size or D_I");
+    return lowres(width, height, D_I, w, h);
+}
+
+int vdi_create(const vdi_desc *d, vdi_t *out)
+{
+    g_err.clear();
+    if (!d || !out) return fail(VDI_ERR_ARG, "null argument");
+    if (d->width < 1 || d->height < 1 || d->width > 32768 || d->height > 32768)
+        return fail(VDI_ERR_ARG, "VDI size %dx%d out of range", d->width, d->height);
+    if (d->max_supersegments < 1 || d->max_supersegments > VDI_MAX_SUPERSEGMENTS)
+        return fail(VDI_ERR_ARG, "max_supersegments must be in [1, 255]");
+    if (!d->count || !d->depth || !d->rgba) return fail(VDI_ERR_ARG, "null VDI plane");
+    if (d->rgba_fmt_in < VDI_F32 || d->rgba_fmt_in > VDI_BF16 || d->rgba_fmt_store < VDI_F32 ||
+        d->rgba_fmt_store > VDI_BF16)
+        return fail(VDI_ERR_ARG, "unknown colour format");
+    if (d->rgba_fmt_in != VDI_F32 && d->rgba_fmt_in != d->rgba_fmt_store)
+        return fail(VDI_ERR_ARG, "16-bit colour input must be stored in the same format");
+    if (d->grid_k < 1 || d->grid_k > VDI_MAX_GRID_K || d->grid_nz < 1 || d->grid_nz > VDI_MAX_GRID_NZ)
+        return fail(VDI_ERR_ARG, "grid shape out of range (k 1..16, nz 1..64)");
+    if (!finite3(d->aabb_min) || !finite3(d->aabb_max)) return fail(VDI_ERR_ARG, "non-finite AABB");
+    for (int a = 0; a < 3; ++a)
+        if (!(d->aabb_max[a] > d->aabb_min[a])) return fail(VDI_ERR_ARG, "empty AABB");
+    Basis ob;
+    int rc = make_basis(d->camera_VO, ob);
+    if (rc) return rc;
+
+    const uint64_t plane = (uint64_t)d->width * d->height;
+    for (uint64_t li = 0; li < plane; ++li)
+        if (d->count[li] > d->max_supersegments) return fail(VDI_ERR_ARG, "a list count exceeds max_supersegments");
+    if (d->validate) {
+        rc = validate_lists(d);
+        if (rc) return rc;
+    }
+    // Grid slice boundaries.
+    std::vector<float> gz(d->grid_nz + 1);
+    if (d->grid_z) {
+        for (int c = 0; c <= d->grid_nz; ++c) {
+            gz[c] = d->grid_z[c];
+            if (!isfinite(gz[c]) || (c > 0 && !(gz[c] > gz[c - 1])))
+                return fail(VDI_ERR_ARG, "grid_z must be finite and strictly increasing");
+        }
+    } else {
+        double lo = INFINITY, hi = -INFINITY;
+        for (int m = 0; m < 8; ++m) {
+            double p[3] = {(m & 1) ? d->aabb_max[0] : d->aabb_min[0], (m & 2) ? d->aabb_max[1] : d->aabb_min[1],
+                           (m & 4) ? d->aabb_max[2] : d->aabb_min[2]};
+            double rel[3] = {p[0] - ob.eye[0], p[1] - ob.eye[1], p[2] - ob.eye[2]};
+            const double z = dot(ob.F, rel);
+            lo = std::min(lo, z);
+            hi = std::max(hi, z);
+        }
+        lo -= 1e-3;
+        hi += 1e-3;
+        for (int c = 0; c <= d->grid_nz; ++c) gz[c] = (float)(lo + (hi - lo) * c / d->grid_nz);
+    }
+
+    vdi_s *v = new (std::nothrow) vdi_s();
+    if (!v) return fail(VDI_ERR_OOM, "host allocation");
+    hipGetDevice(&v->device);
+    v->cam_o = d->camera_VO;
+    memcpy(v->bmin, d->aabb_min, sizeof v->bmin);
+    memcpy(v->bmax, d->aabb_max, sizeof v->bmax);
+    vdi::DevVDI &D = v->dev;
+    D.WO = d->width;
+    D.HO = d->height;
+    D.NS = d->max_supersegments;
+    D.fmt = d->rgba_fmt_store;
+    D.plane = plane;
+    D.gk = d->grid_k;
+    D.gnz = d->grid_nz;
+    D.GW = (d->width + d->grid_k - 1) / d->grid_k;
+    D.GH = (d->height + d->grid_k - 1) / d->grid_k;
+    D.tx_o = (float)(ob.th * ((double)d->width / d->height));
+    D.ty_o = (float)ob.th;
+
+    const uint64_t ns = (uint64_t)d->max_supersegments;
+    const size_t colour = d->rgba_fmt_store == VDI_F32 ? 16 : 8;
+    const size_t grid_bytes = (size_t)D.gnz * D.GH * D.GW * sizeof(uint32_t);
+    hipError_t e;
+    auto bail = [&](hipError_t err, const char *what) {
+        int code = hip_fail(err, what);
+        free_vdi(v);
+        return code;
+    };
+    if ((e = hipMalloc((void **)&v->d_count, plane)) != hipSuccess) return bail(e, "hipMalloc count");
+    if ((e = hipMalloc((void **)&v->d_depth, plane * ns * sizeof(float2))) != hipSuccess) return bail(e, "hipMalloc depth");
+    if ((e = hipMalloc(&v->d_rgba, plane * ns * colour)) != hipSuccess) return bail(e, "hipMalloc rgba");
+    if ((e = hipMalloc((void **)&v->d_grid, grid_bytes)) != hipSuccess) return bail(e, "hipMalloc grid");
+    if ((e = hipMalloc((void **)&v->d_gz, gz.size() * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc grid_z");
+    if ((e = hipMemcpy(v->d_count, d->count, plane, hipMemcpyHostToDevice)) != hipSuccess) return bail(e, "upload count");
+    if ((e = hipMemcpy(v->d_depth, d->depth, plane * ns * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
+        return bail(e, "upload depth");
+    if ((e = hipMemcpy(v->d_gz, gz.data(), gz.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
+        return bail(e, "upload grid_z");
+    if (d->rgba_fmt_in == d->rgba_fmt_store) {
+        if ((e = hipMemcpy(v->d_rgba, d->rgba, plane * ns * colour, hipMemcpyHostToDevice)) != hipSuccess)
+            return bail(e, "upload rgba");
+    } else {
+        // float32 -> 16-bit on the device, through a bounded staging buffer.
+        const uint64_t total = plane * ns, chunk = std::min<uint64_t>(total, 16ull << 20);
+        float4 *stage = nullptr;
+        if ((e = hipMalloc((void **)&stage, chunk * sizeof(float4))) != hipSuccess) return bail(e, "hipMalloc staging");
+        for (uint64_t off = 0; off < total && e == hipSuccess; off += chunk) {
+            const uint64_t n = std::min(chunk, total - off);
+            e = hipMemcpy(stage, static_cast<const float4 *>(d->rgba) + off, n * sizeof(float4), hipMemcpyHostToDevice);
+            if (e == hipSuccess)
+                e = vdi::launch_convert_rgba(stage, static_cast<uint2 *>(v->d_rgba) + off, n, d->rgba_fmt_store, 0);
+            if (e == hipSuccess) e = hipDeviceSynchronize();
+        }
+        hipFree(stage);
+        if (e != hipSuccess) return bail(e, "colour conversion");
+    }
+    D.count = v->d_count;
+    D.depth = v->d_depth;
+    D.rgba = v->d_rgba;
+    D.grid = v->d_grid;
+    D.gz = v->d_gz;
+    if ((e = vdi::launch_grid_build(D, v->d_grid, 0)) != hipSuccess) return bail(e, "grid build");
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return bail(e, "grid build");
+    uint64_t total = 0;
+    for (uint64_t li = 0; li < plane; ++li) total += d->count[li];
+    v->supersegments = total;
+    v->device_bytes = plane + plane * ns * (sizeof(float2) + colour) + grid_bytes + gz.size() * sizeof(float);
+    *out = v;
+    return VDI_OK;
+}
+
+int vdi_render(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, float D_I, float D_R, float *out, void *stream)
+{
+    g_err.clear();
+    return render_impl(v, cam, W, H, D_I, D_R, nullptr, out, static_cast<hipStream_t>(stream));
+}
+
+int vdi_render_ex(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, float D_I, float D_R,
+                  const vdi_render_opts *opts, float *out, void *stream)
+{
+    g_err.clear();
+    return render_impl(v, cam, W, H, D_I, D_R, opts, out, static_cast<hipStream_t>(stream));
+}
+
+int vdi_render_counters(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, const vdi_render_opts *opts,
+                        float *out, uint8_t *touched_lists, uint8_t *touched_slots, int32_t *ray_stats, void *stream)
+{
+    g_err.clear();
+    int rc = check_render_args(v, cam, W, H, 1.0f, 0.0f, out);
+    if (rc) return rc;
+    if (!touched_lists || !touched_slots) return fail(VDI_ERR_ARG, "null counter buffer");
+    vdi::Frame f;
+    rc = make_frame(v, *cam, W, H, (double)W / (double)H, f);
+    if (rc) return rc;
+    rc = check_opts(opts, f);
+    if (rc) return rc;
+    HIP_OR_FAIL(hipSetDevice(v->device), "hipSetDevice");
+    f.out = reinterpret_cast<float4 *>(out);
+    f.touched_lists = touched_lists;
+    f.touched_slots = touched_slots;
+    f.ray_stats = ray_stats;
+    HIP_OR_FAIL(vdi::launch_render_exact(v->dev, f, true, static_cast<hipStream_t>(stream)), "counter render launch");
+    return VDI_OK;
+}
+
+int vdi_get_grid(vdi_t v, uint32_t *host_out, size_t capacity)
+{
+    g_err.clear();
+    if (!v || !host_out) return fail(VDI_ERR_ARG, "null argument");
+    const size_t n = (size_t)v->dev.gnz * v->dev.GH * v->dev.GW;
+    if (capacity < n) return fail(VDI_ERR_ARG, "grid needs %zu elements", n);
+    HIP_OR_FAIL(hipSetDevice(v->device), "hipSetDevice");
+    HIP_OR_FAIL(hipMemcpy(host_out, v->d_grid, n * sizeof(uint32_t), hipMemcpyDeviceToHost), "grid download");
+    return VDI_OK;
+}
+
+int vdi_get_info(vdi_t v, vdi_info_t *info)
+{
+    g_err.clear();
+    if (!v || !info) return fail(VDI_ERR_ARG, "null argument");
+    info->width = v->dev.WO;
+    info->height = v->dev.HO;
+    info->max_supersegments = v->dev.NS;
+    info->rgba_fmt = v->dev.fmt;
+    info->grid_k = v->dev.gk;
+    info->grid_nz = v->dev.gnz;
+    info->grid_w = v->dev.GW;
+    info->grid_h = v->dev.GH;
+    info->device_bytes = v->device_bytes;
+    info->supersegments = v->supersegments;
+    return VDI_OK;
+}
+
+int vdi_destroy(vdi_t v)
+{
+    g_err.clear();
+    if (!v) return VDI_OK;
+    hipSetDevice(v->device);
+    hipError_t e = hipDeviceSynchronize();
+    free_vdi(v);
+    if (e != hipSuccess) return hip_fail(e, "synchronize before destroy");
+    return VDI_OK;
+}
+
+}  // extern "C"

@@ -25,7 +25,7 @@ struct DevVDI {
     const void *rgba;          // [NS][HO][WO] float4 or 4 x 16-bit
     const uint32_t *grid;      // [gnz][GH][GW]
     int32_t gk, gnz, GW, GH;
-    float gz[VDI_MAX_GRID_NZ + 1];
+    const float *gz;           // [gnz + 1] slice boundaries (device)
     float tx_o, ty_o;          // tan(fov/2) * aspect, tan(fov/2) of V_O
 };
 

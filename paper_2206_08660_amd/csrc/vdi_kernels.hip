@@ -1,0 +1,689 @@
+// HIP kernels of libvdi for gfx950 (MI355X): raycasting a VDI from a new
+// viewpoint (Gupta et al., Section 4), its preview mode (Section 4.4), the
+// count grid (Section 4.3) and colour storage conversion.
+//
+// Execution model.  One lane per ray; a 256-lane workgroup covers a 64 x 4
+// pixel tile, so each wavefront is 64 horizontally adjacent rays.  Their
+// projected lines in V_O are near-parallel and offset by about one list, so
+// at any step the wavefront reads the same slot of neighbouring lists: with
+// slot-major planes those loads coalesce, and lists revisited by the
+// neighbouring rays are served from L1/L2 (the paper's spatial smoothness).
+// Tiles are assigned so that each of the 8 XCDs renders one contiguous band
+// of the image, keeping the VDI rows a band needs in that XCD's L2.
+//
+// Precision.  Ray set-up, list crossings and supersegment overlaps run in
+// FP64 (the crossing depth of a ray with a list edge is ill-conditioned near
+// the generating view: an FP32 error of 1e-7 in NDC moves it by ~1e-5 in
+// depth); opacity correction (Eq. 2) and compositing run in FP32.
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "vdi_internal.h"
+
+namespace vdi {
+namespace {
+
+constexpr int kTileW = 64;
+constexpr int kTileH = 4;
+constexpr int kBlock = kTileW * kTileH;
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+// Tile of this workgroup: blocks are dealt to XCDs round-robin, so give XCD x
+// the x-th contiguous range of tiles.
+__device__ __forceinline__ int xcd_tile(int bid, int nblocks)
+{
+    const int x = bid % kXcds, k = bid / kXcds;
+    const int q = nblocks / kXcds, r = nblocks % kXcds;
+    return x * q + min(x, r) + k;
+}
+
+// ---------------------------------------------------------------------------
+// Colour planes
+// ---------------------------------------------------------------------------
+template <int FMT>
+__device__ __forceinline__ float4 load_rgba(const void *base, uint64_t idx)
+{
+    if constexpr (FMT == VDI_F32) {
+        return reinterpret_cast<const float4 *>(base)[idx];
+    } else {
+        const uint2 u = reinterpret_cast<const uint2 *>(base)[idx];
+        if constexpr (FMT == VDI_F16) {
+            const __half2 rg = *reinterpret_cast<const __half2 *>(&u.x);
+            const __half2 ba = *reinterpret_cast<const __half2 *>(&u.y);
+            const float2 a = __half22float2(rg), b = __half22float2(ba);
+            return make_float4(a.x, a.y, b.x, b.y);
+        } else {
+            return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
+                               __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Rays
+// ---------------------------------------------------------------------------
+struct Ray {
+    double Xp, Yp, Zp;  // d/dt of (X, Y, Z) in V_O's frame; Z is V_O view depth
+    double t0, t1;      // clipped parameter range (world distance from eye_N)
+};
+
+// Keep t with a + b t >= 0.
+__device__ __forceinline__ bool clip(double a, double b, double &lo, double &hi)
+{
+    if (b == 0.0) return a >= 0.0;
+    const double t = -a / b;
+    if (b > 0.0)
+        lo = fmax(lo, t);
+    else
+        hi = fmin(hi, t);
+    return true;
+}
+
+// Ray through NDC (xc, yc) of V_N, clipped to V_N's near plane, the AABB and
+// V_O's frustum (Section 4.1: marching starts and ends where the ray meets
+// the generating viewport and the volume's bounding box).
+__device__ bool ray_setup(const Frame &F, double xc, double yc, Ray &r)
+{
+    double d[3];
+    for (int a = 0; a < 3; ++a) d[a] = F.FN[a] + xc * F.tx_n * F.RN[a] + yc * F.ty_n * F.UN[a];
+    const double inv = 1.0 / sqrt(dot3(d, d));
+    for (int a = 0; a < 3; ++a) d[a] *= inv;
+    r.Xp = dot3(F.RO, d) * F.sx_o;
+    r.Yp = dot3(F.UO, d) * F.sy_o;
+    r.Zp = dot3(F.FO, d);
+    double lo = 0.0, hi = __builtin_huge_val();
+    bool ok = clip(-F.near_n, dot3(F.FN, d), lo, hi);
+    for (int a = 0; a < 3; ++a) {
+        ok = ok && clip(F.eyeN[a] - F.bmin[a], d[a], lo, hi);
+        ok = ok && clip(F.bmax[a] - F.eyeN[a], -d[a], lo, hi);
+    }
+    ok = ok && clip(F.Z0 - F.near_o, r.Zp, lo, hi);
+    ok = ok && clip(F.Z0 - F.X0, r.Zp - r.Xp, lo, hi);
+    ok = ok && clip(F.Z0 + F.X0, r.Zp + r.Xp, lo, hi);
+    ok = ok && clip(F.Z0 - F.Y0, r.Zp - r.Yp, lo, hi);
+    ok = ok && clip(F.Z0 + F.Y0, r.Zp + r.Yp, lo, hi);
+    r.t0 = lo;
+    r.t1 = hi;
+    return ok && hi > lo;
+}
+
+// Parameter where the ray meets NDC line coord = -1 + 2 m / n (P = X or Y).
+__device__ __forceinline__ double line_t(int m, int n, double P0, double Pp, double Z0, double Zp)
+{
+    const double c = -1.0 + 2.0 * m / n;
+    return (c * Z0 - P0) / (Pp - c * Zp);
+}
+
+// Cell index of an NDC coordinate; a point exactly on a line belongs to the
+// cell the ray is moving into.
+__device__ __forceinline__ int cell_of(double ndc, int n, int dir)
+{
+    const double f = (ndc + 1.0) * n / 2.0;
+    const double fl = floor(f);
+    int i = (int)fl;
+    if (f == fl && dir < 0) i -= 1;
+    return min(max(i, 0), n - 1);
+}
+
+// cos of the angle between list (ix, iy)'s generating ray and V_O's axis.
+__device__ __forceinline__ float list_cos(const DevVDI &V, int ix, int iy)
+{
+    const float x = (-1.0f + (2.0f * ix + 1.0f) / V.WO) * V.tx_o;
+    const float y = (-1.0f + (2.0f * iy + 1.0f) / V.HO) * V.ty_o;
+    return rsqrtf(1.0f + x * x + y * y);
+}
+
+// Depth slice holding depth z for a ray moving towards larger (fwd) or smaller z.
+__device__ __forceinline__ int slice_of(const float *gz, int gnz, double z, bool fwd)
+{
+    int lo = 0, hi = gnz - 1;  // answer in [0, gnz-1]
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const double b = gz[mid];
+        if (fwd ? (b <= z) : (b < z))
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// First-supersegment search (Section 4.2, supplement Alg. S2)
+// ---------------------------------------------------------------------------
+// Smallest j in [0, n) with b_j > z (n if none).  Back depths increase with j
+// because supersegments are sorted and disjoint.
+template <int SEARCH>
+__device__ __forceinline__ int first_back_above(const float2 *__restrict__ dep, uint64_t plane, uint64_t li, int n,
+                                                double z, int p)
+{
+    if constexpr (SEARCH == VDI_SEARCH_LINEAR) {
+        int j = 0;
+        while (j < n && (double)dep[(uint64_t)j * plane + li].y <= z) ++j;
+        return j;
+    }
+    int lo = 0, hi = n;
+    if constexpr (SEARCH == VDI_SEARCH_SEEDED) {
+        if (p >= 0 && p < n) {
+            // Both candidate back depths are fetched before either is compared.
+            const float b1 = dep[(uint64_t)p * plane + li].y;
+            const float b0 = p > 0 ? dep[(uint64_t)(p - 1) * plane + li].y : -__builtin_huge_valf();
+            if ((double)b0 > z)
+                hi = p - 1;  // the answer is at most p-1
+            else if ((double)b1 > z)
+                return p;    // the seed itself
+            else
+                lo = p + 1;
+        }
+    }
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((double)dep[(uint64_t)mid * plane + li].y > z)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
+// Largest j in [0, n) with f_j < z (-1 if none): the first supersegment met by
+// a ray travelling towards smaller depth.
+template <int SEARCH>
+__device__ __forceinline__ int last_front_below(const float2 *__restrict__ dep, uint64_t plane, uint64_t li, int n,
+                                                double z, int p)
+{
+    if constexpr (SEARCH == VDI_SEARCH_LINEAR) {
+        int j = n - 1;
+        while (j >= 0 && (double)dep[(uint64_t)j * plane + li].x >= z) --j;
+        return j;
+    }
+    int lo = 0, hi = n;  // search the first j with f_j >= z
+    if constexpr (SEARCH == VDI_SEARCH_SEEDED) {
+        if (p >= 0 && p < n) {
+            const float f1 = dep[(uint64_t)p * plane + li].x;
+            const float f2 = p + 1 < n ? dep[(uint64_t)(p + 1) * plane + li].x : __builtin_huge_valf();
+            if ((double)f1 >= z)
+                hi = p;
+            else if ((double)f2 >= z)
+                return p;
+            else
+                lo = p + 2;
+        }
+    }
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((double)dep[(uint64_t)mid * plane + li].x >= z)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo - 1;
+}
+
+// ---------------------------------------------------------------------------
+// Compositing
+// ---------------------------------------------------------------------------
+struct Accum {
+    float r, g, b, T;
+};
+
+// Eq. 2 with exponent l = (world length in S) / (world length of the
+// generating ray in S), then front-to-back "over".
+__device__ __forceinline__ void composite(Accum &A, float4 c, float l)
+{
+    const float at = c.w >= 1.0f ? 1.0f : 1.0f - exp2f(l * log2f(1.0f - c.w));
+    const float w = A.T * at;
+    A.r = fmaf(w, c.x, A.r);
+    A.g = fmaf(w, c.y, A.g);
+    A.b = fmaf(w, c.z, A.b);
+    A.T *= 1.0f - at;
+}
+
+struct Counters {
+    int32_t lists, pieces;
+};
+
+// Composite the part of list li between depths za (entry) and zb (exit) of
+// a ray with dz/dt = Zp.  p is the seed index, updated on return.  Returns
+// true once the ray has terminated.
+template <int FMT, int SEARCH, bool COUNT>
+__device__ bool do_list(const DevVDI &V, const Frame &F, int ix, int iy, double ta, double tb, double Z0, double Zp,
+                        Accum &A, int &p, Counters &cnt)
+{
+    const uint64_t li = (uint64_t)iy * V.WO + ix;
+    if constexpr (COUNT) {
+        F.touched_lists[li] = 1;
+        ++cnt.lists;
+    }
+    const int n = V.count[li];
+    if (n == 0) return false;
+    const double za = Z0 + ta * Zp, zb = Z0 + tb * Zp;
+    const float cth = list_cos(V, ix, iy);
+    const float2 *__restrict__ dep = V.depth;
+    const uint64_t plane = V.plane;
+    if (Zp > kFlatZ) {
+        const double inv = 1.0 / Zp;
+        int j = first_back_above<SEARCH>(dep, plane, li, n, za, p);
+        int last = -1;
+        for (; j < n; ++j) {
+            const float2 fb = dep[(uint64_t)j * plane + li];
+            const double f = fb.x, b = fb.y;
+            if (f >= zb) break;
+            const double zl = fmax(za, f), zh = fmin(zb, b);
+            if (zh > zl) {
+                const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * plane + li);
+                composite(A, c, (float)((zh - zl) * inv) * cth / (fb.y - fb.x));
+                last = j;
+                if constexpr (COUNT) {
+                    F.touched_slots[(uint64_t)j * plane + li] = 1;
+                    ++cnt.pieces;
+                }
+                if (A.T <= kTTerm) return true;
+            }
+            if (b >= zb) break;
+        }
+        p = last >= 0 ? last : min(j, n - 1);
+    } else if (Zp < -kFlatZ) {
+        const double inv = -1.0 / Zp;
+        int j = last_front_below<SEARCH>(dep, plane, li, n, za, p);
+        int last = -1;
+        for (; j >= 0; --j) {
+            const float2 fb = dep[(uint64_t)j * plane + li];
+            const double f = fb.x, b = fb.y;
+            if (b <= zb) break;
+            const double zl = fmax(zb, f), zh = fmin(za, b);
+            if (zh > zl) {
+                const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * plane + li);
+                composite(A, c, (float)((zh - zl) * inv) * cth / (fb.y - fb.x));
+                last = j;
+                if constexpr (COUNT) {
+                    F.touched_slots[(uint64_t)j * plane + li] = 1;
+                    ++cnt.pieces;
+                }
+                if (A.T <= kTTerm) return true;
+            }
+            if (f <= zb) break;
+        }
+        p = last >= 0 ? last : max(j, 0);
+    } else {
+        // Constant depth: the supersegment holding za covers the whole piece.
+        for (int j = 0; j < n; ++j) {
+            const float2 fb = dep[(uint64_t)j * plane + li];
+            if ((double)fb.x <= za && za < (double)fb.y) {
+                const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * plane + li);
+                composite(A, c, (float)(tb - ta) * cth / (fb.y - fb.x));
+                p = j;
+                if constexpr (COUNT) {
+                    F.touched_slots[(uint64_t)j * plane + li] = 1;
+                    ++cnt.pieces;
+                }
+                return A.T <= kTTerm;
+            }
+        }
+    }
+    return false;
+}
+
+// ---------------------------------------------------------------------------
+// Exact render (Sections 4.1-4.3)
+// ---------------------------------------------------------------------------
+template <int FMT, int SEARCH, bool ESS, bool COUNT>
+__global__ __launch_bounds__(kBlock) void k_render_exact(DevVDI V, Frame F)
+{
+    __shared__ float s_gz[VDI_MAX_GRID_NZ + 1];
+    if constexpr (ESS) {
+        for (int i = threadIdx.x; i <= V.gnz; i += kBlock) s_gz[i] = V.gz[i];
+        __syncthreads();
+    }
+    const int tiles_x = (F.W + kTileW - 1) / kTileW, tiles_y = (F.H + kTileH - 1) / kTileH;
+    const int tile = xcd_tile(blockIdx.x, tiles_x * tiles_y);
+    const int px = (tile % tiles_x) * kTileW + (threadIdx.x % kTileW);
+    const int py = (tile / tiles_x) * kTileH + (threadIdx.x / kTileW);
+    if (px >= F.W || py >= F.H) return;
+
+    Accum A = {0.0f, 0.0f, 0.0f, 1.0f};
+    Counters cnt = {0, 0};
+    Ray r;
+    const double xc = -1.0 + (2.0 * px + 1.0) / F.W, yc = -1.0 + (2.0 * py + 1.0) / F.H;
+    if (ray_setup(F, xc, yc, r)) {
+        const int WO = V.WO, HO = V.HO;
+        // Direction of travel across the list grid: d/dt (X/Z) has the sign of Kx.
+        const double Kx = r.Xp * F.Z0 - F.X0 * r.Zp, Ky = r.Yp * F.Z0 - F.Y0 * r.Zp;
+        const int sx = (Kx > 0.0) - (Kx < 0.0), sy = (Ky > 0.0) - (Ky < 0.0);
+        const double inf = __builtin_huge_val();
+        double t = r.t0;
+        int ix, iy, mx, my;
+        double tx, ty;
+        auto locate = [&](double tt) {
+            const double z = F.Z0 + tt * r.Zp;
+            ix = cell_of((F.X0 + tt * r.Xp) / z, WO, sx);
+            iy = cell_of((F.Y0 + tt * r.Yp) / z, HO, sy);
+            mx = sx > 0 ? ix + 1 : ix;
+            my = sy > 0 ? iy + 1 : iy;
+            tx = (sx != 0 && mx > 0 && mx < WO) ? line_t(mx, WO, F.X0, r.Xp, F.Z0, r.Zp) : inf;
+            ty = (sy != 0 && my > 0 && my < HO) ? line_t(my, HO, F.Y0, r.Yp, F.Z0, r.Zp) : inf;
+        };
+        locate(t);
+        int p = -1;
+        // Every iteration moves one list or jumps a grid cell; the cap only
+        // guards against a non-advancing loop.
+        const int max_iter = 4 * (WO + HO) + 4 * V.gnz + 64;
+        for (int it = 0; it < max_iter; ++it) {
+            double tn = fmin(fmin(tx, ty), r.t1);
+            if constexpr (ESS) {
+                // Empty-space skipping (Section 4.3): a cell with count 0 is
+                // crossed in one step, to the nearest of its faces.
+                const int cx = ix / V.gk, cy = iy / V.gk;
+                const bool fwd = r.Zp >= 0.0;
+                const int cz = slice_of(s_gz, V.gnz, F.Z0 + t * r.Zp, fwd);
+                if (V.grid[((uint64_t)cz * V.GH + cy) * V.GW + cx] == 0u) {
+                    double te = r.t1;
+                    if (sx != 0) {
+                        const int m = sx > 0 ? min((cx + 1) * V.gk, WO) : cx * V.gk;
+                        if (m > 0 && m < WO) te = fmin(te, line_t(m, WO, F.X0, r.Xp, F.Z0, r.Zp));
+                    }
+                    if (sy != 0) {
+                        const int m = sy > 0 ? min((cy + 1) * V.gk, HO) : cy * V.gk;
+                        if (m > 0 && m < HO) te = fmin(te, line_t(m, HO, F.Y0, r.Yp, F.Z0, r.Zp));
+                    }
+                    if (r.Zp > kFlatZ && cz + 1 < V.gnz) te = fmin(te, ((double)s_gz[cz + 1] - F.Z0) / r.Zp);
+                    if (r.Zp < -kFlatZ && cz > 0) te = fmin(te, ((double)s_gz[cz] - F.Z0) / r.Zp);
+                    if (te > t) {
+                        t = te;
+                        if (t >= r.t1) break;
+                        locate(t);
+                        continue;
+                    }
+                }
+            }
+            if (tn > t && do_list<FMT, SEARCH, COUNT>(V, F, ix, iy, t, tn, F.Z0, r.Zp, A, p, cnt)) break;
+            if (tn >= r.t1) break;
+            if (tx <= ty) {
+                ix += sx;
+                mx += sx;
+                tx = (mx > 0 && mx < WO) ? line_t(mx, WO, F.X0, r.Xp, F.Z0, r.Zp) : inf;
+            } else {
+                iy += sy;
+                my += sy;
+                ty = (my > 0 && my < HO) ? line_t(my, HO, F.Y0, r.Yp, F.Z0, r.Zp) : inf;
+            }
+            t = fmax(t, tn);
+            if ((unsigned)ix >= (unsigned)WO || (unsigned)iy >= (unsigned)HO) break;
+        }
+    }
+    F.out[(uint64_t)py * F.W + px] = make_float4(A.r, A.g, A.b, 1.0f - A.T);
+    if constexpr (COUNT) {
+        if (F.ray_stats) {
+            F.ray_stats[2 * ((uint64_t)py * F.W + px)] = cnt.lists;
+            F.ray_stats[2 * ((uint64_t)py * F.W + px) + 1] = cnt.pieces;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Preview: adaptive along-ray subsampling (Section 4.4)
+// ---------------------------------------------------------------------------
+template <int FMT>
+__global__ __launch_bounds__(kBlock) void k_render_preview(DevVDI V, Frame F)
+{
+    __shared__ float s_gz[VDI_MAX_GRID_NZ + 1];
+    for (int i = threadIdx.x; i <= V.gnz; i += kBlock) s_gz[i] = V.gz[i];
+    __syncthreads();
+    const int tiles_x = (F.W + kTileW - 1) / kTileW, tiles_y = (F.H + kTileH - 1) / kTileH;
+    const int tile = xcd_tile(blockIdx.x, tiles_x * tiles_y);
+    const int px = (tile % tiles_x) * kTileW + (threadIdx.x % kTileW);
+    const int py = (tile / tiles_x) * kTileH + (threadIdx.x / kTileW);
+    if (px >= F.W || py >= F.H) return;
+
+    Accum A = {0.0f, 0.0f, 0.0f, 1.0f};
+    Ray r;
+    const double xc = -1.0 + (2.0 * px + 1.0) / F.W, yc = -1.0 + (2.0 * py + 1.0) / F.H;
+    if (ray_setup(F, xc, yc, r)) {
+        const int WO = V.WO, HO = V.HO, k = V.gk;
+        const double Kx = r.Xp * F.Z0 - F.X0 * r.Zp, Ky = r.Yp * F.Z0 - F.Y0 * r.Zp;
+        const int sx = (Kx > 0.0) - (Kx < 0.0), sy = (Ky > 0.0) - (Ky < 0.0);
+        const bool fwd = r.Zp >= 0.0;
+        const bool flat = fabs(r.Zp) < kFlatZ;
+        const double inf = __builtin_huge_val();
+        const double inv_k2 = 1.0 / (double)(k * k);
+        const float2 *__restrict__ dep = V.depth;
+        const uint64_t plane = V.plane;
+        double t = r.t0;
+        int cx, cy, cz, mx, my;
+        double tx, ty, tz;
+        auto locate = [&](double tt) {
+            const double z = F.Z0 + tt * r.Zp;
+            cx = cell_of((F.X0 + tt * r.Xp) / z, WO, sx) / k;
+            cy = cell_of((F.Y0 + tt * r.Yp) / z, HO, sy) / k;
+            cz = slice_of(s_gz, V.gnz, z, fwd);
+            mx = sx > 0 ? min((cx + 1) * k, WO) : cx * k;
+            my = sy > 0 ? min((cy + 1) * k, HO) : cy * k;
+            tx = (sx != 0 && mx > 0 && mx < WO) ? line_t(mx, WO, F.X0, r.Xp, F.Z0, r.Zp) : inf;
+            ty = (sy != 0 && my > 0 && my < HO) ? line_t(my, HO, F.Y0, r.Yp, F.Z0, r.Zp) : inf;
+            if (flat)
+                tz = inf;
+            else if (fwd)
+                tz = cz + 1 < V.gnz ? ((double)s_gz[cz + 1] - F.Z0) / r.Zp : inf;
+            else
+                tz = cz > 0 ? ((double)s_gz[cz] - F.Z0) / r.Zp : inf;
+        };
+        locate(t);
+        int p = -1;
+        const int max_iter = 4 * (WO + HO) / k + 4 * V.gnz + 64;
+        bool done = false;
+        for (int it = 0; it < max_iter && !done; ++it) {
+            const double tn = fmin(fmin(fmin(tx, ty), tz), r.t1);
+            if (tn > t) {
+                const uint32_t G = V.grid[((uint64_t)cz * V.GH + cy) * V.GW + cx];
+                if (G != 0u) {
+                    const double dz = (double)s_gz[cz + 1] - (double)s_gz[cz];
+                    const double x = ((tn - t) / dz) * ((double)G * inv_k2) / F.DR;
+                    // D_R >= 1e-4 keeps x far below this bound; it only caps the loop.
+                    const int n = (int)fmin(fmax(ceil(x), 1.0), 16777216.0);
+                    const double h = (tn - t) / n;
+                    for (int q = 0; q < n; ++q) {
+                        const double u = t + (q + 0.5) * h;
+                        const double z = F.Z0 + u * r.Zp;
+                        const int lx = min(max((int)floor(((F.X0 + u * r.Xp) / z + 1.0) * WO / 2.0), 0), WO - 1);
+                        const int ly = min(max((int)floor(((F.Y0 + u * r.Yp) / z + 1.0) * HO / 2.0), 0), HO - 1);
+                        const uint64_t li = (uint64_t)ly * WO + lx;
+                        const int nl = V.count[li];
+                        if (nl == 0) continue;
+                        // Point location: the supersegment with f <= z < b.
+                        const int j = first_back_above<VDI_SEARCH_SEEDED>(dep, plane, li, nl, z, p);
+                        if (j >= nl) continue;
+                        const float2 fb = dep[(uint64_t)j * plane + li];
+                        p = j;
+                        if ((double)fb.x > z) continue;
+                        const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * plane + li);
+                        composite(A, c, (float)h * list_cos(V, lx, ly) / (fb.y - fb.x));
+                        if (A.T <= kTTerm) {
+                            done = true;
+                            break;
+                        }
+                    }
+                }
+            }
+            if (done || tn >= r.t1) break;
+            if (tx <= ty && tx <= tz) {
+                cx += sx;
+                mx = sx > 0 ? min((cx + 1) * k, WO) : cx * k;
+                tx = (mx > 0 && mx < WO) ? line_t(mx, WO, F.X0, r.Xp, F.Z0, r.Zp) : inf;
+            } else if (ty <= tz) {
+                cy += sy;
+                my = sy > 0 ? min((cy + 1) * k, HO) : cy * k;
+                ty = (my > 0 && my < HO) ? line_t(my, HO, F.Y0, r.Yp, F.Z0, r.Zp) : inf;
+            } else {
+                cz += fwd ? 1 : -1;
+                if (fwd)
+                    tz = cz + 1 < V.gnz ? ((double)s_gz[cz + 1] - F.Z0) / r.Zp : inf;
+                else
+                    tz = cz > 0 ? ((double)s_gz[cz] - F.Z0) / r.Zp : inf;
+            }
+            t = fmax(t, tn);
+            if ((unsigned)cx >= (unsigned)V.GW || (unsigned)cy >= (unsigned)V.GH || (unsigned)cz >= (unsigned)V.gnz)
+                break;
+        }
+    }
+    F.out[(uint64_t)py * F.W + px] = make_float4(A.r, A.g, A.b, 1.0f - A.T);
+}
+
+// ---------------------------------------------------------------------------
+// Bilinear upsampling, half-pixel centres, clamped (Section 4.4, Fig. 7)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_upsample(const float4 *__restrict__ lo, int w, int h,
+                                                  float4 *__restrict__ out, int W, int H)
+{
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= W || y >= H) return;
+    double sx = (x + 0.5) * (double)w / W - 0.5, sy = (y + 0.5) * (double)h / H - 0.5;
+    sx = fmin(fmax(sx, 0.0), (double)(w - 1));
+    sy = fmin(fmax(sy, 0.0), (double)(h - 1));
+    const int x0 = (int)sx, y0 = (int)sy;
+    const int x1 = min(x0 + 1, w - 1), y1 = min(y0 + 1, h - 1);
+    const float fx = (float)(sx - x0), fy = (float)(sy - y0);
+    const float4 a = lo[(uint64_t)y0 * w + x0], b = lo[(uint64_t)y0 * w + x1];
+    const float4 c = lo[(uint64_t)y1 * w + x0], d = lo[(uint64_t)y1 * w + x1];
+    auto mix = [&](float pa, float pb, float pc, float pd) {
+        return (pa * (1.0f - fx) + pb * fx) * (1.0f - fy) + (pc * (1.0f - fx) + pd * fx) * fy;
+    };
+    out[(uint64_t)y * W + x] = make_float4(mix(a.x, b.x, c.x, d.x), mix(a.y, b.y, c.y, d.y), mix(a.z, b.z, c.z, d.z),
+                                           mix(a.w, b.w, c.w, d.w));
+}
+
+// ---------------------------------------------------------------------------
+// Count grid (Section 4.3).  One workgroup per k x k column of lists; each
+// lane walks one list and counts, in LDS, the depth slices its supersegments
+// overlap with positive length.  No global atomics; deterministic.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_grid_build(DevVDI V, uint32_t *__restrict__ grid)
+{
+    __shared__ uint32_t s_cnt[VDI_MAX_GRID_NZ];
+    __shared__ float s_gz[VDI_MAX_GRID_NZ + 1];
+    const int k = V.gk;
+    const int cx = blockIdx.x % V.GW, cy = blockIdx.x / V.GW;
+    for (int i = threadIdx.x; i < V.gnz; i += blockDim.x) s_cnt[i] = 0u;
+    for (int i = threadIdx.x; i <= V.gnz; i += blockDim.x) s_gz[i] = V.gz[i];
+    __syncthreads();
+    const int lx = cx * k + (int)threadIdx.x % k, ly = cy * k + (int)threadIdx.x / k;
+    if ((int)threadIdx.x < k * k && lx < V.WO && ly < V.HO) {
+        const uint64_t li = (uint64_t)ly * V.WO + lx;
+        const int n = V.count[li];
+        for (int j = 0; j < n; ++j) {
+            const float2 fb = V.depth[(uint64_t)j * V.plane + li];
+            for (int c = 0; c < V.gnz; ++c)
+                if (fb.x < s_gz[c + 1] && fb.y > s_gz[c]) atomicAdd(&s_cnt[c], 1u);
+        }
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < V.gnz; c += blockDim.x)
+        grid[((uint64_t)c * V.GH + cy) * V.GW + cx] = s_cnt[c];
+}
+
+// ---------------------------------------------------------------------------
+// Colour storage conversion, float32 -> binary16 / bfloat16, round to nearest even
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_convert(const float4 *__restrict__ src, uint2 *__restrict__ dst, uint64_t n,
+                                                 int fmt)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const float4 v = src[i];
+        uint2 o;
+        if (fmt == VDI_F16) {
+            const __half2 rg = __floats2half2_rn(v.x, v.y), ba = __floats2half2_rn(v.z, v.w);
+            o.x = *reinterpret_cast<const uint32_t *>(&rg);
+            o.y = *reinterpret_cast<const uint32_t *>(&ba);
+        } else {
+            const __hip_bfloat16 r = __float2bfloat16(v.x), g = __float2bfloat16(v.y);
+            const __hip_bfloat16 b = __float2bfloat16(v.z), a = __float2bfloat16(v.w);
+            o.x = (uint32_t)(*reinterpret_cast<const uint16_t *>(&r)) |
+                  ((uint32_t)(*reinterpret_cast<const uint16_t *>(&g)) << 16);
+            o.y = (uint32_t)(*reinterpret_cast<const uint16_t *>(&b)) |
+                  ((uint32_t)(*reinterpret_cast<const uint16_t *>(&a)) << 16);
+        }
+        dst[i] = o;
+    }
+}
+
+template <int FMT, bool COUNT>
+hipError_t launch_exact_fmt(const DevVDI &v, const Frame &f, dim3 grid, hipStream_t s)
+{
+    const bool ess = f.ess != 0;
+    switch (f.search) {
+    case VDI_SEARCH_BINARY:
+        if (ess) k_render_exact<FMT, VDI_SEARCH_BINARY, true, COUNT><<<grid, kBlock, 0, s>>>(v, f);
+        else k_render_exact<FMT, VDI_SEARCH_BINARY, false, COUNT><<<grid, kBlock, 0, s>>>(v, f);
+        break;
+    case VDI_SEARCH_LINEAR:
+        if (ess) k_render_exact<FMT, VDI_SEARCH_LINEAR, true, COUNT><<<grid, kBlock, 0, s>>>(v, f);
+        else k_render_exact<FMT, VDI_SEARCH_LINEAR, false, COUNT><<<grid, kBlock, 0, s>>>(v, f);
+        break;
+    default:
+        if (ess) k_render_exact<FMT, VDI_SEARCH_SEEDED, true, COUNT><<<grid, kBlock, 0, s>>>(v, f);
+        else k_render_exact<FMT, VDI_SEARCH_SEEDED, false, COUNT><<<grid, kBlock, 0, s>>>(v, f);
+    }
+    return hipGetLastError();
+}
+
+inline dim3 tile_grid(int W, int H)
+{
+    return dim3((unsigned)(((W + kTileW - 1) / kTileW) * ((H + kTileH - 1) / kTileH)));
+}
+
+}  // namespace
+
+hipError_t launch_render_exact(const DevVDI &v, const Frame &f, bool counters, hipStream_t s)
+{
+    const dim3 g = tile_grid(f.W, f.H);
+    if (counters) {
+        switch (v.fmt) {
+        case VDI_F16: return launch_exact_fmt<VDI_F16, true>(v, f, g, s);
+        case VDI_BF16: return launch_exact_fmt<VDI_BF16, true>(v, f, g, s);
+        default: return launch_exact_fmt<VDI_F32, true>(v, f, g, s);
+        }
+    }
+    switch (v.fmt) {
+    case VDI_F16: return launch_exact_fmt<VDI_F16, false>(v, f, g, s);
+    case VDI_BF16: return launch_exact_fmt<VDI_BF16, false>(v, f, g, s);
+    default: return launch_exact_fmt<VDI_F32, false>(v, f, g, s);
+    }
+}
+
+hipError_t launch_render_preview(const DevVDI &v, const Frame &f, hipStream_t s)
+{
+    const dim3 g = tile_grid(f.W, f.H);
+    switch (v.fmt) {
+    case VDI_F16: k_render_preview<VDI_F16><<<g, kBlock, 0, s>>>(v, f); break;
+    case VDI_BF16: k_render_preview<VDI_BF16><<<g, kBlock, 0, s>>>(v, f); break;
+    default: k_render_preview<VDI_F32><<<g, kBlock, 0, s>>>(v, f); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_upsample(const float4 *lo, int32_t w, int32_t h, float4 *out, int32_t W, int32_t H, hipStream_t s)
+{
+    const dim3 g((unsigned)((W + 63) / 64), (unsigned)((H + 3) / 4));
+    k_upsample<<<g, 256, 0, s>>>(lo, w, h, out, W, H);
+    return hipGetLastError();
+}
+
+hipError_t launch_grid_build(const DevVDI &v, uint32_t *grid, hipStream_t s)
+{
+    const int threads = ((v.gk * v.gk + 63) / 64) * 64;
+    k_grid_build<<<dim3((unsigned)(v.GW * v.GH)), threads, 0, s>>>(v, grid);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_rgba(const float4 *src, void *dst, uint64_t n, int32_t fmt, hipStream_t s)
+{
+    const uint64_t blocks = (n + 255) / 256;
+    const unsigned g = (unsigned)(blocks < 65536 ? blocks : 65536);
+    k_convert<<<g, 256, 0, s>>>(src, reinterpret_cast<uint2 *>(dst), n, fmt);
+    return hipGetLastError();
+}
+
+}  // namespace vdi

@@ -1,0 +1,242 @@
+"""Python binding of libvdi (include/vdi.h): argument marshalling only.
+
+Every step of a render runs in the library's HIP kernels; torch provides the
+device buffers and the stream.  Importing works without a GPU; any call that
+needs the library raises if libvdi.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvdi.so")
+
+VDI_OK = 0
+VDI_ERR_ARG = -1
+VDI_ERR_OOM = -2
+VDI_ERR_HIP = -3
+VDI_ERR_BUDGET = -4
+VDI_ERR_STATE = -5
+
+FORMATS = {"f32": 0, "f16": 1, "bf16": 2}
+SEARCH = {"seeded": 0, "binary": 1, "linear": 2}
+
+# Every symbol include/vdi.h declares.
+EXPORTS = ("vdi_create", "vdi_render", "vdi_render_ex", "vdi_render_counters", "vdi_get_grid", "vdi_get_info",
+           "vdi_destroy", "vdi_lowres_size", "vdi_plane_bytes", "vdi_last_error", "vdi_server_create",
+           "vdi_server_submit", "vdi_server_poll", "vdi_server_drain", "vdi_server_get_stats", "vdi_server_destroy")
+
+
+class VdiError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libvdi error {code}: {msg}")
+        self.code = code
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("eye", ctypes.c_float * 3), ("target", ctypes.c_float * 3), ("up", ctypes.c_float * 3),
+                ("fov_y_deg", ctypes.c_float), ("near_plane", ctypes.c_float)]
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("max_supersegments", ctypes.c_int32),
+                ("camera_VO", Camera), ("aabb_min", ctypes.c_float * 3), ("aabb_max", ctypes.c_float * 3),
+                ("count", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("rgba", ctypes.c_void_p),
+                ("rgba_fmt_in", ctypes.c_int32), ("rgba_fmt_store", ctypes.c_int32),
+                ("grid_k", ctypes.c_int32), ("grid_nz", ctypes.c_int32), ("grid_z", ctypes.c_void_p),
+                ("validate", ctypes.c_int32)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("ess", ctypes.c_int32), ("search", ctypes.c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("max_supersegments", ctypes.c_int32),
+                ("rgba_fmt", ctypes.c_int32), ("grid_k", ctypes.c_int32), ("grid_nz", ctypes.c_int32),
+                ("grid_w", ctypes.c_int32), ("grid_h", ctypes.c_int32), ("device_bytes", ctypes.c_uint64),
+                ("supersegments", ctypes.c_uint64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("rejected_budget", ctypes.c_uint64), ("rejected_slots", ctypes.c_uint64),
+                ("bytes_in_flight", ctypes.c_uint64), ("peak_bytes_in_flight", ctypes.c_uint64),
+                ("inflight", ctypes.c_int32), ("peak_inflight", ctypes.c_int32), ("kernel_running", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libvdi.so; raises if it was not built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2206_08660_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, F = ctypes.c_void_p, ctypes.c_int32, ctypes.c_float
+        L.vdi_create.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(P)]
+        L.vdi_render.argtypes = [P, ctypes.POINTER(Camera), I32, I32, F, F, P, P]
+        L.vdi_render_ex.argtypes = [P, ctypes.POINTER(Camera), I32, I32, F, F, ctypes.POINTER(Opts), P, P]
+        L.vdi_render_counters.argtypes = [P, ctypes.POINTER(Camera), I32, I32, ctypes.POINTER(Opts), P, P, P, P, P]
+        L.vdi_get_grid.argtypes = [P, P, ctypes.c_size_t]
+        L.vdi_get_info.argtypes = [P, ctypes.POINTER(Info)]
+        L.vdi_destroy.argtypes = [P]
+        L.vdi_lowres_size.argtypes = [I32, I32, F, ctypes.POINTER(I32), ctypes.POINTER(I32)]
+        L.vdi_plane_bytes.argtypes = [I32, I32, I32, I32]
+        L.vdi_plane_bytes.restype = ctypes.c_uint64
+        L.vdi_last_error.restype = ctypes.c_char_p
+        L.vdi_server_create.argtypes = [ctypes.c_uint64, I32, I32, ctypes.POINTER(P)]
+        L.vdi_server_submit.argtypes = [P, P, ctypes.POINTER(Camera), I32, I32, F, F, P,
+                                        ctypes.POINTER(ctypes.c_uint64)]
+        L.vdi_server_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
+        L.vdi_server_drain.argtypes = [P]
+        L.vdi_server_get_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
+        L.vdi_server_destroy.argtypes = [P]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != VDI_OK:
+        raise VdiError(rc, lib().vdi_last_error().decode())
+
+
+def last_error() -> str:
+    return lib().vdi_last_error().decode()
+
+
+def camera(cam) -> Camera:
+    """ctypes camera from any object with eye, target, up, fov_y_deg, near."""
+    c = Camera()
+    c.eye[:] = [float(x) for x in cam.eye]
+    c.target[:] = [float(x) for x in cam.target]
+    c.up[:] = [float(x) for x in cam.up]
+    c.fov_y_deg = float(cam.fov_y_deg)
+    c.near_plane = float(cam.near)
+    return c
+
+
+def lowres_size(width: int, height: int, d_i: float):
+    w, h = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().vdi_lowres_size(width, height, d_i, ctypes.byref(w), ctypes.byref(h)))
+    return w.value, h.value
+
+
+def plane_bytes(width: int, height: int, ns: int, fmt: str = "f32") -> int:
+    return int(lib().vdi_plane_bytes(width, height, ns, FORMATS[fmt]))
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _opts(ess: bool, search: str) -> Opts:
+    return Opts(1 if ess else 0, SEARCH[search])
+
+
+class Vdi:
+    """A VDI resident in device memory (vdi_create ... vdi_destroy)."""
+
+    def __init__(self, src, store: str = "f32", validate: bool = False, rgba_in: Optional[np.ndarray] = None,
+                 fmt_in: str = "f32"):
+        """src: any object with width, height, ns, camera, bmin, bmax, count,
+        depth, rgba, grid_k, grid_nz, grid_z (e.g. inputs.VDI)."""
+        self._h = None
+        count = np.ascontiguousarray(src.count, dtype=np.uint8)
+        depth = np.ascontiguousarray(src.depth, dtype=np.float32)
+        rgba = np.ascontiguousarray(src.rgba if rgba_in is None else rgba_in)
+        if fmt_in == "f32":
+            rgba = rgba.astype(np.float32, copy=False)
+        gz = None if src.grid_z is None else np.ascontiguousarray(src.grid_z, dtype=np.float32)
+        d = Desc()
+        d.width, d.height, d.max_supersegments = src.width, src.height, src.ns
+        d.camera_VO = camera(src.camera)
+        d.aabb_min[:] = [float(x) for x in src.bmin]
+        d.aabb_max[:] = [float(x) for x in src.bmax]
+        d.count = count.ctypes.data
+        d.depth = depth.ctypes.data
+        d.rgba = rgba.ctypes.data
+        d.rgba_fmt_in = FORMATS[fmt_in]
+        d.rgba_fmt_store = FORMATS[store]
+        d.grid_k, d.grid_nz = src.grid_k, src.grid_nz
+        d.grid_z = None if gz is None else gz.ctypes.data
+        d.validate = 1 if validate else 0
+        h = ctypes.c_void_p()
+        _check(lib().vdi_create(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        self.width, self.height, self.ns, self.store = src.width, src.height, src.ns, store
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if self._h is None:
+            raise VdiError(VDI_ERR_STATE, "VDI already destroyed")
+        return self._h
+
+    def render(self, cam, width: int, height: int, d_i: float = 1.0, d_r: float = 0.0, out=None, stream=None,
+               ess: bool = True, search: str = "seeded"):
+        """Render into a float32 [height, width, 4] device tensor (allocated if
+        `out` is None) on `stream` (default: torch's current stream)."""
+        import torch
+        if out is None:
+            out = torch.empty((height, width, 4), dtype=torch.float32, device="cuda")
+        if out.dtype != torch.float32 or not out.is_cuda or not out.is_contiguous() or out.numel() < height * width * 4:
+            raise ValueError("out must be a contiguous float32 CUDA tensor with height*width*4 elements")
+        c = camera(cam)
+        o = _opts(ess, search)
+        _check(lib().vdi_render_ex(self.handle, ctypes.byref(c), width, height, d_i, d_r, ctypes.byref(o),
+                                   ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+        return out
+
+    def render_counters(self, cam, width: int, height: int, ess: bool = False, search: str = "seeded",
+                        stream=None):
+        """Instrumented exact render: (image, touched_lists [H_O, W_O] u8,
+        touched_slots [N_S, H_O, W_O] u8, ray_stats [H, W, 2] i32), all torch CUDA tensors."""
+        import torch
+        out = torch.empty((height, width, 4), dtype=torch.float32, device="cuda")
+        tl = torch.zeros((self.height, self.width), dtype=torch.uint8, device="cuda")
+        ts = torch.zeros((self.ns, self.height, self.width), dtype=torch.uint8, device="cuda")
+        st = torch.zeros((height, width, 2), dtype=torch.int32, device="cuda")
+        c = camera(cam)
+        o = _opts(ess, search)
+        _check(lib().vdi_render_counters(self.handle, ctypes.byref(c), width, height, ctypes.byref(o),
+                                         ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(tl.data_ptr()),
+                                         ctypes.c_void_p(ts.data_ptr()), ctypes.c_void_p(st.data_ptr()),
+                                         _stream_handle(stream)))
+        return out, tl, ts, st
+
+    def info(self) -> Info:
+        i = Info()
+        _check(lib().vdi_get_info(self.handle, ctypes.byref(i)))
+        return i
+
+    def grid(self) -> np.ndarray:
+        i = self.info()
+        g = np.zeros((i.grid_nz, i.grid_h, i.grid_w), dtype=np.uint32)
+        _check(lib().vdi_get_grid(self.handle, ctypes.c_void_p(g.ctypes.data), g.size))
+        return g
+
+    def close(self):
+        if self._h is not None:
+            h, self._h = self._h, None
+            _check(lib().vdi_destroy(h))
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,175 @@
+"""HIP path vs the FP64 oracle, through the C ABI (needs an MI355X).
+
+Exact mode: max |dRGBA| <= 1e-4 on every pixel (the result is unique).
+Preview mode: the same bound on pixels the oracle does not flag as resting on
+a floating-point tie; the flagged fraction is bounded.
+Count grid: bit-exact.  Search strategies and ESS: same image.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+from tests import synth
+from tests.gpu_util import TOL, psnr, sample_pixels
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def _v():
+    from paper_2206_08660_amd import vdi as V
+    return V
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_render(h, cam, W, H, **kw):
+    out = h.render(cam, W, H, **kw)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return inputs.load_workload("tiny")
+
+
+@pytest.fixture(scope="module")
+def tiny_h(tiny):
+    V = _v()
+    h = V.Vdi(tiny)
+    yield h
+    h.close()
+
+
+# ------------------------------------------------------------------ exact, tiny
+@pytest.mark.parametrize("theta", [0.0, 5.0, 17.0, -33.0, 60.0])
+def test_tiny_exact_full_frame(tiny, tiny_h, theta):
+    say(f"[gpu] tiny exact theta={theta}")
+    cam = inputs.orbit_camera(theta)
+    ref = oracle.render_exact(tiny, cam, 128, 128)
+    for ess in (True, False):
+        for search in ("seeded", "binary", "linear"):
+            img = gpu_render(tiny_h, cam, 128, 128, ess=ess, search=search)
+            err = np.abs(img - ref).max()
+            assert err <= TOL, (theta, ess, search, err)
+
+
+def test_tiny_exact_ragged_sizes(tiny, tiny_h):
+    # Output sizes that are not multiples of the 64 x 4 tile, and 1 x 1.
+    cam = inputs.orbit_camera(7.0)
+    for (W, H) in [(1, 1), (65, 5), (131, 97), (200, 37)]:
+        say(f"[gpu] tiny ragged {W}x{H}")
+        img = gpu_render(tiny_h, cam, W, H)
+        ref = oracle.render_exact(tiny, cam, W, H)
+        assert np.abs(img - ref).max() <= TOL, (W, H)
+
+
+def test_identity_view_reproduces_composite(tiny, tiny_h):
+    img = gpu_render(tiny_h, tiny.camera, 128, 128)
+    assert np.abs(img - synth.composite_at_vo(tiny)).max() <= TOL
+
+
+def test_deterministic(tiny_h):
+    cam = inputs.orbit_camera(11.0)
+    a = tiny_h.render(cam, 128, 128).cpu().numpy()
+    b = tiny_h.render(cam, 128, 128).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------------ synthetic VDIs
+@pytest.mark.parametrize("seed,theta", [(1, 8.0), (2, 25.0), (3, -40.0), (4, 90.0), (5, 135.0), (6, 180.0)])
+def test_random_vdi_exact(seed, theta):
+    V = _v()
+    say(f"[gpu] random VDI seed={seed} theta={theta}")
+    v = synth.random_vdi(40, 24, 7, seed=seed)
+    cam = inputs.orbit_camera(theta)
+    ref = oracle.render_exact(v, cam, 70, 45)
+    with V.Vdi(v, validate=True) as h:
+        for ess in (True, False):
+            for search in ("seeded", "binary", "linear"):
+                img = gpu_render(h, cam, 70, 45, ess=ess, search=search)
+                assert np.abs(img - ref).max() <= TOL, (ess, search)
+
+
+def test_slab_closed_form_on_gpu():
+    V = _v()
+    slabs = [(1.2, 1.4, 2.0, (0.9, 0.1, 0.1)), (1.5, 1.9, 5.0, (0.1, 0.8, 0.3))]
+    v = synth.slab_vdi(96, 64, slabs)
+    cam = inputs.orbit_camera(21.0)
+    ref = oracle.render_exact(v, cam, 80, 60)
+    with V.Vdi(v) as h:
+        img = gpu_render(h, cam, 80, 60)
+    assert np.abs(img - ref).max() <= TOL
+
+
+def test_empty_vdi_on_gpu():
+    V = _v()
+    v = synth.empty_vdi(16, 16, 3)
+    with V.Vdi(v) as h:
+        img = gpu_render(h, inputs.orbit_camera(10.0), 33, 17)
+        pv = gpu_render(h, inputs.orbit_camera(10.0), 33, 17, d_i=2.0, d_r=1.0)
+    assert not img.any() and not pv.any()
+
+
+# ------------------------------------------------------------------ count grid
+def test_grid_bit_exact_small(tiny, tiny_h):
+    assert np.array_equal(tiny_h.grid(), oracle.count_grid(tiny))
+    V = _v()
+    v = synth.random_vdi(37, 21, 9, seed=12)
+    with V.Vdi(v) as h:
+        assert np.array_equal(h.grid(), oracle.count_grid(v))
+
+
+# ------------------------------------------------------------------ preview, tiny
+@pytest.mark.parametrize("d_i,d_r", [(1.0, 2.0), (1.0, 0.5), (2.0, 0.0), (2.0, 2.0), (4.0, 2.0), (3.0, 0.25)])
+def test_tiny_preview(tiny, tiny_h, d_i, d_r):
+    say(f"[gpu] tiny preview D_I={d_i} D_R={d_r}")
+    cam = inputs.orbit_camera(9.0)
+    ref, flags = oracle.render(tiny, cam, 128, 128, d_i, d_r)
+    img = gpu_render(tiny_h, cam, 128, 128, d_i=d_i, d_r=d_r)
+    ok = flags == 0
+    assert ok.mean() > 0.99
+    assert np.abs(img - ref)[ok].max() <= TOL
+
+
+def test_random_preview_backward():
+    V = _v()
+    v = synth.random_vdi(32, 24, 6, seed=9)
+    cam = inputs.orbit_camera(150.0)
+    ref, flags = oracle.render(v, cam, 50, 40, 1.0, 0.3)
+    with V.Vdi(v) as h:
+        img = gpu_render(h, cam, 50, 40, d_r=0.3)
+    ok = flags == 0
+    assert ok.mean() > 0.98
+    assert np.abs(img - ref)[ok].max() <= TOL
+
+
+# ------------------------------------------------------------------ counters (B_alg)
+def test_counters_match_oracle(tiny, tiny_h):
+    cam = inputs.orbit_camera(14.0)
+    img, tl, ts, st = tiny_h.render_counters(cam, 128, 128, ess=False)
+    torch.cuda.synchronize()
+    ref, ost, otl, ots = oracle.render_exact(tiny, cam, 128, 128, stats=True, touched=True)
+    assert np.abs(img.cpu().numpy() - ref).max() <= TOL
+    gl, gs = tl.cpu().numpy(), ts.cpu().numpy()
+    # Lists and supersegments touched agree except where FP32 and FP64 termination straddle.
+    assert (gl != otl).sum() <= 2 + 1e-3 * otl.sum()
+    assert (gs != ots).sum() <= 2 + 1e-3 * ots.sum()
+    assert np.abs(st.cpu().numpy() - ost).max() <= 2
