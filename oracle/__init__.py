@@ -217,11 +217,12 @@ def dequant_f16(x: np.ndarray) -> np.ndarray:
 
 def dequant_bf16(x: np.ndarray) -> np.ndarray:
     """float32 -> bfloat16 by rounding the low 16 bits to nearest, ties to
-    even (finite inputs), -> float32."""
-    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
-    lsb = (u >> 16) & 1
-    r = ((u + 0x7FFF + lsb) >> 16) << 16
-    return (r & 0xFFFFFFFF).astype(np.uint32).view(np.float32)
+    even (finite inputs; the largest finite values round to infinity as IEEE
+    rounding does), -> float32."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32)
+    lsb = (u >> np.uint32(16)) & np.uint32(1)
+    r = (u + np.uint32(0x7FFF) + lsb) & np.uint32(0xFFFF0000)
+    return r.view(np.float32)
 
 
 # ----------------------------------------------------------------------------

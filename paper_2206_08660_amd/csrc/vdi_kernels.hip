@@ -24,12 +24,16 @@
 namespace vdi {
 namespace {
 
+// Per-ray functions are host-callable too, so the traversal can be stepped
+// through on the CPU with the same code.
+#define VDI_HD __host__ __device__
+
 constexpr int kTileW = 64;
 constexpr int kTileH = 4;
 constexpr int kBlock = kTileW * kTileH;
 constexpr int kXcds = 8;
 
-__device__ __forceinline__ double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+VDI_HD inline double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
 // Tile of this workgroup: blocks are dealt to XCDs round-robin, so give XCD x
 // the x-th contiguous range of tiles.
@@ -44,7 +48,7 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblocks)
 // Colour planes
 // ---------------------------------------------------------------------------
 template <int FMT>
-__device__ __forceinline__ float4 load_rgba(const void *base, uint64_t idx)
+VDI_HD inline float4 load_rgba(const void *base, uint64_t idx)
 {
     if constexpr (FMT == VDI_F32) {
         return reinterpret_cast<const float4 *>(base)[idx];
@@ -56,8 +60,8 @@ __device__ __forceinline__ float4 load_rgba(const void *base, uint64_t idx)
             const float2 a = __half22float2(rg), b = __half22float2(ba);
             return make_float4(a.x, a.y, b.x, b.y);
         } else {
-            return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
-                               __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
+            return make_float4(__builtin_bit_cast(float, u.x << 16), __builtin_bit_cast(float, u.x & 0xffff0000u),
+                               __builtin_bit_cast(float, u.y << 16), __builtin_bit_cast(float, u.y & 0xffff0000u));
         }
     }
 }
@@ -71,7 +75,7 @@ struct Ray {
 };
 
 // Keep t with a + b t >= 0.
-__device__ __forceinline__ bool clip(double a, double b, double &lo, double &hi)
+VDI_HD inline bool clip(double a, double b, double &lo, double &hi)
 {
     if (b == 0.0) return a >= 0.0;
     const double t = -a / b;
@@ -85,7 +89,7 @@ __device__ __forceinline__ bool clip(double a, double b, double &lo, double &hi)
 // Ray through NDC (xc, yc) of V_N, clipped to V_N's near plane, the AABB and
 // V_O's frustum (Section 4.1: marching starts and ends where the ray meets
 // the generating viewport and the volume's bounding box).
-__device__ bool ray_setup(const Frame &F, double xc, double yc, Ray &r)
+VDI_HD bool ray_setup(const Frame &F, double xc, double yc, Ray &r)
 {
     double d[3];
     for (int a = 0; a < 3; ++a) d[a] = F.FN[a] + xc * F.tx_n * F.RN[a] + yc * F.ty_n * F.UN[a];
@@ -110,16 +114,21 @@ __device__ bool ray_setup(const Frame &F, double xc, double yc, Ray &r)
     return ok && hi > lo;
 }
 
-// Parameter where the ray meets NDC line coord = -1 + 2 m / n (P = X or Y).
-__device__ __forceinline__ double line_t(int m, int n, double P0, double Pp, double Z0, double Zp)
+// Parameter where the ray meets NDC line coord = -1 + 2 m / n (P = X or Y),
+// or +inf if it never does.  coord(t) = P(t) / Z(t) is monotone where Z > 0
+// but its asymptote is the ray's vanishing point: a line beyond it has its
+// only root on the branch behind V_O (Z < 0), which is not a crossing.
+VDI_HD inline double line_t(int m, int n, double P0, double Pp, double Z0, double Zp)
 {
     const double c = -1.0 + 2.0 * m / n;
-    return (c * Z0 - P0) / (Pp - c * Zp);
+    const double den = Pp - c * Zp;
+    const double t = (c * Z0 - P0) / den;
+    return (den != 0.0 && Z0 + t * Zp > 0.0) ? t : __builtin_huge_val();
 }
 
 // Cell index of an NDC coordinate; a point exactly on a line belongs to the
 // cell the ray is moving into.
-__device__ __forceinline__ int cell_of(double ndc, int n, int dir)
+VDI_HD inline int cell_of(double ndc, int n, int dir)
 {
     const double f = (ndc + 1.0) * n / 2.0;
     const double fl = floor(f);
@@ -129,15 +138,15 @@ __device__ __forceinline__ int cell_of(double ndc, int n, int dir)
 }
 
 // cos of the angle between list (ix, iy)'s generating ray and V_O's axis.
-__device__ __forceinline__ float list_cos(const DevVDI &V, int ix, int iy)
+VDI_HD inline float list_cos(const DevVDI &V, int ix, int iy)
 {
     const float x = (-1.0f + (2.0f * ix + 1.0f) / V.WO) * V.tx_o;
     const float y = (-1.0f + (2.0f * iy + 1.0f) / V.HO) * V.ty_o;
-    return rsqrtf(1.0f + x * x + y * y);
+    return 1.0f / sqrtf(1.0f + x * x + y * y);
 }
 
 // Depth slice holding depth z for a ray moving towards larger (fwd) or smaller z.
-__device__ __forceinline__ int slice_of(const float *gz, int gnz, double z, bool fwd)
+VDI_HD inline int slice_of(const float *gz, int gnz, double z, bool fwd)
 {
     int lo = 0, hi = gnz - 1;  // answer in [0, gnz-1]
     while (lo < hi) {
@@ -157,7 +166,7 @@ __device__ __forceinline__ int slice_of(const float *gz, int gnz, double z, bool
 // Smallest j in [0, n) with b_j > z (n if none).  Back depths increase with j
 // because supersegments are sorted and disjoint.
 template <int SEARCH>
-__device__ __forceinline__ int first_back_above(const float2 *__restrict__ dep, uint64_t plane, uint64_t li, int n,
+VDI_HD inline int first_back_above(const float2 *__restrict__ dep, uint64_t plane, uint64_t li, int n,
                                                 double z, int p)
 {
     if constexpr (SEARCH == VDI_SEARCH_LINEAR) {
@@ -192,7 +201,7 @@ __device__ __forceinline__ int first_back_above(const float2 *__restrict__ dep, 
 // Largest j in [0, n) with f_j < z (-1 if none): the first supersegment met by
 // a ray travelling towards smaller depth.
 template <int SEARCH>
-__device__ __forceinline__ int last_front_below(const float2 *__restrict__ dep, uint64_t plane, uint64_t li, int n,
+VDI_HD inline int last_front_below(const float2 *__restrict__ dep, uint64_t plane, uint64_t li, int n,
                                                 double z, int p)
 {
     if constexpr (SEARCH == VDI_SEARCH_LINEAR) {
@@ -232,7 +241,7 @@ struct Accum {
 
 // Eq. 2 with exponent l = (world length in S) / (world length of the
 // generating ray in S), then front-to-back "over".
-__device__ __forceinline__ void composite(Accum &A, float4 c, float l)
+VDI_HD inline void composite(Accum &A, float4 c, float l)
 {
     const float at = c.w >= 1.0f ? 1.0f : 1.0f - exp2f(l * log2f(1.0f - c.w));
     const float w = A.T * at;
@@ -250,7 +259,7 @@ struct Counters {
 // a ray with dz/dt = Zp.  p is the seed index, updated on return.  Returns
 // true once the ray has terminated.
 template <int FMT, int SEARCH, bool COUNT>
-__device__ bool do_list(const DevVDI &V, const Frame &F, int ix, int iy, double ta, double tb, double Z0, double Zp,
+VDI_HD bool do_list(const DevVDI &V, const Frame &F, int ix, int iy, double ta, double tb, double Z0, double Zp,
                         Accum &A, int &p, Counters &cnt)
 {
     const uint64_t li = (uint64_t)iy * V.WO + ix;
@@ -330,22 +339,11 @@ __device__ bool do_list(const DevVDI &V, const Frame &F, int ix, int iy, double 
 // ---------------------------------------------------------------------------
 // Exact render (Sections 4.1-4.3)
 // ---------------------------------------------------------------------------
+// One exact ray through V_N pixel (px, py); gz = slice boundaries (LDS copy).
 template <int FMT, int SEARCH, bool ESS, bool COUNT>
-__global__ __launch_bounds__(kBlock) void k_render_exact(DevVDI V, Frame F)
+VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, int px, int py, Counters &cnt)
 {
-    __shared__ float s_gz[VDI_MAX_GRID_NZ + 1];
-    if constexpr (ESS) {
-        for (int i = threadIdx.x; i <= V.gnz; i += kBlock) s_gz[i] = V.gz[i];
-        __syncthreads();
-    }
-    const int tiles_x = (F.W + kTileW - 1) / kTileW, tiles_y = (F.H + kTileH - 1) / kTileH;
-    const int tile = xcd_tile(blockIdx.x, tiles_x * tiles_y);
-    const int px = (tile % tiles_x) * kTileW + (threadIdx.x % kTileW);
-    const int py = (tile / tiles_x) * kTileH + (threadIdx.x / kTileW);
-    if (px >= F.W || py >= F.H) return;
-
     Accum A = {0.0f, 0.0f, 0.0f, 1.0f};
-    Counters cnt = {0, 0};
     Ray r;
     const double xc = -1.0 + (2.0 * px + 1.0) / F.W, yc = -1.0 + (2.0 * py + 1.0) / F.H;
     if (ray_setup(F, xc, yc, r)) {
@@ -414,7 +412,24 @@ __global__ __launch_bounds__(kBlock) void k_render_exact(DevVDI V, Frame F)
             if ((unsigned)ix >= (unsigned)WO || (unsigned)iy >= (unsigned)HO) break;
         }
     }
-    F.out[(uint64_t)py * F.W + px] = make_float4(A.r, A.g, A.b, 1.0f - A.T);
+    return make_float4(A.r, A.g, A.b, 1.0f - A.T);
+}
+
+template <int FMT, int SEARCH, bool ESS, bool COUNT>
+__global__ __launch_bounds__(kBlock) void k_render_exact(DevVDI V, Frame F)
+{
+    __shared__ float s_gz[VDI_MAX_GRID_NZ + 1];
+    if constexpr (ESS) {
+        for (int i = threadIdx.x; i <= V.gnz; i += kBlock) s_gz[i] = V.gz[i];
+        __syncthreads();
+    }
+    const int tiles_x = (F.W + kTileW - 1) / kTileW, tiles_y = (F.H + kTileH - 1) / kTileH;
+    const int tile = xcd_tile(blockIdx.x, tiles_x * tiles_y);
+    const int px = (tile % tiles_x) * kTileW + (threadIdx.x % kTileW);
+    const int py = (tile / tiles_x) * kTileH + (threadIdx.x / kTileW);
+    if (px >= F.W || py >= F.H) return;
+    Counters cnt = {0, 0};
+    F.out[(uint64_t)py * F.W + px] = trace_exact<FMT, SEARCH, ESS, COUNT>(V, F, s_gz, px, py, cnt);
     if constexpr (COUNT) {
         if (F.ray_stats) {
             F.ray_stats[2 * ((uint64_t)py * F.W + px)] = cnt.lists;
@@ -426,18 +441,10 @@ __global__ __launch_bounds__(kBlock) void k_render_exact(DevVDI V, Frame F)
 // ---------------------------------------------------------------------------
 // Preview: adaptive along-ray subsampling (Section 4.4)
 // ---------------------------------------------------------------------------
+// One preview ray through V_N pixel (px, py) of the (low-res) grid.
 template <int FMT>
-__global__ __launch_bounds__(kBlock) void k_render_preview(DevVDI V, Frame F)
+VDI_HD float4 trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, int px, int py)
 {
-    __shared__ float s_gz[VDI_MAX_GRID_NZ + 1];
-    for (int i = threadIdx.x; i <= V.gnz; i += kBlock) s_gz[i] = V.gz[i];
-    __syncthreads();
-    const int tiles_x = (F.W + kTileW - 1) / kTileW, tiles_y = (F.H + kTileH - 1) / kTileH;
-    const int tile = xcd_tile(blockIdx.x, tiles_x * tiles_y);
-    const int px = (tile % tiles_x) * kTileW + (threadIdx.x % kTileW);
-    const int py = (tile / tiles_x) * kTileH + (threadIdx.x / kTileW);
-    if (px >= F.W || py >= F.H) return;
-
     Accum A = {0.0f, 0.0f, 0.0f, 1.0f};
     Ray r;
     const double xc = -1.0 + (2.0 * px + 1.0) / F.W, yc = -1.0 + (2.0 * py + 1.0) / F.H;
@@ -528,7 +535,21 @@ __global__ __launch_bounds__(kBlock) void k_render_preview(DevVDI V, Frame F)
                 break;
         }
     }
-    F.out[(uint64_t)py * F.W + px] = make_float4(A.r, A.g, A.b, 1.0f - A.T);
+    return make_float4(A.r, A.g, A.b, 1.0f - A.T);
+}
+
+template <int FMT>
+__global__ __launch_bounds__(kBlock) void k_render_preview(DevVDI V, Frame F)
+{
+    __shared__ float s_gz[VDI_MAX_GRID_NZ + 1];
+    for (int i = threadIdx.x; i <= V.gnz; i += kBlock) s_gz[i] = V.gz[i];
+    __syncthreads();
+    const int tiles_x = (F.W + kTileW - 1) / kTileW, tiles_y = (F.H + kTileH - 1) / kTileH;
+    const int tile = xcd_tile(blockIdx.x, tiles_x * tiles_y);
+    const int px = (tile % tiles_x) * kTileW + (threadIdx.x % kTileW);
+    const int py = (tile / tiles_x) * kTileH + (threadIdx.x / kTileW);
+    if (px >= F.W || py >= F.H) return;
+    F.out[(uint64_t)py * F.W + px] = trace_preview<FMT>(V, F, s_gz, px, py);
 }
 
 // ---------------------------------------------------------------------------
