@@ -1,0 +1,286 @@
+#!/usr/bin/env python3
+"""Benchmark of VDI raycasting on one MI355X.
+
+One step renders the 1920x1080 VDI with N_S = 50 (the turbulence-shell
+workload) at the ten viewpoints 0, 5, ..., 45 degrees about the volume's y
+axis, each in three modes: exact (D_I = 1, D_R = 0) and the preview modes
+D_I = 2 / D_R = 2 and D_I = 4 / D_R = 2, all to a 1920x1080 output: 30 frames.
+The VDI is resident in HBM before timing starts (its generation on the host
+is never timed).
+
+Printed: one JSON line with Mpixels/s over the step, the roofline of the
+dominant kernel (algorithmic bytes per launch from the instrumented
+counter kernel / launch time from HIP events on the launch stream), the FP16
+and BF16 storage forms, the served form (continuous batching) and the FP64
+CPU oracle timed on a bounded pixel sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+W, H = 1920, 1080
+ANGLES = [5.0 * i for i in range(10)]
+MODES = [(1.0, 0.0), (2.0, 2.0), (4.0, 2.0)]
+METRIC = "VDI render Mpixels/s + HBM GB/s fraction; p50/p99 frame latency (served)"
+KERNEL_SRC = os.path.join(ROOT, "paper_2206_08660_amd", "csrc", "vdi_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_exact_1080p_traffic.json")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--skip-cpu-baseline", action="store_true")
+    p.add_argument("--skip-served", action="store_true")
+    p.add_argument("--skip-precision", action="store_true")
+    p.add_argument("--profile-pass", action="store_true",
+                   help="short run for rocprofv3: one 1 GiB copy (counter calibration) and one exact render per angle")
+    return p.parse_args()
+
+
+def kernel_hash() -> str:
+    return hashlib.sha1(open(KERNEL_SRC, "rb").read()).hexdigest()[:12]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU design is described, "
+              "not built", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import inputs
+    from paper_2206_08660_amd import vdi as V
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+
+    t = time.time()
+    src = inputs.load_workload("1080p", verbose=True)
+    log(f"workload ready in {time.time() - t:.1f}s: VDI {src.width}x{src.height}x{src.ns}, "
+        f"{int(src.count.sum())} supersegments")
+    h = V.Vdi(src)
+    info = h.info()
+    log(f"resident: {info.device_bytes / 2**30:.2f} GiB")
+    out = torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
+    cams = {th: inputs.orbit_camera(th) for th in ANGLES}
+    renders = [(th, di, dr) for th in ANGLES for (di, dr) in MODES]
+
+    if args.profile_pass:
+        a = torch.empty(2 ** 28, dtype=torch.float32, device="cuda").fill_(1.0)   # 1 GiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        for th in ANGLES:
+            h.render(cams[th], W, H, 1.0, 0.0, out=out)
+        torch.cuda.synchronize()
+        log("profile pass done")
+        return
+
+    def step(handle):
+        for (th, di, dr) in renders:
+            handle.render(cams[th], W, H, di, dr, out=out)
+
+    for _ in range(args.warmup):
+        step(h)
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} steps done; timing {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(h)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = 1e3 * elapsed / args.steps
+    mpix = len(renders) * W * H * args.steps / elapsed / 1e6
+    log(f"step {ms_step:.3f} ms, {mpix:.1f} Mpixels/s")
+
+    # Per-render launch times with HIP events on the launch stream.
+    reps = 10
+    per = {}
+    for (th, di, dr) in renders:
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for e0, e1 in ev:
+            e0.record(stream)
+            h.render(cams[th], W, H, di, dr, out=out)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        per[(th, di, dr)] = float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev]))
+    exact_ms = {th: per[(th, 1.0, 0.0)] for th in ANGLES}
+    mode_ms = {f"D_I={di:g},D_R={dr:g}": sum(per[(th, di, dr)] for th in ANGLES) for (di, dr) in MODES}
+    log("per-mode ms (sum over 10 angles): " + ", ".join(f"{k}: {v:.3f}" for k, v in mode_ms.items()))
+
+    # Algorithmic bytes of each exact frame (instrumented kernel, same options
+    # as the timed one): per list a ray entered, its count byte and all its
+    # (f, b) pairs; per supersegment composited, its colour; plus the output.
+    count_d = torch.from_numpy(np.ascontiguousarray(src.count)).cuda().to(torch.int64)
+    balg = {}
+    for th in ANGLES:
+        _, tl, ts, st = h.render_counters(cams[th], W, H, ess=True)
+        touched = tl.bool()
+        balg[th] = int(touched.sum().item() + 8 * count_d[touched].sum().item() + 16 * ts.sum(dtype=torch.int64).item()
+                       + 16 * W * H)
+        del tl, ts, st
+    torch.cuda.synchronize()
+    total_b = sum(balg.values())
+    total_s = sum(exact_ms.values()) / 1e3
+    achieved = total_b / total_s / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        if tr.get("kernel_src_sha1") == kernel_hash():
+            traffic = tr.get("bytes_per_launch")
+    breakdown = {
+        "exact_ms": {f"{th:g}": round(exact_ms[th], 4) for th in ANGLES},
+        "exact_balg_MB": {f"{th:g}": round(balg[th] / 1e6, 2) for th in ANGLES},
+        "exact_GBs": {f"{th:g}": round(balg[th] / exact_ms[th] / 1e6, 1) for th in ANGLES},
+        "preview_D_I2_D_R2_ms": {f"{th:g}": round(per[(th, 2.0, 2.0)], 4) for th in ANGLES},
+        "preview_D_I4_D_R2_ms": {f"{th:g}": round(per[(th, 4.0, 2.0)], 4) for th in ANGLES},
+        "mode_ms_per_10_angles": {k: round(v, 3) for k, v in mode_ms.items()},
+        "fps_exact": {f"{th:g}": round(1e3 / exact_ms[th], 1) for th in ANGLES},
+    }
+    result = {
+        "metric": METRIC,
+        "value": round(mpix, 2),
+        "unit": "Mpixels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded 1024x1024x512 f32 turbulence-shell volume -> VDI by Eq. 1 + Alg. S1)",
+        "config": {"workload": "1080p VDI 1920x1080, N_S=50, FP32 colour; 10 viewpoints 0-45 deg x "
+                               "{exact, D_I=2/D_R=2, D_I=4/D_R=2}; output 1920x1080",
+                   "frames_per_step": len(renders), "vdi_supersegments": int(info.supersegments),
+                   "vdi_device_GiB": round(info.device_bytes / 2 ** 30, 3)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "k_render_exact (exact mode, FP32 colour, ESS, seeded search)",
+                     "algorithmic_bytes_per_launch": int(total_b / len(ANGLES)),
+                     "launch_ms": round(1e3 * total_s / len(ANGLES), 4)},
+        "breakdown": breakdown,
+    }
+
+    if not args.skip_precision:
+        result["precision"] = precision_leg(src, cams, out, exact_ms, torch, V)
+    if not args.skip_served:
+        result["served"] = served_leg(torch, V)
+    h.close()
+    if not args.skip_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline_leg(src, cams, per, result.get("precision"), np, torch, V)
+    print(json.dumps(result), flush=True)
+
+
+def precision_leg(src, cams, out, exact_ms, torch, V):
+    """FP16 / BF16 colour storage: exact-mode frame times against FP32."""
+    import numpy as np
+    res = {}
+    stream = torch.cuda.current_stream()
+    for fmt in ("f16", "bf16"):
+        with V.Vdi(src, store=fmt) as hq:
+            ms = {}
+            for th in ANGLES:
+                for _ in range(2):
+                    hq.render(cams[th], W, H, out=out)
+                ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
+                for e0, e1 in ev:
+                    e0.record(stream)
+                    hq.render(cams[th], W, H, out=out)
+                    e1.record(stream)
+                torch.cuda.synchronize()
+                ms[th] = float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev]))
+            res[fmt] = {"exact_ms_sum_10_angles": round(sum(ms.values()), 4),
+                        "speedup_vs_f32": round(sum(exact_ms.values()) / sum(ms.values()), 3),
+                        "device_GiB": round(hq.info().device_bytes / 2 ** 30, 3)}
+        log(f"{fmt}: exact sweep {res[fmt]['exact_ms_sum_10_angles']:.3f} ms "
+            f"(x{res[fmt]['speedup_vs_f32']} vs f32)")
+    return res
+
+
+def served_leg(torch, V):
+    """Continuous-batching server (filled in by the serving module when built)."""
+    try:
+        from paper_2206_08660_amd import serve
+    except ImportError:
+        return None
+    return serve.benchmark(log=log)
+
+
+def cpu_baseline_leg(src, cams, per, precision, np, torch, V):
+    """The FP64 oracle on the host cores, on a bounded random sample of the
+    step's pixels; its per-frame time is extrapolated from the sample.  Also
+    the accuracy of the FP32/FP16/BF16 GPU frames on the same sample."""
+    import oracle
+    rng = np.random.default_rng(1234)
+    frac = {1.0: 0.02, 2.0: 0.002, 4.0: 0.002}
+    t_frames = 0.0
+    n_px = 0
+    errs = {"f32": [], "f16": [], "bf16": []}
+    sq = {"f32": [0.0, 0], "f16": [0.0, 0], "bf16": [0.0, 0]}
+    handles = {"f32": V.Vdi(src)}
+    deq = {"f16": oracle.dequant_f16(src.rgba), "bf16": oracle.dequant_bf16(src.rgba)}
+    for fmt in ("f16", "bf16"):
+        handles[fmt] = V.Vdi(src, store=fmt)
+    t_all = time.time()
+    for th in ANGLES:
+        for (di, dr) in MODES:
+            n = max(64, int(frac[di] * W * H))
+            pix = np.sort(rng.choice(W * H, size=n, replace=False))
+            t = time.perf_counter()
+            if dr == 0.0 and di == 1.0:
+                ref = oracle.render_exact(src, cams[th], W, H, pixels=pix)
+                flags = np.zeros(n, np.uint8)
+            else:
+                ref, flags = oracle.render_points(src, cams[th], W, H, di, dr, pix)
+            dt = time.perf_counter() - t
+            t_frames += dt / (n / (W * H))
+            n_px += n
+            if di == 1.0:
+                ok = flags == 0
+                for fmt, hh in handles.items():
+                    img = hh.render(cams[th], W, H).cpu().numpy().reshape(-1, 4)[pix].astype(np.float64)
+                    d = np.abs(img - ref)[ok]
+                    errs[fmt].append(float(d.max()))
+                    sq[fmt][0] += float((d ** 2).sum())
+                    sq[fmt][1] += d.size
+                    if fmt != "f32":
+                        rq = oracle.render_exact(src, cams[th], W, H, pixels=pix, rgba=deq[fmt])
+                        errs.setdefault(fmt + "_vs_dequantized", []).append(float(np.abs(img - rq).max()))
+    for hh in handles.values():
+        hh.close()
+    cpu_s = time.time() - t_all
+    mpix = len(per) * W * H / t_frames / 1e6
+    acc = {}
+    for fmt in ("f32", "f16", "bf16"):
+        mse = sq[fmt][0] / max(1, sq[fmt][1])
+        acc[fmt] = {"max_abs_vs_fp64_oracle": errs[fmt] and max(errs[fmt]),
+                    "psnr_db_vs_fp64_oracle": (None if mse == 0 else round(10 * math.log10(1.0 / mse), 2))}
+        if fmt != "f32":
+            acc[fmt]["max_abs_vs_oracle_on_dequantized"] = max(errs[fmt + "_vs_dequantized"])
+    log(f"cpu baseline: {mpix:.4f} Mpixels/s extrapolated, {n_px} pixels in {cpu_s:.1f}s on {oracle.threads()} threads")
+    return {"value": round(mpix, 5), "unit": "Mpixels/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{n_px} random pixels of the 30 frames of one step (2% of each exact frame, 0.2% of each "
+                      f"preview frame), frame time extrapolated per frame",
+            "accuracy_exact_mode_sampled": acc, "host_seconds": round(cpu_s, 1)}
+
+
+if __name__ == "__main__":
+    main()
