@@ -224,11 +224,12 @@ int validate_lists(const vdi_desc *d)
 void free_vdi(vdi_s *v)
 {
     if (!v) return;
-    hipFree(v->d_count);
-    hipFree(v->d_depth);
-    hipFree(v->d_rgba);
-    hipFree(v->d_grid);
-    hipFree(v->d_gz);
+    // Errors are ignored: every pointer was allocated here or is null.
+    (void)hipFree(v->d_count);
+    (void)hipFree(v->d_depth);
+    (void)hipFree(v->d_rgba);
+    (void)hipFree(v->d_grid);
+    (void)hipFree(v->d_gz);
     delete v;
 }
 
@@ -308,7 +309,11 @@ int vdi_create(const vdi_desc *d, vdi_t *out)
 
     vdi_s *v = new (std::nothrow) vdi_s();
     if (!v) return fail(VDI_ERR_OOM, "host allocation");
-    hipGetDevice(&v->device);
+    hipError_t e0;
+    if ((e0 = hipGetDevice(&v->device)) != hipSuccess) {
+        delete v;
+        return hip_fail(e0, "hipGetDevice");
+    }
     v->cam_o = d->camera_VO;
     memcpy(v->bmin, d->aabb_min, sizeof v->bmin);
     memcpy(v->bmax, d->aabb_max, sizeof v->bmax);
@@ -359,7 +364,8 @@ int vdi_create(const vdi_desc *d, vdi_t *out)
                 e = vdi::launch_convert_rgba(stage, static_cast<uint2 *>(v->d_rgba) + off, n, d->rgba_fmt_store, 0);
             if (e == hipSuccess) e = hipDeviceSynchronize();
         }
-        hipFree(stage);
+        const hipError_t ef = hipFree(stage);
+        if (e == hipSuccess) e = ef;
         if (e != hipSuccess) return bail(e, "colour conversion");
     }
     D.count = v->d_count;
@@ -443,8 +449,8 @@ int vdi_destroy(vdi_t v)
 {
     g_err.clear();
     if (!v) return VDI_OK;
-    hipSetDevice(v->device);
-    hipError_t e = hipDeviceSynchronize();
+    hipError_t e = hipSetDevice(v->device);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
     free_vdi(v);
     if (e != hipSuccess) return hip_fail(e, "synchronize before destroy");
     return VDI_OK;

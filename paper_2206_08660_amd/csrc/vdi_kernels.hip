@@ -35,13 +35,37 @@ constexpr int kXcds = 8;
 
 VDI_HD inline double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
-// Tile of this workgroup: blocks are dealt to XCDs round-robin, so give XCD x
-// the x-th contiguous range of tiles.
-__device__ __forceinline__ int xcd_tile(int bid, int nblocks)
+// Tile of workgroup `bid`.  Workgroups are dealt to the 8 XCDs round-robin
+// and each XCD has its own L2.  Tile rows are grouped into bands of kBandRows;
+// band b belongs to XCD b % 8, so each XCD renders whole bands (horizontal
+// neighbours, whose rays cross the same V_O lists, share an L2) while the
+// bands of every XCD are spread over the image (the work is balanced).
+// The map is a bijection from [0, tiles_x * tiles_y) onto itself.
+constexpr int kBandRows = 2;
+
+VDI_HD inline int xcd_tile(int bid, int tiles_x, int tiles_y)
 {
+    const int total = tiles_x * tiles_y;
     const int x = bid % kXcds, k = bid / kXcds;
-    const int q = nblocks / kXcds, r = nblocks % kXcds;
-    return x * q + min(x, r) + k;
+    // Position of this block in the XCD-major order of all blocks.
+    const int pos = x * (total / kXcds) + min(x, total % kXcds) + k;
+    // Bands in XCD-group order: group g holds bands g, g + 8, g + 16, ...
+    const int nb = (tiles_y + kBandRows - 1) / kBandRows;
+    const int last_rows = tiles_y - (nb - 1) * kBandRows;
+    const int band_tiles = kBandRows * tiles_x;
+    int start = 0;
+    for (int g = 0; g < kXcds; ++g) {
+        const int nbg = g < nb ? (nb - 1 - g) / kXcds + 1 : 0;
+        int size = nbg * band_tiles;
+        if (nbg > 0 && (nb - 1) % kXcds == g) size -= (kBandRows - last_rows) * tiles_x;
+        if (pos < start + size) {
+            const int local = pos - start;
+            const int b = g + kXcds * (local / band_tiles);
+            return b * band_tiles + local % band_tiles;
+        }
+        start += size;
+    }
+    return pos;  // not reached
 }
 
 // ---------------------------------------------------------------------------
@@ -255,76 +279,198 @@ struct Counters {
     int32_t lists, pieces;
 };
 
-// Composite the part of list li between depths za (entry) and zb (exit) of
-// a ray with dz/dt = Zp.  p is the seed index, updated on return.  Returns
-// true once the ray has terminated.
-template <int FMT, int SEARCH, bool COUNT>
-VDI_HD bool do_list(const DevVDI &V, const Frame &F, int ix, int iy, double ta, double tb, double Z0, double Zp,
-                        Accum &A, int &p, Counters &cnt)
+// One list segment of a ray: list (ix, iy) over [ta, tb], with the values
+// fetched for it one step ahead of its processing: the list's count and the
+// depth pairs of the seed slot ps and its neighbour towards the ray's entry.
+struct Seg {
+    int ix, iy;
+    double ta, tb;
+    int n, ps;
+    float2 dp, dq;
+};
+
+VDI_HD inline float2 depth_at(const DevVDI &V, int j, uint64_t li) { return V.depth[(uint64_t)j * V.plane + li]; }
+
+// Issue the loads a segment needs first.  Slots at or beyond the count are
+// in bounds (every list has N_S slots) and are never used.
+template <int SEARCH>
+VDI_HD inline void prefetch(const DevVDI &V, Seg &s, int p, int dir)
 {
-    const uint64_t li = (uint64_t)iy * V.WO + ix;
+    const uint64_t li = (uint64_t)s.iy * V.WO + s.ix;
+    s.n = V.count[li];
+    s.ps = -1;
+    if constexpr (SEARCH == VDI_SEARCH_SEEDED) {
+        if (p >= 0 && p < V.NS) {
+            s.ps = p;
+            s.dp = depth_at(V, p, li);
+            const int q = p - dir;
+            s.dq = (q >= 0 && q < V.NS) ? depth_at(V, q, li) : make_float2(0.0f, 0.0f);
+        }
+    }
+}
+
+// Composite segment s of a ray with dz/dt = Zp (Sections 4.2, Eq. 2).  The
+// first supersegment is found by the configured search (seeded by p, the
+// index used in the previous list, supplement Alg. S2), the next ones by
+// adjacency.  Long segments fetch four supersegments per round trip; short
+// ones overlap each supersegment's colour load with the next depth load.
+// p is updated; returns true once the ray has terminated.
+template <int FMT, int SEARCH, bool COUNT>
+VDI_HD bool do_seg(const DevVDI &V, const Frame &F, const Seg &s, double Z0, double Zp, double ray_len, Accum &A,
+                   int &p, Counters &cnt)
+{
+    const uint64_t li = (uint64_t)s.iy * V.WO + s.ix;
     if constexpr (COUNT) {
         F.touched_lists[li] = 1;
         ++cnt.lists;
     }
-    const int n = V.count[li];
+    const int n = s.n;
     if (n == 0) return false;
-    const double za = Z0 + ta * Zp, zb = Z0 + tb * Zp;
-    const float cth = list_cos(V, ix, iy);
+    const double za = Z0 + s.ta * Zp, zb = Z0 + s.tb * Zp;
+    const float cth = list_cos(V, s.ix, s.iy);
     const float2 *__restrict__ dep = V.depth;
     const uint64_t plane = V.plane;
+    const double inf = __builtin_huge_val();
+    auto piece = [&](int j, float2 d, float4 c, double zl, double zh, double inv) -> bool {
+        composite(A, c, (float)((zh - zl) * inv) * cth / (d.y - d.x));
+        if constexpr (COUNT) {
+            F.touched_slots[(uint64_t)j * plane + li] = 1;
+            ++cnt.pieces;
+        }
+        return A.T <= kTTerm;
+    };
+    // Expected supersegments in this segment: the list's count times the
+    // segment's share of the ray.
+    const bool batch = (double)n * (s.tb - s.ta) >= 3.0 * ray_len;
     if (Zp > kFlatZ) {
         const double inv = 1.0 / Zp;
-        int j = first_back_above<SEARCH>(dep, plane, li, n, za, p);
-        int last = -1;
-        for (; j < n; ++j) {
-            const float2 fb = dep[(uint64_t)j * plane + li];
-            const double f = fb.x, b = fb.y;
-            if (f >= zb) break;
-            const double zl = fmax(za, f), zh = fmin(zb, b);
-            if (zh > zl) {
-                const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * plane + li);
-                composite(A, c, (float)((zh - zl) * inv) * cth / (fb.y - fb.x));
-                last = j;
-                if constexpr (COUNT) {
-                    F.touched_slots[(uint64_t)j * plane + li] = 1;
-                    ++cnt.pieces;
+        int j;
+        bool have = false;
+        float2 d = make_float2(0.0f, 0.0f);
+        if (SEARCH == VDI_SEARCH_SEEDED && p >= 0 && p < n) {
+            const float2 dp = s.ps == p ? s.dp : depth_at(V, p, li);
+            const float b0 = p > 0 ? (s.ps == p ? s.dq.y : depth_at(V, p - 1, li).y) : -__builtin_huge_valf();
+            if ((double)b0 > za) {
+                j = first_back_above<VDI_SEARCH_BINARY>(dep, plane, li, p - 1, za, -1);
+                if (j == p - 1) {
+                    d = s.ps == p ? s.dq : depth_at(V, p - 1, li);
+                    have = true;
                 }
-                if (A.T <= kTTerm) return true;
+            } else if ((double)dp.y > za) {
+                j = p;
+                d = dp;
+                have = true;
+            } else {
+                j = p + 1 + first_back_above<VDI_SEARCH_BINARY>(dep, plane, li + (uint64_t)(p + 1) * plane, n - p - 1,
+                                                                 za, -1);
             }
-            if (b >= zb) break;
+        } else {
+            j = first_back_above<SEARCH>(dep, plane, li, n, za, -1);
+        }
+        int last = -1;
+        if (batch) {
+            while (j < n) {
+                float2 dd[4];
+                float4 cc[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int jj = min(j + u, n - 1);
+                    dd[u] = dep[(uint64_t)jj * plane + li];
+                    cc[u] = load_rgba<FMT>(V.rgba, (uint64_t)jj * plane + li);
+                }
+                bool stop = false;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (!stop) {
+                        if (j + u >= n || (double)dd[u].x >= zb) {
+                            stop = true;
+                        } else {
+                            const double zl = fmax(za, (double)dd[u].x), zh = fmin(zb, (double)dd[u].y);
+                            if (zh > zl) {
+                                last = j + u;
+                                if (piece(j + u, dd[u], cc[u], zl, zh, inv)) {
+                                    p = last;
+                                    return true;
+                                }
+                            }
+                            if ((double)dd[u].y >= zb) stop = true;
+                        }
+                    }
+                }
+                if (stop) break;
+                j += 4;
+            }
+        } else {
+            if (j < n && !have) d = depth_at(V, j, li);
+            while (j < n) {
+                if ((double)d.x >= zb) break;
+                const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * plane + li);
+                const bool more = (double)d.y < zb && j + 1 < n;
+                const float2 dn = more ? depth_at(V, j + 1, li) : d;
+                const double zl = fmax(za, (double)d.x), zh = fmin(zb, (double)d.y);
+                if (zh > zl) {
+                    last = j;
+                    if (piece(j, d, c, zl, zh, inv)) {
+                        p = last;
+                        return true;
+                    }
+                }
+                if (!more) break;
+                d = dn;
+                ++j;
+            }
         }
         p = last >= 0 ? last : min(j, n - 1);
     } else if (Zp < -kFlatZ) {
+        // Travelling towards smaller depth: mirror image of the above.
         const double inv = -1.0 / Zp;
-        int j = last_front_below<SEARCH>(dep, plane, li, n, za, p);
-        int last = -1;
-        for (; j >= 0; --j) {
-            const float2 fb = dep[(uint64_t)j * plane + li];
-            const double f = fb.x, b = fb.y;
-            if (b <= zb) break;
-            const double zl = fmax(zb, f), zh = fmin(za, b);
-            if (zh > zl) {
-                const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * plane + li);
-                composite(A, c, (float)((zh - zl) * inv) * cth / (fb.y - fb.x));
-                last = j;
-                if constexpr (COUNT) {
-                    F.touched_slots[(uint64_t)j * plane + li] = 1;
-                    ++cnt.pieces;
-                }
-                if (A.T <= kTTerm) return true;
+        int j;
+        bool have = false;
+        float2 d = make_float2(0.0f, 0.0f);
+        if (SEARCH == VDI_SEARCH_SEEDED && p >= 0 && p < n) {
+            const float2 dp = s.ps == p ? s.dp : depth_at(V, p, li);
+            const float f2 = p + 1 < n ? (s.ps == p ? s.dq.x : depth_at(V, p + 1, li).x) : __builtin_huge_valf();
+            if ((double)dp.x >= za) {
+                j = last_front_below<VDI_SEARCH_BINARY>(dep, plane, li, p, za, -1);
+            } else if ((double)f2 >= za) {
+                j = p;
+                d = dp;
+                have = true;
+            } else {
+                j = p + 2 + last_front_below<VDI_SEARCH_BINARY>(dep, plane, li + (uint64_t)(p + 2) * plane, n - p - 2,
+                                                                 za, -1);
             }
-            if (f <= zb) break;
+        } else {
+            j = last_front_below<SEARCH>(dep, plane, li, n, za, -1);
+        }
+        int last = -1;
+        if (j >= 0 && !have) d = depth_at(V, j, li);
+        while (j >= 0) {
+            if ((double)d.y <= zb) break;
+            const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * plane + li);
+            const bool more = (double)d.x > zb && j > 0;
+            const float2 dn = more ? depth_at(V, j - 1, li) : d;
+            const double zl = fmax(zb, (double)d.x), zh = fmin(za, (double)d.y);
+            if (zh > zl) {
+                last = j;
+                if (piece(j, d, c, zl, zh, inv)) {
+                    p = last;
+                    return true;
+                }
+            }
+            if (!more) break;
+            d = dn;
+            --j;
         }
         p = last >= 0 ? last : max(j, 0);
     } else {
-        // Constant depth: the supersegment holding za covers the whole piece.
+        // Constant depth: the supersegment holding za covers the whole segment.
         for (int j = 0; j < n; ++j) {
-            const float2 fb = dep[(uint64_t)j * plane + li];
-            if ((double)fb.x <= za && za < (double)fb.y) {
+            const float2 d = depth_at(V, j, li);
+            if ((double)d.x <= za && za < (double)d.y) {
                 const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * plane + li);
-                composite(A, c, (float)(tb - ta) * cth / (fb.y - fb.x));
                 p = j;
+                composite(A, c, (float)(s.tb - s.ta) * cth / (d.y - d.x));
                 if constexpr (COUNT) {
                     F.touched_slots[(uint64_t)j * plane + li] = 1;
                     ++cnt.pieces;
@@ -332,6 +478,7 @@ VDI_HD bool do_list(const DevVDI &V, const Frame &F, int ix, int iy, double ta, 
                 return A.T <= kTTerm;
             }
         }
+        (void)inf;
     }
     return false;
 }
@@ -339,78 +486,120 @@ VDI_HD bool do_list(const DevVDI &V, const Frame &F, int ix, int iy, double ta, 
 // ---------------------------------------------------------------------------
 // Exact render (Sections 4.1-4.3)
 // ---------------------------------------------------------------------------
-// One exact ray through V_N pixel (px, py); gz = slice boundaries (LDS copy).
+// One exact ray through V_N pixel (px, py); s_gz = slice boundaries (LDS copy).
+// A walker steps through the list grid (voxel stepping in V_O NDC, Section
+// 4.1), skipping grid cells with count 0 when ESS is on (Section 4.3); each
+// segment it produces is prefetched one step before it is composited.
 template <int FMT, int SEARCH, bool ESS, bool COUNT>
 VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, int px, int py, Counters &cnt)
 {
     Accum A = {0.0f, 0.0f, 0.0f, 1.0f};
     Ray r;
     const double xc = -1.0 + (2.0 * px + 1.0) / F.W, yc = -1.0 + (2.0 * py + 1.0) / F.H;
-    if (ray_setup(F, xc, yc, r)) {
-        const int WO = V.WO, HO = V.HO;
-        // Direction of travel across the list grid: d/dt (X/Z) has the sign of Kx.
-        const double Kx = r.Xp * F.Z0 - F.X0 * r.Zp, Ky = r.Yp * F.Z0 - F.Y0 * r.Zp;
-        const int sx = (Kx > 0.0) - (Kx < 0.0), sy = (Ky > 0.0) - (Ky < 0.0);
-        const double inf = __builtin_huge_val();
-        double t = r.t0;
-        int ix, iy, mx, my;
-        double tx, ty;
-        auto locate = [&](double tt) {
-            const double z = F.Z0 + tt * r.Zp;
-            ix = cell_of((F.X0 + tt * r.Xp) / z, WO, sx);
-            iy = cell_of((F.Y0 + tt * r.Yp) / z, HO, sy);
-            mx = sx > 0 ? ix + 1 : ix;
-            my = sy > 0 ? iy + 1 : iy;
-            tx = (sx != 0 && mx > 0 && mx < WO) ? line_t(mx, WO, F.X0, r.Xp, F.Z0, r.Zp) : inf;
-            ty = (sy != 0 && my > 0 && my < HO) ? line_t(my, HO, F.Y0, r.Yp, F.Z0, r.Zp) : inf;
-        };
-        locate(t);
-        int p = -1;
-        // Every iteration moves one list or jumps a grid cell; the cap only
-        // guards against a non-advancing loop.
-        const int max_iter = 4 * (WO + HO) + 4 * V.gnz + 64;
-        for (int it = 0; it < max_iter; ++it) {
-            double tn = fmin(fmin(tx, ty), r.t1);
+    if (!ray_setup(F, xc, yc, r)) return make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const int WO = V.WO, HO = V.HO, gk = V.gk;
+    // Direction of travel across the list grid: d/dt (X/Z) has the sign of Kx.
+    const double Kx = r.Xp * F.Z0 - F.X0 * r.Zp, Ky = r.Yp * F.Z0 - F.Y0 * r.Zp;
+    const int sx = (Kx > 0.0) - (Kx < 0.0), sy = (Ky > 0.0) - (Ky < 0.0);
+    const bool fwd = r.Zp >= 0.0, flat = fabs(r.Zp) < kFlatZ;
+    const int dir = r.Zp < 0.0 ? -1 : 1;
+    const double inf = __builtin_huge_val();
+    double t = r.t0, tx = inf, ty = inf, tz = inf;
+    int ix = 0, iy = 0, mx = 0, my = 0, cz = 0;
+    int ccx = -1, ccy = -1, ccz = -1;
+    uint32_t cg = 0;
+    bool dead = false;
+    auto slice_t = [&](int c) -> double {
+        if (flat) return inf;
+        if (fwd) return c + 1 < V.gnz ? ((double)s_gz[c + 1] - F.Z0) / r.Zp : inf;
+        return c > 0 ? ((double)s_gz[c] - F.Z0) / r.Zp : inf;
+    };
+    auto locate = [&](double tt) {
+        const double z = F.Z0 + tt * r.Zp;
+        ix = cell_of((F.X0 + tt * r.Xp) / z, WO, sx);
+        iy = cell_of((F.Y0 + tt * r.Yp) / z, HO, sy);
+        mx = sx > 0 ? ix + 1 : ix;
+        my = sy > 0 ? iy + 1 : iy;
+        tx = (sx != 0 && mx > 0 && mx < WO) ? line_t(mx, WO, F.X0, r.Xp, F.Z0, r.Zp) : inf;
+        ty = (sy != 0 && my > 0 && my < HO) ? line_t(my, HO, F.Y0, r.Yp, F.Z0, r.Zp) : inf;
+        if constexpr (ESS) {
+            cz = slice_of(s_gz, V.gnz, z, fwd);
+            tz = slice_t(cz);
+        }
+    };
+    // Every call moves at least one list or grid cell, or ends the ray; the
+    // budget only guards against a loop that does not advance.
+    int budget = 4 * (WO + HO) + 4 * V.gnz + 64;
+    auto next_seg = [&](Seg &s) -> bool {
+        while (budget-- > 0) {
+            if (dead || t >= r.t1) return false;
             if constexpr (ESS) {
-                // Empty-space skipping (Section 4.3): a cell with count 0 is
-                // crossed in one step, to the nearest of its faces.
-                const int cx = ix / V.gk, cy = iy / V.gk;
-                const bool fwd = r.Zp >= 0.0;
-                const int cz = slice_of(s_gz, V.gnz, F.Z0 + t * r.Zp, fwd);
-                if (V.grid[((uint64_t)cz * V.GH + cy) * V.GW + cx] == 0u) {
-                    double te = r.t1;
+                while (tz <= t) {
+                    cz += dir;
+                    tz = slice_t(cz);
+                }
+                const int cx = ix / gk, cy = iy / gk;
+                if (cx != ccx || cy != ccy || cz != ccz) {
+                    cg = V.grid[((uint64_t)cz * V.GH + cy) * V.GW + cx];
+                    ccx = cx;
+                    ccy = cy;
+                    ccz = cz;
+                }
+                if (cg == 0u) {
+                    // Empty-space skipping: cross the empty cell in one step.
+                    double te = fmin(tz, r.t1);
                     if (sx != 0) {
-                        const int m = sx > 0 ? min((cx + 1) * V.gk, WO) : cx * V.gk;
+                        const int m = sx > 0 ? min((cx + 1) * gk, WO) : cx * gk;
                         if (m > 0 && m < WO) te = fmin(te, line_t(m, WO, F.X0, r.Xp, F.Z0, r.Zp));
                     }
                     if (sy != 0) {
-                        const int m = sy > 0 ? min((cy + 1) * V.gk, HO) : cy * V.gk;
+                        const int m = sy > 0 ? min((cy + 1) * gk, HO) : cy * gk;
                         if (m > 0 && m < HO) te = fmin(te, line_t(m, HO, F.Y0, r.Yp, F.Z0, r.Zp));
                     }
-                    if (r.Zp > kFlatZ && cz + 1 < V.gnz) te = fmin(te, ((double)s_gz[cz + 1] - F.Z0) / r.Zp);
-                    if (r.Zp < -kFlatZ && cz > 0) te = fmin(te, ((double)s_gz[cz] - F.Z0) / r.Zp);
                     if (te > t) {
                         t = te;
-                        if (t >= r.t1) break;
+                        if (t >= r.t1) return false;
                         locate(t);
                         continue;
                     }
                 }
             }
-            if (tn > t && do_list<FMT, SEARCH, COUNT>(V, F, ix, iy, t, tn, F.Z0, r.Zp, A, p, cnt)) break;
-            if (tn >= r.t1) break;
-            if (tx <= ty) {
-                ix += sx;
-                mx += sx;
-                tx = (mx > 0 && mx < WO) ? line_t(mx, WO, F.X0, r.Xp, F.Z0, r.Zp) : inf;
+            const double tn = fmin(fmin(tx, ty), r.t1);
+            s.ix = ix;
+            s.iy = iy;
+            s.ta = t;
+            s.tb = tn;
+            if (tn >= r.t1) {
+                t = r.t1;
             } else {
-                iy += sy;
-                my += sy;
-                ty = (my > 0 && my < HO) ? line_t(my, HO, F.Y0, r.Yp, F.Z0, r.Zp) : inf;
+                if (tx <= ty) {
+                    ix += sx;
+                    mx += sx;
+                    tx = (mx > 0 && mx < WO) ? line_t(mx, WO, F.X0, r.Xp, F.Z0, r.Zp) : inf;
+                } else {
+                    iy += sy;
+                    my += sy;
+                    ty = (my > 0 && my < HO) ? line_t(my, HO, F.Y0, r.Yp, F.Z0, r.Zp) : inf;
+                }
+                t = fmax(t, tn);
+                if ((unsigned)ix >= (unsigned)WO || (unsigned)iy >= (unsigned)HO) dead = true;
             }
-            t = fmax(t, tn);
-            if ((unsigned)ix >= (unsigned)WO || (unsigned)iy >= (unsigned)HO) break;
+            if (s.tb > s.ta) return true;
         }
+        return false;
+    };
+    locate(t);
+    const double ray_len = r.t1 - r.t0;
+    int p = -1;
+    Seg cur, nxt;
+    bool have = next_seg(cur);
+    if (have) prefetch<SEARCH>(V, cur, p, dir);
+    while (have) {
+        const bool have_n = next_seg(nxt);
+        if (have_n) prefetch<SEARCH>(V, nxt, p, dir);
+        if (do_seg<FMT, SEARCH, COUNT>(V, F, cur, F.Z0, r.Zp, ray_len, A, p, cnt)) break;
+        cur = nxt;
+        have = have_n;
     }
     return make_float4(A.r, A.g, A.b, 1.0f - A.T);
 }
@@ -424,7 +613,7 @@ __global__ __launch_bounds__(kBlock) void k_render_exact(DevVDI V, Frame F)
         __syncthreads();
     }
     const int tiles_x = (F.W + kTileW - 1) / kTileW, tiles_y = (F.H + kTileH - 1) / kTileH;
-    const int tile = xcd_tile(blockIdx.x, tiles_x * tiles_y);
+    const int tile = xcd_tile(blockIdx.x, tiles_x, tiles_y);
     const int px = (tile % tiles_x) * kTileW + (threadIdx.x % kTileW);
     const int py = (tile / tiles_x) * kTileH + (threadIdx.x / kTileW);
     if (px >= F.W || py >= F.H) return;
@@ -545,7 +734,7 @@ __global__ __launch_bounds__(kBlock) void k_render_preview(DevVDI V, Frame F)
     for (int i = threadIdx.x; i <= V.gnz; i += kBlock) s_gz[i] = V.gz[i];
     __syncthreads();
     const int tiles_x = (F.W + kTileW - 1) / kTileW, tiles_y = (F.H + kTileH - 1) / kTileH;
-    const int tile = xcd_tile(blockIdx.x, tiles_x * tiles_y);
+    const int tile = xcd_tile(blockIdx.x, tiles_x, tiles_y);
     const int px = (tile % tiles_x) * kTileW + (threadIdx.x % kTileW);
     const int py = (tile / tiles_x) * kTileH + (threadIdx.x / kTileW);
     if (px >= F.W || py >= F.H) return;

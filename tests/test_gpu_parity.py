@@ -100,11 +100,14 @@ def test_random_vdi_exact(seed, theta):
     say(f"[gpu] random VDI seed={seed} theta={theta}")
     v = synth.random_vdi(40, 24, 7, seed=seed)
     cam = inputs.orbit_camera(theta)
-    ref = oracle.render_exact(v, cam, 70, 45)
+    # Even image sizes: with odd ones, the centre column/row of a view whose
+    # eye lies on V_O's axis (theta = 180) runs exactly along a list edge, a
+    # tie the exact result does not decide.
+    ref = oracle.render_exact(v, cam, 70, 44)
     with V.Vdi(v, validate=True) as h:
         for ess in (True, False):
             for search in ("seeded", "binary", "linear"):
-                img = gpu_render(h, cam, 70, 45, ess=ess, search=search)
+                img = gpu_render(h, cam, 70, 44, ess=ess, search=search)
                 assert np.abs(img - ref).max() <= TOL, (ess, search)
 
 
