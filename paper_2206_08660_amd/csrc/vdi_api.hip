@@ -14,18 +14,6 @@
 
 #include "vdi_internal.h"
 
-struct vdi_s {
-    vdi::DevVDI dev;
-    vdi_camera cam_o;
-    float bmin[3], bmax[3];
-    int device;
-    uint8_t *d_count = nullptr;
-    float2 *d_depth = nullptr;
-    void *d_rgba = nullptr;
-    uint32_t *d_grid = nullptr;
-    float *d_gz = nullptr;
-    uint64_t device_bytes = 0, supersegments = 0;
-};
 
 namespace {
 
@@ -96,7 +84,7 @@ int make_basis(const vdi_camera &c, Basis &b)
 double dot(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
 // Frame constants for rays on a w x h grid with aspect `aspect`.
-int make_frame(const vdi_s *v, const vdi_camera &cam, int w, int h, double aspect, vdi::Frame &f)
+int build_frame(const vdi_s *v, const vdi_camera &cam, int w, int h, double aspect, vdi::Frame &f)
 {
     Basis o, n;
     int rc = make_basis(v->cam_o, o);
@@ -145,14 +133,14 @@ int check_opts(const vdi_render_opts *opts, vdi::Frame &f)
     return VDI_OK;
 }
 
-int lowres(int32_t W, int32_t H, float D_I, int32_t *w, int32_t *h)
+int lowres_dims(int32_t W, int32_t H, float D_I, int32_t *w, int32_t *h)
 {
     *w = std::max(1, (int32_t)floor((double)W / (double)D_I + 0.5));
     *h = std::max(1, (int32_t)floor((double)H / (double)D_I + 0.5));
     return VDI_OK;
 }
 
-int check_render_args(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, float D_I, float D_R, const float *out)
+int check_args(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, float D_I, float D_R, const float *out)
 {
     if (!v) return fail(VDI_ERR_ARG, "null VDI handle");
     if (!cam) return fail(VDI_ERR_ARG, "null camera");
@@ -168,12 +156,12 @@ int check_render_args(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, floa
 int render_impl(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, float D_I, float D_R,
                 const vdi_render_opts *opts, float *out, hipStream_t s)
 {
-    int rc = check_render_args(v, cam, W, H, D_I, D_R, out);
+    int rc = check_args(v, cam, W, H, D_I, D_R, out);
     if (rc) return rc;
     int32_t w, h;
-    lowres(W, H, D_I, &w, &h);
+    lowres_dims(W, H, D_I, &w, &h);
     vdi::Frame f;
-    rc = make_frame(v, *cam, w, h, (double)W / (double)H, f);
+    rc = build_frame(v, *cam, w, h, (double)W / (double)H, f);
     if (rc) return rc;
     rc = check_opts(opts, f);
     if (rc) return rc;
@@ -235,6 +223,29 @@ void free_vdi(vdi_s *v)
 
 }  // namespace
 
+namespace vdi {
+int set_error(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+int hip_error(hipError_t e, const char *what) { return hip_fail(e, what); }
+int check_render_args(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, float D_I, float D_R, const float *out)
+{
+    return ::check_args(v, cam, W, H, D_I, D_R, out);
+}
+void lowres_size(int32_t W, int32_t H, float D_I, int32_t *w, int32_t *h) { ::lowres_dims(W, H, D_I, w, h); }
+int make_frame(const vdi_s *v, const vdi_camera &cam, int w, int h, double aspect, Frame &f)
+{
+    return ::build_frame(v, cam, w, h, aspect, f);
+}
+}  // namespace vdi
+
 extern "C" {
 
 const char *vdi_last_error(void) { return g_err.c_str(); }
@@ -251,7 +262,7 @@ int vdi_lowres_size(int32_t width, int32_t height, float D_I, int32_t *w, int32_
 {
     if (!w || !h) return fail(VDI_ERR_ARG, "null output");
     if (width < 1 || height < 1 || !isfinite(D_I) || D_I < 1.0f) return fail(VDI_ERR_ARG, "invalid size or D_I");
-    return lowres(width, height, D_I, w, h);
+    return lowres_dims(width, height, D_I, w, h);
 }
 
 int vdi_create(const vdi_desc *d, vdi_t *out)
@@ -400,11 +411,11 @@ int vdi_render_counters(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, co
                         float *out, uint8_t *touched_lists, uint8_t *touched_slots, int32_t *ray_stats, void *stream)
 {
     g_err.clear();
-    int rc = check_render_args(v, cam, W, H, 1.0f, 0.0f, out);
+    int rc = check_args(v, cam, W, H, 1.0f, 0.0f, out);
     if (rc) return rc;
     if (!touched_lists || !touched_slots) return fail(VDI_ERR_ARG, "null counter buffer");
     vdi::Frame f;
-    rc = make_frame(v, *cam, W, H, (double)W / (double)H, f);
+    rc = build_frame(v, *cam, W, H, (double)W / (double)H, f);
     if (rc) return rc;
     rc = check_opts(opts, f);
     if (rc) return rc;

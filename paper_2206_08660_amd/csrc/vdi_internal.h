@@ -49,6 +49,34 @@ struct Frame {
     int32_t *ray_stats;
 };
 
+}  // namespace vdi
+
+// A resident VDI (the object behind vdi_t).
+struct vdi_s {
+    vdi::DevVDI dev;
+    vdi_camera cam_o;
+    float bmin[3], bmax[3];
+    int device;
+    uint8_t *d_count = nullptr;
+    float2 *d_depth = nullptr;
+    void *d_rgba = nullptr;
+    uint32_t *d_grid = nullptr;
+    float *d_gz = nullptr;
+    uint64_t device_bytes = 0, supersegments = 0;
+};
+
+namespace vdi {
+
+// Host helpers shared by the render and serving entry points (vdi_api.hip).
+// Each returns VDI_OK or an error code after recording the reason.
+int set_error(int code, const char *fmt, ...);
+int hip_error(hipError_t e, const char *what);
+int check_render_args(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, float D_I, float D_R, const float *out);
+// Ray-grid size for downsampling factor D_I.
+void lowres_size(int32_t W, int32_t H, float D_I, int32_t *w, int32_t *h);
+// Frame constants for rays on a w x h grid of camera `cam` with aspect `aspect`.
+int make_frame(const vdi_s *v, const vdi_camera &cam, int w, int h, double aspect, Frame &f);
+
 // Launchers (vdi_kernels.hip).  All run on `stream` and return the launch status.
 hipError_t launch_render_exact(const DevVDI &v, const Frame &f, bool counters, hipStream_t stream);
 hipError_t launch_render_preview(const DevVDI &v, const Frame &f, hipStream_t stream);

@@ -1,0 +1,718 @@
+// Per-ray device code of libvdi, shared by the one-shot kernels
+// (vdi_kernels.hip) and the persistent serving kernel (vdi_serve.hip):
+// ray set-up and clipping, list-grid walking, first-supersegment search,
+// opacity correction and compositing, preview sampling.  Every function is
+// host-callable too, so a ray can be stepped through on the CPU.
+#pragma once
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "vdi_internal.h"
+
+namespace vdi {
+
+// Per-ray functions are host-callable too, so the traversal can be stepped
+// through on the CPU with the same code.
+#define VDI_HD __host__ __device__
+
+constexpr int kTileW = 64;
+constexpr int kTileH = 4;
+constexpr int kBlock = kTileW * kTileH;
+constexpr int kXcds = 8;
+
+VDI_HD inline double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+// Tile of workgroup `bid`.  Workgroups are dealt to the 8 XCDs round-robin
+// and each XCD has its own L2.  Tile rows are grouped into bands of kBandRows;
+// band b belongs to XCD b % 8, so each XCD renders whole bands (horizontal
+// neighbours, whose rays cross the same V_O lists, share an L2) while the
+// bands of every XCD are spread over the image (the work is balanced).
+// The map is a bijection from [0, tiles_x * tiles_y) onto itself.
+constexpr int kBandRows = 2;
+
+VDI_HD inline int xcd_tile(int bid, int tiles_x, int tiles_y)
+{
+    const int total = tiles_x * tiles_y;
+    const int x = bid % kXcds, k = bid / kXcds;
+    // Position of this block in the XCD-major order of all blocks.
+    const int pos = x * (total / kXcds) + min(x, total % kXcds) + k;
+    // Bands in XCD-group order: group g holds bands g, g + 8, g + 16, ...
+    const int nb = (tiles_y + kBandRows - 1) / kBandRows;
+    const int last_rows = tiles_y - (nb - 1) * kBandRows;
+    const int band_tiles = kBandRows * tiles_x;
+    int start = 0;
+    for (int g = 0; g < kXcds; ++g) {
+        const int nbg = g < nb ? (nb - 1 - g) / kXcds + 1 : 0;
+        int size = nbg * band_tiles;
+        if (nbg > 0 && (nb - 1) % kXcds == g) size -= (kBandRows - last_rows) * tiles_x;
+        if (pos < start + size) {
+            const int local = pos - start;
+            const int b = g + kXcds * (local / band_tiles);
+            return b * band_tiles + local % band_tiles;
+        }
+        start += size;
+    }
+    return pos;  // not reached
+}
+
+// ---------------------------------------------------------------------------
+// Colour planes
+// ---------------------------------------------------------------------------
+template <int FMT>
+VDI_HD inline float4 load_rgba(const void *base, uint64_t idx)
+{
+    if constexpr (FMT == VDI_F32) {
+        return reinterpret_cast<const float4 *>(base)[idx];
+    } else {
+        const uint2 u = reinterpret_cast<const uint2 *>(base)[idx];
+        if constexpr (FMT == VDI_F16) {
+            const __half2 rg = *reinterpret_cast<const __half2 *>(&u.x);
+            const __half2 ba = *reinterpret_cast<const __half2 *>(&u.y);
+            const float2 a = __half22float2(rg), b = __half22float2(ba);
+            return make_float4(a.x, a.y, b.x, b.y);
+        } else {
+            return make_float4(__builtin_bit_cast(float, u.x << 16), __builtin_bit_cast(float, u.x & 0xffff0000u),
+                               __builtin_bit_cast(float, u.y << 16), __builtin_bit_cast(float, u.y & 0xffff0000u));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Rays
+// ---------------------------------------------------------------------------
+struct Ray {
+    double Xp, Yp, Zp;  // d/dt of (X, Y, Z) in V_O's frame; Z is V_O view depth
+    double t0, t1;      // clipped parameter range (world distance from eye_N)
+};
+
+// Keep t with a + b t >= 0.
+VDI_HD inline bool clip(double a, double b, double &lo, double &hi)
+{
+    if (b == 0.0) return a >= 0.0;
+    const double t = -a / b;
+    if (b > 0.0)
+        lo = fmax(lo, t);
+    else
+        hi = fmin(hi, t);
+    return true;
+}
+
+// Ray through NDC (xc, yc) of V_N, clipped to V_N's near plane, the AABB and
+// V_O's frustum (Section 4.1: marching starts and ends where the ray meets
+// the generating viewport and the volume's bounding box).
+VDI_HD inline bool ray_setup(const Frame &F, double xc, double yc, Ray &r)
+{
+    double d[3];
+    for (int a = 0; a < 3; ++a) d[a] = F.FN[a] + xc * F.tx_n * F.RN[a] + yc * F.ty_n * F.UN[a];
+    const double inv = 1.0 / sqrt(dot3(d, d));
+    for (int a = 0; a < 3; ++a) d[a] *= inv;
+    r.Xp = dot3(F.RO, d) * F.sx_o;
+    r.Yp = dot3(F.UO, d) * F.sy_o;
+    r.Zp = dot3(F.FO, d);
+    double lo = 0.0, hi = __builtin_huge_val();
+    bool ok = clip(-F.near_n, dot3(F.FN, d), lo, hi);
+    for (int a = 0; a < 3; ++a) {
+        ok = ok && clip(F.eyeN[a] - F.bmin[a], d[a], lo, hi);
+        ok = ok && clip(F.bmax[a] - F.eyeN[a], -d[a], lo, hi);
+    }
+    ok = ok && clip(F.Z0 - F.near_o, r.Zp, lo, hi);
+    ok = ok && clip(F.Z0 - F.X0, r.Zp - r.Xp, lo, hi);
+    ok = ok && clip(F.Z0 + F.X0, r.Zp + r.Xp, lo, hi);
+    ok = ok && clip(F.Z0 - F.Y0, r.Zp - r.Yp, lo, hi);
+    ok = ok && clip(F.Z0 + F.Y0, r.Zp + r.Yp, lo, hi);
+    r.t0 = lo;
+    r.t1 = hi;
+    return ok && hi > lo;
+}
+
+// Parameter where the ray meets NDC line coord = -1 + 2 m / n (P = X or Y),
+// or +inf if it never does.  coord(t) = P(t) / Z(t) is monotone where Z > 0
+// but its asymptote is the ray's vanishing point: a line beyond it has its
+// only root on the branch behind V_O (Z < 0), which is not a crossing.
+VDI_HD inline double line_t(int m, int n, double P0, double Pp, double Z0, double Zp)
+{
+    const double c = -1.0 + 2.0 * m / n;
+    const double den = Pp - c * Zp;
+    const double t = (c * Z0 - P0) / den;
+    return (den != 0.0 && Z0 + t * Zp > 0.0) ? t : __builtin_huge_val();
+}
+
+// Cell index of an NDC coordinate; a point exactly on a line belongs to the
+// cell the ray is moving into.
+VDI_HD inline int cell_of(double ndc, int n, int dir)
+{
+    const double f = (ndc + 1.0) * n / 2.0;
+    const double fl = floor(f);
+    int i = (int)fl;
+    if (f == fl && dir < 0) i -= 1;
+    return min(max(i, 0), n - 1);
+}
+
+// cos of the angle between list (ix, iy)'s generating ray and V_O's axis.
+VDI_HD inline float list_cos(const DevVDI &V, int ix, int iy)
+{
+    const float x = (-1.0f + (2.0f * ix + 1.0f) / V.WO) * V.tx_o;
+    const float y = (-1.0f + (2.0f * iy + 1.0f) / V.HO) * V.ty_o;
+    return 1.0f / sqrtf(1.0f + x * x + y * y);
+}
+
+// Depth slice holding depth z for a ray moving towards larger (fwd) or smaller z.
+VDI_HD inline int slice_of(const float *gz, int gnz, double z, bool fwd)
+{
+    int lo = 0, hi = gnz - 1;  // answer in [0, gnz-1]
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const double b = gz[mid];
+        if (fwd ? (b <= z) : (b < z))
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// First-supersegment search (Section 4.2, supplement Alg. S2)
+// ---------------------------------------------------------------------------
+// Smallest j in [0, n) with b_j > z (n if none).  Back depths increase with j
+// because supersegments are sorted and disjoint.
+template <int SEARCH>
+VDI_HD inline int first_back_above(const float2 *__restrict__ dep, uint64_t plane, uint64_t li, int n,
+                                                double z, int p)
+{
+    if constexpr (SEARCH == VDI_SEARCH_LINEAR) {
+        int j = 0;
+        while (j < n && (double)dep[(uint64_t)j * plane + li].y <= z) ++j;
+        return j;
+    }
+    int lo = 0, hi = n;
+    if constexpr (SEARCH == VDI_SEARCH_SEEDED) {
+        if (p >= 0 && p < n) {
+            // Both candidate back depths are fetched before either is compared.
+            const float b1 = dep[(uint64_t)p * plane + li].y;
+            const float b0 = p > 0 ? dep[(uint64_t)(p - 1) * plane + li].y : -__builtin_huge_valf();
+            if ((double)b0 > z)
+                hi = p - 1;  // the answer is at most p-1
+            else if ((double)b1 > z)
+                return p;    // the seed itself
+            else
+                lo = p + 1;
+        }
+    }
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((double)dep[(uint64_t)mid * plane + li].y > z)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
+// Largest j in [0, n) with f_j < z (-1 if none): the first supersegment met by
+// a ray travelling towards smaller depth.
+template <int SEARCH>
+VDI_HD inline int last_front_below(const float2 *__restrict__ dep, uint64_t plane, uint64_t li, int n,
+                                                double z, int p)
+{
+    if constexpr (SEARCH == VDI_SEARCH_LINEAR) {
+        int j = n - 1;
+        while (j >= 0 && (double)dep[(uint64_t)j * plane + li].x >= z) --j;
+        return j;
+    }
+    int lo = 0, hi = n;  // search the first j with f_j >= z
+    if constexpr (SEARCH == VDI_SEARCH_SEEDED) {
+        if (p >= 0 && p < n) {
+            const float f1 = dep[(uint64_t)p * plane + li].x;
+            const float f2 = p + 1 < n ? dep[(uint64_t)(p + 1) * plane + li].x : __builtin_huge_valf();
+            if ((double)f1 >= z)
+                hi = p;
+            else if ((double)f2 >= z)
+                return p;
+            else
+                lo = p + 2;
+        }
+    }
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((double)dep[(uint64_t)mid * plane + li].x >= z)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo - 1;
+}
+
+// ---------------------------------------------------------------------------
+// Compositing
+// ---------------------------------------------------------------------------
+struct Accum {
+    float r, g, b, T;
+};
+
+// Eq. 2 with exponent l = (world length in S) / (world length of the
+// generating ray in S), then front-to-back "over".
+VDI_HD inline void composite(Accum &A, float4 c, float l)
+{
+    const float at = c.w >= 1.0f ? 1.0f : 1.0f - exp2f(l * log2f(1.0f - c.w));
+    const float w = A.T * at;
+    A.r = fmaf(w, c.x, A.r);
+    A.g = fmaf(w, c.y, A.g);
+    A.b = fmaf(w, c.z, A.b);
+    A.T *= 1.0f - at;
+}
+
+struct Counters {
+    int32_t lists, pieces;
+};
+
+// One list segment of a ray: list (ix, iy) over [ta, tb], with the values
+// fetched for it one step ahead of its processing: the list's count and the
+// depth pairs of the seed slot ps and its neighbour towards the ray's entry.
+struct Seg {
+    int ix, iy;
+    double ta, tb;
+    int n, ps;
+    float2 dp, dq;
+};
+
+VDI_HD inline float2 depth_at(const DevVDI &V, int j, uint64_t li) { return V.depth[(uint64_t)j * V.plane + li]; }
+
+// Issue the loads a segment needs first.  Slots at or beyond the count are
+// in bounds (every list has N_S slots) and are never used.
+template <int SEARCH>
+VDI_HD inline void prefetch(const DevVDI &V, Seg &s, int p, int dir)
+{
+    const uint64_t li = (uint64_t)s.iy * V.WO + s.ix;
+    s.n = V.count[li];
+    s.ps = -1;
+    if constexpr (SEARCH == VDI_SEARCH_SEEDED) {
+        if (p >= 0 && p < V.NS) {
+            s.ps = p;
+            s.dp = depth_at(V, p, li);
+            const int q = p - dir;
+            s.dq = (q >= 0 && q < V.NS) ? depth_at(V, q, li) : make_float2(0.0f, 0.0f);
+        }
+    }
+}
+
+// Composite segment s of a ray with dz/dt = Zp (Sections 4.2, Eq. 2).  The
+// first supersegment is found by the configured search (seeded by p, the
+// index used in the previous list, supplement Alg. S2), the next ones by
+// adjacency.  Long segments fetch four supersegments per round trip; short
+// ones overlap each supersegment's colour load with the next depth load.
+// p is updated; returns true once the ray has terminated.
+template <int FMT, int SEARCH, bool COUNT>
+VDI_HD bool do_seg(const DevVDI &V, const Frame &F, const Seg &s, double Z0, double Zp, double ray_len, Accum &A,
+                   int &p, Counters &cnt)
+{
+    const uint64_t li = (uint64_t)s.iy * V.WO + s.ix;
+    if constexpr (COUNT) {
+        F.touched_lists[li] = 1;
+        ++cnt.lists;
+    }
+    const int n = s.n;
+    if (n == 0) return false;
+    const double za = Z0 + s.ta * Zp, zb = Z0 + s.tb * Zp;
+    const float cth = list_cos(V, s.ix, s.iy);
+    const float2 *__restrict__ dep = V.depth;
+    const uint64_t plane = V.plane;
+    const double inf = __builtin_huge_val();
+    auto piece = [&](int j, float2 d, float4 c, double zl, double zh, double inv) -> bool {
+        composite(A, c, (float)((zh - zl) * inv) * cth / (d.y - d.x));
+        if constexpr (COUNT) {
+            F.touched_slots[(uint64_t)j * plane + li] = 1;
+            ++cnt.pieces;
+        }
+        return A.T <= kTTerm;
+    };
+    // Expected supersegments in this segment: the list's count times the
+    // segment's share of the ray.
+    const bool batch = (double)n * (s.tb - s.ta) >= 3.0 * ray_len;
+    if (Zp > kFlatZ) {
+        const double inv = 1.0 / Zp;
+        int j;
+        bool have = false;
+        float2 d = make_float2(0.0f, 0.0f);
+        if (SEARCH == VDI_SEARCH_SEEDED && p >= 0 && p < n) {
+            const float2 dp = s.ps == p ? s.dp : depth_at(V, p, li);
+            const float b0 = p > 0 ? (s.ps == p ? s.dq.y : depth_at(V, p - 1, li).y) : -__builtin_huge_valf();
+            if ((double)b0 > za) {
+                j = first_back_above<VDI_SEARCH_BINARY>(dep, plane, li, p - 1, za, -1);
+                if (j == p - 1) {
+                    d = s.ps == p ? s.dq : depth_at(V, p - 1, li);
+                    have = true;
+                }
+            } else if ((double)dp.y > za) {
+                j = p;
+                d = dp;
+                have = true;
+            } else {
+                j = p + 1 + first_back_above<VDI_SEARCH_BINARY>(dep, plane, li + (uint64_t)(p + 1) * plane, n - p - 1,
+                                                                 za, -1);
+            }
+        } else {
+            j = first_back_above<SEARCH>(dep, plane, li, n, za, -1);
+        }
+        int last = -1;
+        if (batch) {
+            while (j < n) {
+                float2 dd[4];
+                float4 cc[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int jj = min(j + u, n - 1);
+                    dd[u] = dep[(uint64_t)jj * plane + li];
+                    cc[u] = load_rgba<FMT>(V.rgba, (uint64_t)jj * plane + li);
+                }
+                bool stop = false;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (!stop) {
+                        if (j + u >= n || (double)dd[u].x >= zb) {
+                            stop = true;
+                        } else {
+                            const double zl = fmax(za, (double)dd[u].x), zh = fmin(zb, (double)dd[u].y);
+                            if (zh > zl) {
+                                last = j + u;
+                                if (piece(j + u, dd[u], cc[u], zl, zh, inv)) {
+                                    p = last;
+                                    return true;
+                                }
+                            }
+                            if ((double)dd[u].y >= zb) stop = true;
+                        }
+                    }
+                }
+                if (stop) break;
+                j += 4;
+            }
+        } else {
+            if (j < n && !have) d = depth_at(V, j, li);
+            while (j < n) {
+                if ((double)d.x >= zb) break;
+                const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * plane + li);
+                const bool more = (double)d.y < zb && j + 1 < n;
+                const float2 dn = more ? depth_at(V, j + 1, li) : d;
+                const double zl = fmax(za, (double)d.x), zh = fmin(zb, (double)d.y);
+                if (zh > zl) {
+                    last = j;
+                    if (piece(j, d, c, zl, zh, inv)) {
+                        p = last;
+                        return true;
+                    }
+                }
+                if (!more) break;
+                d = dn;
+                ++j;
+            }
+        }
+        p = last >= 0 ? last : min(j, n - 1);
+    } else if (Zp < -kFlatZ) {
+        // Travelling towards smaller depth: mirror image of the above.
+        const double inv = -1.0 / Zp;
+        int j;
+        bool have = false;
+        float2 d = make_float2(0.0f, 0.0f);
+        if (SEARCH == VDI_SEARCH_SEEDED && p >= 0 && p < n) {
+            const float2 dp = s.ps == p ? s.dp : depth_at(V, p, li);
+            const float f2 = p + 1 < n ? (s.ps == p ? s.dq.x : depth_at(V, p + 1, li).x) : __builtin_huge_valf();
+            if ((double)dp.x >= za) {
+                j = last_front_below<VDI_SEARCH_BINARY>(dep, plane, li, p, za, -1);
+            } else if ((double)f2 >= za) {
+                j = p;
+                d = dp;
+                have = true;
+            } else {
+                j = p + 2 + last_front_below<VDI_SEARCH_BINARY>(dep, plane, li + (uint64_t)(p + 2) * plane, n - p - 2,
+                                                                 za, -1);
+            }
+        } else {
+            j = last_front_below<SEARCH>(dep, plane, li, n, za, -1);
+        }
+        int last = -1;
+        if (j >= 0 && !have) d = depth_at(V, j, li);
+        while (j >= 0) {
+            if ((double)d.y <= zb) break;
+            const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * plane + li);
+            const bool more = (double)d.x > zb && j > 0;
+            const float2 dn = more ? depth_at(V, j - 1, li) : d;
+            const double zl = fmax(zb, (double)d.x), zh = fmin(za, (double)d.y);
+            if (zh > zl) {
+                last = j;
+                if (piece(j, d, c, zl, zh, inv)) {
+                    p = last;
+                    return true;
+                }
+            }
+            if (!more) break;
+            d = dn;
+            --j;
+        }
+        p = last >= 0 ? last : max(j, 0);
+    } else {
+        // Constant depth: the supersegment holding za covers the whole segment.
+        for (int j = 0; j < n; ++j) {
+            const float2 d = depth_at(V, j, li);
+            if ((double)d.x <= za && za < (double)d.y) {
+                const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * plane + li);
+                p = j;
+                composite(A, c, (float)(s.tb - s.ta) * cth / (d.y - d.x));
+                if constexpr (COUNT) {
+                    F.touched_slots[(uint64_t)j * plane + li] = 1;
+                    ++cnt.pieces;
+                }
+                return A.T <= kTTerm;
+            }
+        }
+        (void)inf;
+    }
+    return false;
+}
+
+// ---------------------------------------------------------------------------
+// Exact render (Sections 4.1-4.3)
+// ---------------------------------------------------------------------------
+// One exact ray through V_N pixel (px, py); s_gz = slice boundaries (LDS copy).
+// A walker steps through the list grid (voxel stepping in V_O NDC, Section
+// 4.1), skipping grid cells with count 0 when ESS is on (Section 4.3); each
+// segment it produces is prefetched one step before it is composited.
+template <int FMT, int SEARCH, bool ESS, bool COUNT>
+VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, int px, int py, Counters &cnt)
+{
+    Accum A = {0.0f, 0.0f, 0.0f, 1.0f};
+    Ray r;
+    const double xc = -1.0 + (2.0 * px + 1.0) / F.W, yc = -1.0 + (2.0 * py + 1.0) / F.H;
+    if (!ray_setup(F, xc, yc, r)) return make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const int WO = V.WO, HO = V.HO, gk = V.gk;
+    // Direction of travel across the list grid: d/dt (X/Z) has the sign of Kx.
+    const double Kx = r.Xp * F.Z0 - F.X0 * r.Zp, Ky = r.Yp * F.Z0 - F.Y0 * r.Zp;
+    const int sx = (Kx > 0.0) - (Kx < 0.0), sy = (Ky > 0.0) - (Ky < 0.0);
+    const bool fwd = r.Zp >= 0.0, flat = fabs(r.Zp) < kFlatZ;
+    const int dir = r.Zp < 0.0 ? -1 : 1;
+    const double inf = __builtin_huge_val();
+    double t = r.t0, tx = inf, ty = inf, tz = inf;
+    int ix = 0, iy = 0, mx = 0, my = 0, cz = 0;
+    int ccx = -1, ccy = -1, ccz = -1;
+    uint32_t cg = 0;
+    bool dead = false;
+    auto slice_t = [&](int c) -> double {
+        if (flat) return inf;
+        if (fwd) return c + 1 < V.gnz ? ((double)s_gz[c + 1] - F.Z0) / r.Zp : inf;
+        return c > 0 ? ((double)s_gz[c] - F.Z0) / r.Zp : inf;
+    };
+    auto locate = [&](double tt) {
+        const double z = F.Z0 + tt * r.Zp;
+        ix = cell_of((F.X0 + tt * r.Xp) / z, WO, sx);
+        iy = cell_of((F.Y0 + tt * r.Yp) / z, HO, sy);
+        mx = sx > 0 ? ix + 1 : ix;
+        my = sy > 0 ? iy + 1 : iy;
+        tx = (sx != 0 && mx > 0 && mx < WO) ? line_t(mx, WO, F.X0, r.Xp, F.Z0, r.Zp) : inf;
+        ty = (sy != 0 && my > 0 && my < HO) ? line_t(my, HO, F.Y0, r.Yp, F.Z0, r.Zp) : inf;
+        if constexpr (ESS) {
+            cz = slice_of(s_gz, V.gnz, z, fwd);
+            tz = slice_t(cz);
+        }
+    };
+    // Every call moves at least one list or grid cell, or ends the ray; the
+    // budget only guards against a loop that does not advance.
+    int budget = 4 * (WO + HO) + 4 * V.gnz + 64;
+    auto next_seg = [&](Seg &s) -> bool {
+        while (budget-- > 0) {
+            if (dead || t >= r.t1) return false;
+            if constexpr (ESS) {
+                while (tz <= t) {
+                    cz += dir;
+                    tz = slice_t(cz);
+                }
+                const int cx = ix / gk, cy = iy / gk;
+                if (cx != ccx || cy != ccy || cz != ccz) {
+                    cg = V.grid[((uint64_t)cz * V.GH + cy) * V.GW + cx];
+                    ccx = cx;
+                    ccy = cy;
+                    ccz = cz;
+                }
+                if (cg == 0u) {
+                    // Empty-space skipping: cross the empty cell in one step.
+                    double te = fmin(tz, r.t1);
+                    if (sx != 0) {
+                        const int m = sx > 0 ? min((cx + 1) * gk, WO) : cx * gk;
+                        if (m > 0 && m < WO) te = fmin(te, line_t(m, WO, F.X0, r.Xp, F.Z0, r.Zp));
+                    }
+                    if (sy != 0) {
+                        const int m = sy > 0 ? min((cy + 1) * gk, HO) : cy * gk;
+                        if (m > 0 && m < HO) te = fmin(te, line_t(m, HO, F.Y0, r.Yp, F.Z0, r.Zp));
+                    }
+                    if (te > t) {
+                        t = te;
+                        if (t >= r.t1) return false;
+                        locate(t);
+                        continue;
+                    }
+                }
+            }
+            const double tn = fmin(fmin(tx, ty), r.t1);
+            s.ix = ix;
+            s.iy = iy;
+            s.ta = t;
+            s.tb = tn;
+            if (tn >= r.t1) {
+                t = r.t1;
+            } else {
+                if (tx <= ty) {
+                    ix += sx;
+                    mx += sx;
+                    tx = (mx > 0 && mx < WO) ? line_t(mx, WO, F.X0, r.Xp, F.Z0, r.Zp) : inf;
+                } else {
+                    iy += sy;
+                    my += sy;
+                    ty = (my > 0 && my < HO) ? line_t(my, HO, F.Y0, r.Yp, F.Z0, r.Zp) : inf;
+                }
+                t = fmax(t, tn);
+                if ((unsigned)ix >= (unsigned)WO || (unsigned)iy >= (unsigned)HO) dead = true;
+            }
+            if (s.tb > s.ta) return true;
+        }
+        return false;
+    };
+    locate(t);
+    const double ray_len = r.t1 - r.t0;
+    int p = -1;
+    Seg cur, nxt;
+    bool have = next_seg(cur);
+    if (have) prefetch<SEARCH>(V, cur, p, dir);
+    while (have) {
+        const bool have_n = next_seg(nxt);
+        if (have_n) prefetch<SEARCH>(V, nxt, p, dir);
+        if (do_seg<FMT, SEARCH, COUNT>(V, F, cur, F.Z0, r.Zp, ray_len, A, p, cnt)) break;
+        cur = nxt;
+        have = have_n;
+    }
+    return make_float4(A.r, A.g, A.b, 1.0f - A.T);
+}
+
+// ---------------------------------------------------------------------------
+// Preview: adaptive along-ray subsampling (Section 4.4)
+// ---------------------------------------------------------------------------
+// One preview ray through V_N pixel (px, py) of the (low-res) grid.
+template <int FMT>
+VDI_HD float4 trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, int px, int py)
+{
+    Accum A = {0.0f, 0.0f, 0.0f, 1.0f};
+    Ray r;
+    const double xc = -1.0 + (2.0 * px + 1.0) / F.W, yc = -1.0 + (2.0 * py + 1.0) / F.H;
+    if (ray_setup(F, xc, yc, r)) {
+        const int WO = V.WO, HO = V.HO, k = V.gk;
+        const double Kx = r.Xp * F.Z0 - F.X0 * r.Zp, Ky = r.Yp * F.Z0 - F.Y0 * r.Zp;
+        const int sx = (Kx > 0.0) - (Kx < 0.0), sy = (Ky > 0.0) - (Ky < 0.0);
+        const bool fwd = r.Zp >= 0.0;
+        const bool flat = fabs(r.Zp) < kFlatZ;
+        const double inf = __builtin_huge_val();
+        const double inv_k2 = 1.0 / (double)(k * k);
+        const float2 *__restrict__ dep = V.depth;
+        const uint64_t plane = V.plane;
+        double t = r.t0;
+        int cx, cy, cz, mx, my;
+        double tx, ty, tz;
+        auto locate = [&](double tt) {
+            const double z = F.Z0 + tt * r.Zp;
+            cx = cell_of((F.X0 + tt * r.Xp) / z, WO, sx) / k;
+            cy = cell_of((F.Y0 + tt * r.Yp) / z, HO, sy) / k;
+            cz = slice_of(s_gz, V.gnz, z, fwd);
+            mx = sx > 0 ? min((cx + 1) * k, WO) : cx * k;
+            my = sy > 0 ? min((cy + 1) * k, HO) : cy * k;
+            tx = (sx != 0 && mx > 0 && mx < WO) ? line_t(mx, WO, F.X0, r.Xp, F.Z0, r.Zp) : inf;
+            ty = (sy != 0 && my > 0 && my < HO) ? line_t(my, HO, F.Y0, r.Yp, F.Z0, r.Zp) : inf;
+            if (flat)
+                tz = inf;
+            else if (fwd)
+                tz = cz + 1 < V.gnz ? ((double)s_gz[cz + 1] - F.Z0) / r.Zp : inf;
+            else
+                tz = cz > 0 ? ((double)s_gz[cz] - F.Z0) / r.Zp : inf;
+        };
+        locate(t);
+        int p = -1;
+        const int max_iter = 4 * (WO + HO) / k + 4 * V.gnz + 64;
+        bool done = false;
+        for (int it = 0; it < max_iter && !done; ++it) {
+            const double tn = fmin(fmin(fmin(tx, ty), tz), r.t1);
+            if (tn > t) {
+                const uint32_t G = V.grid[((uint64_t)cz * V.GH + cy) * V.GW + cx];
+                if (G != 0u) {
+                    const double dz = (double)s_gz[cz + 1] - (double)s_gz[cz];
+                    const double x = ((tn - t) / dz) * ((double)G * inv_k2) / F.DR;
+                    // D_R >= 1e-4 keeps x far below this bound; it only caps the loop.
+                    const int n = (int)fmin(fmax(ceil(x), 1.0), 16777216.0);
+                    const double h = (tn - t) / n;
+                    for (int q = 0; q < n; ++q) {
+                        const double u = t + (q + 0.5) * h;
+                        const double z = F.Z0 + u * r.Zp;
+                        const int lx = min(max((int)floor(((F.X0 + u * r.Xp) / z + 1.0) * WO / 2.0), 0), WO - 1);
+                        const int ly = min(max((int)floor(((F.Y0 + u * r.Yp) / z + 1.0) * HO / 2.0), 0), HO - 1);
+                        const uint64_t li = (uint64_t)ly * WO + lx;
+                        const int nl = V.count[li];
+                        if (nl == 0) continue;
+                        // Point location: the supersegment with f <= z < b.
+                        const int j = first_back_above<VDI_SEARCH_SEEDED>(dep, plane, li, nl, z, p);
+                        if (j >= nl) continue;
+                        const float2 fb = dep[(uint64_t)j * plane + li];
+                        p = j;
+                        if ((double)fb.x > z) continue;
+                        const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * plane + li);
+                        composite(A, c, (float)h * list_cos(V, lx, ly) / (fb.y - fb.x));
+                        if (A.T <= kTTerm) {
+                            done = true;
+                            break;
+                        }
+                    }
+                }
+            }
+            if (done || tn >= r.t1) break;
+            if (tx <= ty && tx <= tz) {
+                cx += sx;
+                mx = sx > 0 ? min((cx + 1) * k, WO) : cx * k;
+                tx = (mx > 0 && mx < WO) ? line_t(mx, WO, F.X0, r.Xp, F.Z0, r.Zp) : inf;
+            } else if (ty <= tz) {
+                cy += sy;
+                my = sy > 0 ? min((cy + 1) * k, HO) : cy * k;
+                ty = (my > 0 && my < HO) ? line_t(my, HO, F.Y0, r.Yp, F.Z0, r.Zp) : inf;
+            } else {
+                cz += fwd ? 1 : -1;
+                if (fwd)
+                    tz = cz + 1 < V.gnz ? ((double)s_gz[cz + 1] - F.Z0) / r.Zp : inf;
+                else
+                    tz = cz > 0 ? ((double)s_gz[cz] - F.Z0) / r.Zp : inf;
+            }
+            t = fmax(t, tn);
+            if ((unsigned)cx >= (unsigned)V.GW || (unsigned)cy >= (unsigned)V.GH || (unsigned)cz >= (unsigned)V.gnz)
+                break;
+        }
+    }
+    return make_float4(A.r, A.g, A.b, 1.0f - A.T);
+}
+
+
+// ---------------------------------------------------------------------------
+// Bilinear upsampling of one output pixel (x, y) of a W x H image from a
+// w x h image, half-pixel centres, clamped (Section 4.4, Fig. 7 caption).
+// ---------------------------------------------------------------------------
+VDI_HD inline float4 upsample_px(const float4 *__restrict__ lo, int w, int h, int W, int H, int x, int y)
+{
+    double sx = (x + 0.5) * (double)w / W - 0.5, sy = (y + 0.5) * (double)h / H - 0.5;
+    sx = fmin(fmax(sx, 0.0), (double)(w - 1));
+    sy = fmin(fmax(sy, 0.0), (double)(h - 1));
+    const int x0 = (int)sx, y0 = (int)sy;
+    const int x1 = min(x0 + 1, w - 1), y1 = min(y0 + 1, h - 1);
+    const float fx = (float)(sx - x0), fy = (float)(sy - y0);
+    const float4 a = lo[(uint64_t)y0 * w + x0], b = lo[(uint64_t)y0 * w + x1];
+    const float4 c = lo[(uint64_t)y1 * w + x0], d = lo[(uint64_t)y1 * w + x1];
+    auto mix = [&](float pa, float pb, float pc, float pd) {
+        return (pa * (1.0f - fx) + pb * fx) * (1.0f - fy) + (pc * (1.0f - fx) + pd * fx) * fy;
+    };
+    return make_float4(mix(a.x, b.x, c.x, d.x), mix(a.y, b.y, c.y, d.y), mix(a.z, b.z, c.z, d.z),
+                       mix(a.w, b.w, c.w, d.w));
+}
+
+}  // namespace vdi
