@@ -1,0 +1,197 @@
+"""Served form: continuous batching of VDI render requests (binding + load test).
+
+`Server` wraps the vdi_server_* calls of include/vdi.h.  `benchmark()` runs
+the served workload: four resident VDIs (two 1280x720 / N_S=20 and two
+1920x1080 / N_S=50, generating views 90 degrees apart, FP16 colour), 2000
+requests with Poisson arrivals at 600 requests/s, viewpoint deviation
+U[0, 30] degrees with random sign, output uniform over {1280x720 exact,
+1920x1080 exact, 1920x1080 D_I=2/D_R=2}, admission budget 64 GB.  The same
+trace is then rendered one request at a time with vdi_render for comparison.
+Arrival times are drawn in advance (open loop); a request's latency runs from
+its arrival to the moment the host sees it complete.
+"""
+from __future__ import annotations
+
+import ctypes
+import time
+from typing import Callable, Optional
+
+import numpy as np
+
+from . import vdi as V
+
+TRACE_SEED = 2005
+OUTPUTS = [(1280, 720, 1.0, 0.0), (1920, 1080, 1.0, 0.0), (1920, 1080, 2.0, 2.0)]
+
+
+class Server:
+    """A continuous-batching server on the current device."""
+
+    def __init__(self, budget_bytes: int, max_inflight: int = 64, workers: int = 0):
+        h = ctypes.c_void_p()
+        V._check(V.lib().vdi_server_create(int(budget_bytes), int(max_inflight), int(workers), ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, vdi: "V.Vdi", cam, width: int, height: int, d_i: float, d_r: float, out) -> Optional[int]:
+        """Ticket, or None when the request does not fit the budget or slots now."""
+        c = V.camera(cam)
+        t = ctypes.c_uint64()
+        rc = V.lib().vdi_server_submit(self._h, vdi.handle, ctypes.byref(c), width, height, d_i, d_r,
+                                       ctypes.c_void_p(out.data_ptr()), ctypes.byref(t))
+        if rc == V.VDI_ERR_BUDGET:
+            return None
+        V._check(rc)
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        d = ctypes.c_int()
+        V._check(V.lib().vdi_server_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(d)))
+        return bool(d.value)
+
+    def drain(self):
+        V._check(V.lib().vdi_server_drain(self._h))
+
+    def stats(self) -> dict:
+        s = V.ServerStats()
+        V._check(V.lib().vdi_server_get_stats(self._h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in V.ServerStats._fields_}
+
+    def close(self):
+        if self._h is not None:
+            h, self._h = self._h, None
+            V._check(V.lib().vdi_server_destroy(h))
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def make_trace(n: int = 2000, rate: float = 600.0, seed: int = TRACE_SEED, nvdi: int = 4):
+    """Pre-drawn request trace: arrival times, VDI index, yaw, output choice."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n))
+    which = rng.integers(0, nvdi, size=n)
+    yaw = rng.uniform(0.0, 30.0, size=n) * rng.choice([-1.0, 1.0], size=n)
+    out = rng.integers(0, len(OUTPUTS), size=n)
+    return arrivals, which, yaw, out
+
+
+def _percentiles(lat):
+    lat = np.asarray(lat) * 1e3
+    return {"p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "mean_ms": round(float(lat.mean()), 3), "max_ms": round(float(lat.max()), 3)}
+
+
+def load_vdis(store: str = "f16", log: Callable = print):
+    import inputs
+    srcs = []
+    for name in ("720p", "1080p"):
+        for base in (0.0, 90.0):
+            srcs.append((name, base, inputs.load_workload(name, base_deg=base, verbose=True, keep_dvr=False)))
+            log(f"loaded {name} base {base:g}")
+    return srcs
+
+
+def run_served(handles, bases, trace, budget: int, max_inflight: int, log: Callable = print):
+    """Open-loop served run; returns (latencies [s], makespan [s], stats, outputs by request)."""
+    import torch
+
+    import inputs
+    arrivals, which, yaw, outsel = trace
+    n = len(arrivals)
+    bufs = {}
+    pool = {k: [] for k in range(len(OUTPUTS))}
+    lat = np.zeros(n)
+    out_of = {}
+    with Server(budget, max_inflight) as srv:
+        pending = {}
+        nxt = 0
+        t0 = time.perf_counter()
+        done_count = 0
+        while done_count < n:
+            now = time.perf_counter() - t0
+            # admit every request that has arrived, while it fits
+            while nxt < n and arrivals[nxt] <= now:
+                k = int(outsel[nxt])
+                W, H, di, dr = OUTPUTS[k]
+                buf = pool[k].pop() if pool[k] else torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
+                cam = inputs.orbit_camera(float(yaw[nxt]), bases[int(which[nxt])])
+                t = srv.submit(handles[int(which[nxt])], cam, W, H, di, dr, buf)
+                if t is None:
+                    pool[k].append(buf)
+                    break
+                pending[t] = (nxt, k, buf)
+                nxt += 1
+            for t in list(pending):
+                if srv.poll(t):
+                    i, k, buf = pending.pop(t)
+                    lat[i] = (time.perf_counter() - t0) - arrivals[i]
+                    out_of[i] = buf
+                    done_count += 1
+            if not pending and nxt < n:
+                wait = arrivals[nxt] - (time.perf_counter() - t0)
+                if wait > 2e-4:
+                    time.sleep(wait - 1e-4)
+        makespan = time.perf_counter() - t0
+        stats = srv.stats()
+    return lat, makespan, stats, out_of
+
+
+def run_unbatched(handles, bases, trace):
+    """The same trace, one vdi_render at a time, synchronised per request."""
+    import torch
+
+    import inputs
+    arrivals, which, yaw, outsel = trace
+    n = len(arrivals)
+    bufs = {k: torch.empty((OUTPUTS[k][1], OUTPUTS[k][0], 4), dtype=torch.float32, device="cuda")
+            for k in range(len(OUTPUTS))}
+    lat = np.zeros(n)
+    t0 = time.perf_counter()
+    for i in range(n):
+        wait = arrivals[i] - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        k = int(outsel[i])
+        W, H, di, dr = OUTPUTS[k]
+        handles[int(which[i])].render(inputs.orbit_camera(float(yaw[i]), bases[int(which[i])]), W, H, di, dr,
+                                      out=bufs[k])
+        torch.cuda.synchronize()
+        lat[i] = (time.perf_counter() - t0) - arrivals[i]
+    return lat, time.perf_counter() - t0
+
+
+def benchmark(n: int = 2000, rate: float = 600.0, budget: int = 64 * 2 ** 30, max_inflight: int = 256,
+              log: Callable = print) -> dict:
+    import torch
+    srcs = load_vdis(log=log)
+    handles = [V.Vdi(s, store="f16") for _, _, s in srcs]
+    bases = [b for _, b, _ in srcs]
+    trace = make_trace(n, rate)
+    px = sum(OUTPUTS[int(k)][0] * OUTPUTS[int(k)][1] for k in trace[3])
+    # warm both paths on a few requests
+    warm = tuple(a[:16] for a in trace)
+    run_served(handles, bases, (warm[0] - warm[0][0], *warm[1:]), budget, max_inflight)
+    run_unbatched(handles, bases, (warm[0] * 0, *warm[1:]))
+    torch.cuda.synchronize()
+    lat, makespan, stats, _ = run_served(handles, bases, trace, budget, max_inflight, log)
+    log(f"served: {n} requests in {makespan:.2f}s, p50 {np.percentile(lat, 50)*1e3:.2f} ms, "
+        f"p99 {np.percentile(lat, 99)*1e3:.2f} ms, peak in flight {stats['peak_inflight']}")
+    ulat, umake = run_unbatched(handles, bases, trace)
+    log(f"unbatched: {n} requests in {umake:.2f}s, p50 {np.percentile(ulat, 50)*1e3:.2f} ms, "
+        f"p99 {np.percentile(ulat, 99)*1e3:.2f} ms")
+    for h in handles:
+        h.close()
+    return {
+        "workload": "4 resident FP16 VDIs (2x 1280x720/N_S=20, 2x 1920x1080/N_S=50; V_O 0 and 90 deg); "
+                    f"{n} requests, Poisson {rate:g}/s, yaw U[0,30] deg +-, outputs 720p exact / 1080p exact / "
+                    "1080p D_I=2,D_R=2; admission budget 64 GB",
+        "served": {**_percentiles(lat), "Mpixels_per_s": round(px / makespan / 1e6, 1),
+                   "requests_per_s": round(n / makespan, 1), "peak_inflight": stats["peak_inflight"],
+                   "peak_bytes_in_flight": stats["peak_bytes_in_flight"],
+                   "rejected_budget": stats["rejected_budget"], "rejected_slots": stats["rejected_slots"]},
+        "unbatched": {**_percentiles(ulat), "Mpixels_per_s": round(px / umake / 1e6, 1),
+                      "requests_per_s": round(n / umake, 1)},
+    }
