@@ -203,6 +203,10 @@ __global__ __launch_bounds__(kServeBlock) void k_serve(Ctl *ctl, const Job *desc
             if (x < s_job.W && y < s_job.H)
                 s_job.out[(uint64_t)y * s_job.W + x] = upsample_px(s_job.F.out, s_job.w, s_job.h, s_job.W, s_job.H, x, y);
         }
+        // Each wavefront's stores must reach device scope before thread 0
+        // counts the tile: the barrier alone does not wait for other
+        // wavefronts' stores, and readers of this tile may sit on another XCD.
+        __threadfence();
         __syncthreads();
         if (threadIdx.x == 0) {
             if (phase1)

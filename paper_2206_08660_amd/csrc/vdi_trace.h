@@ -268,58 +268,30 @@ struct Counters {
     int32_t lists, pieces;
 };
 
-// One list segment of a ray: list (ix, iy) over [ta, tb], with the values
-// fetched for it one step ahead of its processing: the list's count and the
-// depth pairs of the seed slot ps and its neighbour towards the ray's entry.
-struct Seg {
-    int ix, iy;
-    double ta, tb;
-    int n, ps;
-    float2 dp, dq;
-};
-
 VDI_HD inline float2 depth_at(const DevVDI &V, int j, uint64_t li) { return V.depth[(uint64_t)j * V.plane + li]; }
 
-// Issue the loads a segment needs first.  Slots at or beyond the count are
-// in bounds (every list has N_S slots) and are never used.
-template <int SEARCH>
-VDI_HD inline void prefetch(const DevVDI &V, Seg &s, int p, int dir)
-{
-    const uint64_t li = (uint64_t)s.iy * V.WO + s.ix;
-    s.n = V.count[li];
-    s.ps = -1;
-    if constexpr (SEARCH == VDI_SEARCH_SEEDED) {
-        if (p >= 0 && p < V.NS) {
-            s.ps = p;
-            s.dp = depth_at(V, p, li);
-            const int q = p - dir;
-            s.dq = (q >= 0 && q < V.NS) ? depth_at(V, q, li) : make_float2(0.0f, 0.0f);
-        }
-    }
-}
-
-// Composite segment s of a ray with dz/dt = Zp (Sections 4.2, Eq. 2).  The
-// first supersegment is found by the configured search (seeded by p, the
-// index used in the previous list, supplement Alg. S2), the next ones by
-// adjacency.  Long segments fetch four supersegments per round trip; short
-// ones overlap each supersegment's colour load with the next depth load.
-// p is updated; returns true once the ray has terminated.
+// Composite the part of list (ix, iy) that a ray with dz/dt = Zp crosses
+// between parameters ta and tb (Sections 4.2, Eq. 2).  n is the list's count
+// (fetched one step ahead by the caller).  The first supersegment comes from
+// the configured search, seeded by p, the index used in the previous list
+// (supplement Alg. S2: both candidate depth pairs are loaded before either is
+// compared, and the one that hits is reused); the next ones by adjacency,
+// each colour load overlapping the following depth load.  p is updated;
+// returns true once the ray has terminated.
 template <int FMT, int SEARCH, bool COUNT>
-VDI_HD bool do_seg(const DevVDI &V, const Frame &F, const Seg &s, double Z0, double Zp, double ray_len, Accum &A,
-                   int &p, Counters &cnt)
+VDI_HD bool do_list(const DevVDI &V, const Frame &F, int ix, int iy, int n, double ta, double tb, double Z0,
+                    double Zp, Accum &A, int &p, Counters &cnt)
 {
-    const uint64_t li = (uint64_t)s.iy * V.WO + s.ix;
+    const uint64_t li = (uint64_t)iy * V.WO + ix;
     if constexpr (COUNT) {
         F.touched_lists[li] = 1;
         ++cnt.lists;
     }
-    const int n = s.n;
     if (n == 0) return false;
-    const double za = Z0 + s.ta * Zp, zb = Z0 + s.tb * Zp;
-    const float cth = list_cos(V, s.ix, s.iy);
+    const double za = Z0 + ta * Zp, zb = Z0 + tb * Zp;
+    const float cth = list_cos(V, ix, iy);
     const float2 *__restrict__ dep = V.depth;
     const uint64_t plane = V.plane;
-    const double inf = __builtin_huge_val();
     auto piece = [&](int j, float2 d, float4 c, double zl, double zh, double inv) -> bool {
         composite(A, c, (float)((zh - zl) * inv) * cth / (d.y - d.x));
         if constexpr (COUNT) {
@@ -328,21 +300,18 @@ VDI_HD bool do_seg(const DevVDI &V, const Frame &F, const Seg &s, double Z0, dou
         }
         return A.T <= kTTerm;
     };
-    // Expected supersegments in this segment: the list's count times the
-    // segment's share of the ray.
-    const bool batch = (double)n * (s.tb - s.ta) >= 3.0 * ray_len;
     if (Zp > kFlatZ) {
         const double inv = 1.0 / Zp;
         int j;
         bool have = false;
         float2 d = make_float2(0.0f, 0.0f);
         if (SEARCH == VDI_SEARCH_SEEDED && p >= 0 && p < n) {
-            const float2 dp = s.ps == p ? s.dp : depth_at(V, p, li);
-            const float b0 = p > 0 ? (s.ps == p ? s.dq.y : depth_at(V, p - 1, li).y) : -__builtin_huge_valf();
-            if ((double)b0 > za) {
+            const float2 dp = depth_at(V, p, li);
+            const float2 dq = p > 0 ? depth_at(V, p - 1, li) : make_float2(-__builtin_huge_valf(), -__builtin_huge_valf());
+            if ((double)dq.y > za) {
                 j = first_back_above<VDI_SEARCH_BINARY>(dep, plane, li, p - 1, za, -1);
                 if (j == p - 1) {
-                    d = s.ps == p ? s.dq : depth_at(V, p - 1, li);
+                    d = dq;
                     have = true;
                 }
             } else if ((double)dp.y > za) {
@@ -357,57 +326,23 @@ VDI_HD bool do_seg(const DevVDI &V, const Frame &F, const Seg &s, double Z0, dou
             j = first_back_above<SEARCH>(dep, plane, li, n, za, -1);
         }
         int last = -1;
-        if (batch) {
-            while (j < n) {
-                float2 dd[4];
-                float4 cc[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int jj = min(j + u, n - 1);
-                    dd[u] = dep[(uint64_t)jj * plane + li];
-                    cc[u] = load_rgba<FMT>(V.rgba, (uint64_t)jj * plane + li);
+        if (j < n && !have) d = depth_at(V, j, li);
+        while (j < n) {
+            if ((double)d.x >= zb) break;
+            const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * plane + li);
+            const bool more = (double)d.y < zb && j + 1 < n;
+            const float2 dn = more ? depth_at(V, j + 1, li) : d;
+            const double zl = fmax(za, (double)d.x), zh = fmin(zb, (double)d.y);
+            if (zh > zl) {
+                last = j;
+                if (piece(j, d, c, zl, zh, inv)) {
+                    p = last;
+                    return true;
                 }
-                bool stop = false;
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (!stop) {
-                        if (j + u >= n || (double)dd[u].x >= zb) {
-                            stop = true;
-                        } else {
-                            const double zl = fmax(za, (double)dd[u].x), zh = fmin(zb, (double)dd[u].y);
-                            if (zh > zl) {
-                                last = j + u;
-                                if (piece(j + u, dd[u], cc[u], zl, zh, inv)) {
-                                    p = last;
-                                    return true;
-                                }
-                            }
-                            if ((double)dd[u].y >= zb) stop = true;
-                        }
-                    }
-                }
-                if (stop) break;
-                j += 4;
             }
-        } else {
-            if (j < n && !have) d = depth_at(V, j, li);
-            while (j < n) {
-                if ((double)d.x >= zb) break;
-                const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * plane + li);
-                const bool more = (double)d.y < zb && j + 1 < n;
-                const float2 dn = more ? depth_at(V, j + 1, li) : d;
-                const double zl = fmax(za, (double)d.x), zh = fmin(zb, (double)d.y);
-                if (zh > zl) {
-                    last = j;
-                    if (piece(j, d, c, zl, zh, inv)) {
-                        p = last;
-                        return true;
-                    }
-                }
-                if (!more) break;
-                d = dn;
-                ++j;
-            }
+            if (!more) break;
+            d = dn;
+            ++j;
         }
         p = last >= 0 ? last : min(j, n - 1);
     } else if (Zp < -kFlatZ) {
@@ -417,11 +352,11 @@ VDI_HD bool do_seg(const DevVDI &V, const Frame &F, const Seg &s, double Z0, dou
         bool have = false;
         float2 d = make_float2(0.0f, 0.0f);
         if (SEARCH == VDI_SEARCH_SEEDED && p >= 0 && p < n) {
-            const float2 dp = s.ps == p ? s.dp : depth_at(V, p, li);
-            const float f2 = p + 1 < n ? (s.ps == p ? s.dq.x : depth_at(V, p + 1, li).x) : __builtin_huge_valf();
+            const float2 dp = depth_at(V, p, li);
+            const float2 dq = p + 1 < n ? depth_at(V, p + 1, li) : make_float2(__builtin_huge_valf(), __builtin_huge_valf());
             if ((double)dp.x >= za) {
                 j = last_front_below<VDI_SEARCH_BINARY>(dep, plane, li, p, za, -1);
-            } else if ((double)f2 >= za) {
+            } else if ((double)dq.x >= za) {
                 j = p;
                 d = dp;
                 have = true;
@@ -453,13 +388,13 @@ VDI_HD bool do_seg(const DevVDI &V, const Frame &F, const Seg &s, double Z0, dou
         }
         p = last >= 0 ? last : max(j, 0);
     } else {
-        // Constant depth: the supersegment holding za covers the whole segment.
+        // Constant depth: the supersegment holding za covers the whole piece.
         for (int j = 0; j < n; ++j) {
             const float2 d = depth_at(V, j, li);
             if ((double)d.x <= za && za < (double)d.y) {
                 const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * plane + li);
                 p = j;
-                composite(A, c, (float)(s.tb - s.ta) * cth / (d.y - d.x));
+                composite(A, c, (float)(tb - ta) * cth / (d.y - d.x));
                 if constexpr (COUNT) {
                     F.touched_slots[(uint64_t)j * plane + li] = 1;
                     ++cnt.pieces;
@@ -467,7 +402,6 @@ VDI_HD bool do_seg(const DevVDI &V, const Frame &F, const Seg &s, double Z0, dou
                 return A.T <= kTTerm;
             }
         }
-        (void)inf;
     }
     return false;
 }
@@ -476,9 +410,10 @@ VDI_HD bool do_seg(const DevVDI &V, const Frame &F, const Seg &s, double Z0, dou
 // Exact render (Sections 4.1-4.3)
 // ---------------------------------------------------------------------------
 // One exact ray through V_N pixel (px, py); s_gz = slice boundaries (LDS copy).
-// A walker steps through the list grid (voxel stepping in V_O NDC, Section
-// 4.1), skipping grid cells with count 0 when ESS is on (Section 4.3); each
-// segment it produces is prefetched one step before it is composited.
+// The ray steps through the list grid (voxel stepping in V_O NDC, Section
+// 4.1), fetching the count of the list it enters next while it composites the
+// current one; with ESS on it crosses grid cells of count 0 in one step
+// (Section 4.3), keeping the current cell and depth slice from step to step.
 template <int FMT, int SEARCH, bool ESS, bool COUNT>
 VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, int px, int py, Counters &cnt)
 {
@@ -491,13 +426,11 @@ VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, in
     const double Kx = r.Xp * F.Z0 - F.X0 * r.Zp, Ky = r.Yp * F.Z0 - F.Y0 * r.Zp;
     const int sx = (Kx > 0.0) - (Kx < 0.0), sy = (Ky > 0.0) - (Ky < 0.0);
     const bool fwd = r.Zp >= 0.0, flat = fabs(r.Zp) < kFlatZ;
-    const int dir = r.Zp < 0.0 ? -1 : 1;
     const double inf = __builtin_huge_val();
     double t = r.t0, tx = inf, ty = inf, tz = inf;
     int ix = 0, iy = 0, mx = 0, my = 0, cz = 0;
     int ccx = -1, ccy = -1, ccz = -1;
     uint32_t cg = 0;
-    bool dead = false;
     auto slice_t = [&](int c) -> double {
         if (flat) return inf;
         if (fwd) return c + 1 < V.gnz ? ((double)s_gz[c + 1] - F.Z0) / r.Zp : inf;
@@ -516,79 +449,64 @@ VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, in
             tz = slice_t(cz);
         }
     };
-    // Every call moves at least one list or grid cell, or ends the ray; the
-    // budget only guards against a loop that does not advance.
-    int budget = 4 * (WO + HO) + 4 * V.gnz + 64;
-    auto next_seg = [&](Seg &s) -> bool {
-        while (budget-- > 0) {
-            if (dead || t >= r.t1) return false;
-            if constexpr (ESS) {
-                while (tz <= t) {
-                    cz += dir;
-                    tz = slice_t(cz);
-                }
-                const int cx = ix / gk, cy = iy / gk;
-                if (cx != ccx || cy != ccy || cz != ccz) {
-                    cg = V.grid[((uint64_t)cz * V.GH + cy) * V.GW + cx];
-                    ccx = cx;
-                    ccy = cy;
-                    ccz = cz;
-                }
-                if (cg == 0u) {
-                    // Empty-space skipping: cross the empty cell in one step.
-                    double te = fmin(tz, r.t1);
-                    if (sx != 0) {
-                        const int m = sx > 0 ? min((cx + 1) * gk, WO) : cx * gk;
-                        if (m > 0 && m < WO) te = fmin(te, line_t(m, WO, F.X0, r.Xp, F.Z0, r.Zp));
-                    }
-                    if (sy != 0) {
-                        const int m = sy > 0 ? min((cy + 1) * gk, HO) : cy * gk;
-                        if (m > 0 && m < HO) te = fmin(te, line_t(m, HO, F.Y0, r.Yp, F.Z0, r.Zp));
-                    }
-                    if (te > t) {
-                        t = te;
-                        if (t >= r.t1) return false;
-                        locate(t);
-                        continue;
-                    }
-                }
-            }
-            const double tn = fmin(fmin(tx, ty), r.t1);
-            s.ix = ix;
-            s.iy = iy;
-            s.ta = t;
-            s.tb = tn;
-            if (tn >= r.t1) {
-                t = r.t1;
-            } else {
-                if (tx <= ty) {
-                    ix += sx;
-                    mx += sx;
-                    tx = (mx > 0 && mx < WO) ? line_t(mx, WO, F.X0, r.Xp, F.Z0, r.Zp) : inf;
-                } else {
-                    iy += sy;
-                    my += sy;
-                    ty = (my > 0 && my < HO) ? line_t(my, HO, F.Y0, r.Yp, F.Z0, r.Zp) : inf;
-                }
-                t = fmax(t, tn);
-                if ((unsigned)ix >= (unsigned)WO || (unsigned)iy >= (unsigned)HO) dead = true;
-            }
-            if (s.tb > s.ta) return true;
-        }
-        return false;
-    };
     locate(t);
-    const double ray_len = r.t1 - r.t0;
     int p = -1;
-    Seg cur, nxt;
-    bool have = next_seg(cur);
-    if (have) prefetch<SEARCH>(V, cur, p, dir);
-    while (have) {
-        const bool have_n = next_seg(nxt);
-        if (have_n) prefetch<SEARCH>(V, nxt, p, dir);
-        if (do_seg<FMT, SEARCH, COUNT>(V, F, cur, F.Z0, r.Zp, ray_len, A, p, cnt)) break;
-        cur = nxt;
-        have = have_n;
+    int n = V.count[(uint64_t)iy * WO + ix];
+    // Every iteration moves one list or jumps a grid cell; the cap only
+    // guards against a loop that does not advance.
+    const int max_iter = 4 * (WO + HO) + 4 * V.gnz + 64;
+    for (int it = 0; it < max_iter; ++it) {
+        const double tn = fmin(fmin(tx, ty), r.t1);
+        if constexpr (ESS) {
+            while (tz <= t) {
+                cz += fwd ? 1 : -1;
+                tz = slice_t(cz);
+            }
+            const int cx = ix / gk, cy = iy / gk;
+            if (cx != ccx || cy != ccy || cz != ccz) {
+                cg = V.grid[((uint64_t)cz * V.GH + cy) * V.GW + cx];
+                ccx = cx;
+                ccy = cy;
+                ccz = cz;
+            }
+            if (cg == 0u) {
+                // Empty-space skipping: cross the empty cell in one step.
+                double te = fmin(tz, r.t1);
+                if (sx != 0) {
+                    const int m = sx > 0 ? min((cx + 1) * gk, WO) : cx * gk;
+                    if (m > 0 && m < WO) te = fmin(te, line_t(m, WO, F.X0, r.Xp, F.Z0, r.Zp));
+                }
+                if (sy != 0) {
+                    const int m = sy > 0 ? min((cy + 1) * gk, HO) : cy * gk;
+                    if (m > 0 && m < HO) te = fmin(te, line_t(m, HO, F.Y0, r.Yp, F.Z0, r.Zp));
+                }
+                if (te > t) {
+                    t = te;
+                    if (t >= r.t1) break;
+                    locate(t);
+                    n = V.count[(uint64_t)iy * WO + ix];
+                    continue;
+                }
+            }
+        }
+        // The list entered next, and its count, are known before this one is composited.
+        const bool stepx = tx <= ty;
+        const int nx = stepx ? ix + sx : ix, ny = stepx ? iy : iy + sy;
+        const bool more = tn < r.t1 && (unsigned)nx < (unsigned)WO && (unsigned)ny < (unsigned)HO;
+        const int n_next = more ? V.count[(uint64_t)ny * WO + nx] : 0;
+        if (tn > t && do_list<FMT, SEARCH, COUNT>(V, F, ix, iy, n, t, tn, F.Z0, r.Zp, A, p, cnt)) break;
+        if (!more) break;
+        if (stepx) {
+            mx += sx;
+            tx = (mx > 0 && mx < WO) ? line_t(mx, WO, F.X0, r.Xp, F.Z0, r.Zp) : inf;
+        } else {
+            my += sy;
+            ty = (my > 0 && my < HO) ? line_t(my, HO, F.Y0, r.Yp, F.Z0, r.Zp) : inf;
+        }
+        ix = nx;
+        iy = ny;
+        n = n_next;
+        t = fmax(t, tn);
     }
     return make_float4(A.r, A.g, A.b, 1.0f - A.T);
 }
@@ -708,8 +626,11 @@ VDI_HD inline float4 upsample_px(const float4 *__restrict__ lo, int w, int h, in
     const float fx = (float)(sx - x0), fy = (float)(sy - y0);
     const float4 a = lo[(uint64_t)y0 * w + x0], b = lo[(uint64_t)y0 * w + x1];
     const float4 c = lo[(uint64_t)y1 * w + x0], d = lo[(uint64_t)y1 * w + x1];
+    // Explicit fused multiply-adds: the result does not depend on how a
+    // compiler contracts the expression in the kernel it is inlined into.
     auto mix = [&](float pa, float pb, float pc, float pd) {
-        return (pa * (1.0f - fx) + pb * fx) * (1.0f - fy) + (pc * (1.0f - fx) + pd * fx) * fy;
+        const float top = fmaf(fx, pb - pa, pa), bot = fmaf(fx, pd - pc, pc);
+        return fmaf(fy, bot - top, top);
     };
     return make_float4(mix(a.x, b.x, c.x, d.x), mix(a.y, b.y, c.y, d.y), mix(a.z, b.z, c.z, d.z),
                        mix(a.w, b.w, c.w, d.w));
