@@ -178,11 +178,7 @@ __global__ __launch_bounds__(kServeBlock) void k_serve(Ctl *ctl, const Job *desc
         const uint32_t local = (uint32_t)(s_g - s_base);
         const bool phase1 = local < (uint32_t)s_job.ntiles1;
         if (phase1) {
-            switch (s_job.V.fmt) {
-            case VDI_F16: render_tile<VDI_F16>(s_job, s_gz, local); break;
-            case VDI_BF16: render_tile<VDI_BF16>(s_job, s_gz, local); break;
-            default: render_tile<VDI_F32>(s_job, s_gz, local); break;
-            }
+            render_tile<kFmtRuntime>(s_job, s_gz, local);
         } else {
             if (threadIdx.x == 0) {
                 const uint64_t t0 = now_ticks();

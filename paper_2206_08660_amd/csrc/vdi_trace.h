@@ -60,23 +60,24 @@ VDI_HD inline int xcd_tile(int bid, int tiles_x, int tiles_y)
 // ---------------------------------------------------------------------------
 // Colour planes
 // ---------------------------------------------------------------------------
+// Colour of slot idx.  FMT is the storage format, or kFmtRuntime to read it
+// from `fmt` (one code path for kernels that serve VDIs of any format).
+constexpr int kFmtRuntime = -1;
+
 template <int FMT>
-VDI_HD inline float4 load_rgba(const void *base, uint64_t idx)
+VDI_HD inline float4 load_rgba(const void *base, uint64_t idx, int fmt = FMT)
 {
-    if constexpr (FMT == VDI_F32) {
-        return reinterpret_cast<const float4 *>(base)[idx];
-    } else {
-        const uint2 u = reinterpret_cast<const uint2 *>(base)[idx];
-        if constexpr (FMT == VDI_F16) {
-            const __half2 rg = *reinterpret_cast<const __half2 *>(&u.x);
-            const __half2 ba = *reinterpret_cast<const __half2 *>(&u.y);
-            const float2 a = __half22float2(rg), b = __half22float2(ba);
-            return make_float4(a.x, a.y, b.x, b.y);
-        } else {
-            return make_float4(__builtin_bit_cast(float, u.x << 16), __builtin_bit_cast(float, u.x & 0xffff0000u),
-                               __builtin_bit_cast(float, u.y << 16), __builtin_bit_cast(float, u.y & 0xffff0000u));
-        }
+    const int f = FMT >= 0 ? FMT : fmt;
+    if (FMT == VDI_F32 || (FMT < 0 && f == VDI_F32)) return reinterpret_cast<const float4 *>(base)[idx];
+    const uint2 u = reinterpret_cast<const uint2 *>(base)[idx];
+    if (f == VDI_F16) {
+        const __half2 rg = *reinterpret_cast<const __half2 *>(&u.x);
+        const __half2 ba = *reinterpret_cast<const __half2 *>(&u.y);
+        const float2 a = __half22float2(rg), b = __half22float2(ba);
+        return make_float4(a.x, a.y, b.x, b.y);
     }
+    return make_float4(__builtin_bit_cast(float, u.x << 16), __builtin_bit_cast(float, u.x & 0xffff0000u),
+                       __builtin_bit_cast(float, u.y << 16), __builtin_bit_cast(float, u.y & 0xffff0000u));
 }
 
 // ---------------------------------------------------------------------------
@@ -329,7 +330,7 @@ VDI_HD bool do_list(const DevVDI &V, const Frame &F, int ix, int iy, int n, doub
         if (j < n && !have) d = depth_at(V, j, li);
         while (j < n) {
             if ((double)d.x >= zb) break;
-            const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * plane + li);
+            const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * plane + li, V.fmt);
             const bool more = (double)d.y < zb && j + 1 < n;
             const float2 dn = more ? depth_at(V, j + 1, li) : d;
             const double zl = fmax(za, (double)d.x), zh = fmin(zb, (double)d.y);
@@ -371,7 +372,7 @@ VDI_HD bool do_list(const DevVDI &V, const Frame &F, int ix, int iy, int n, doub
         if (j >= 0 && !have) d = depth_at(V, j, li);
         while (j >= 0) {
             if ((double)d.y <= zb) break;
-            const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * plane + li);
+            const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * plane + li, V.fmt);
             const bool more = (double)d.x > zb && j > 0;
             const float2 dn = more ? depth_at(V, j - 1, li) : d;
             const double zl = fmax(zb, (double)d.x), zh = fmin(za, (double)d.y);
@@ -392,7 +393,7 @@ VDI_HD bool do_list(const DevVDI &V, const Frame &F, int ix, int iy, int n, doub
         for (int j = 0; j < n; ++j) {
             const float2 d = depth_at(V, j, li);
             if ((double)d.x <= za && za < (double)d.y) {
-                const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * plane + li);
+                const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * plane + li, V.fmt);
                 p = j;
                 composite(A, c, (float)(tb - ta) * cth / (d.y - d.x));
                 if constexpr (COUNT) {
@@ -578,7 +579,7 @@ VDI_HD float4 trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, 
                         const float2 fb = dep[(uint64_t)j * plane + li];
                         p = j;
                         if ((double)fb.x > z) continue;
-                        const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * plane + li);
+                        const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * plane + li, V.fmt);
                         composite(A, c, (float)h * list_cos(V, lx, ly) / (fb.y - fb.x));
                         if (A.T <= kTTerm) {
                             done = true;
