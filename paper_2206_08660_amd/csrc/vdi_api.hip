@@ -340,6 +340,9 @@ int vdi_create(const vdi_desc *d, vdi_t *out)
     D.GH = (d->height + d->grid_k - 1) / d->grid_k;
     D.tx_o = (float)(ob.th * ((double)d->width / d->height));
     D.ty_o = (float)ob.th;
+    D.dcx = 2.0 / d->width;
+    D.dcy = 2.0 / d->height;
+    D.inv_gk = nextafterf(1.0f / (float)d->grid_k, INFINITY);
 
     const uint64_t ns = (uint64_t)d->max_supersegments;
     const size_t colour = d->rgba_fmt_store == VDI_F32 ? 16 : 8;

@@ -27,6 +27,8 @@ struct DevVDI {
     int32_t gk, gnz, GW, GH;
     const float *gz;           // [gnz + 1] slice boundaries (device)
     float tx_o, ty_o;          // tan(fov/2) * aspect, tan(fov/2) of V_O
+    double dcx, dcy;           // 2 / WO, 2 / HO: spacing of the list grid lines in NDC
+    float inv_gk;              // 1 / gk rounded up: (int)(i * inv_gk) == i / gk for i < 2^15
 };
 
 // Per-render constants, computed on the host in double precision.

@@ -17,6 +17,26 @@ namespace vdi {
 // through on the CPU with the same code.
 #define VDI_HD __host__ __device__
 
+// Arithmetic helpers: native gfx950 instructions on the device (overloaded
+// on the compilation target), the plain formulas on the host.  The FP64
+// reciprocal is refined by two Newton steps to full precision; the FP32 ones
+// are within an ulp or two, far below the 1e-4 the renders are held to.
+__device__ inline double rcp64(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+__host__ inline double rcp64(double x) { return 1.0 / x; }
+__device__ inline float rcp32(float x) { return __builtin_amdgcn_rcpf(x); }
+__host__ inline float rcp32(float x) { return 1.0f / x; }
+__device__ inline float rsqrt32(float x) { return __builtin_amdgcn_rsqf(x); }
+__host__ inline float rsqrt32(float x) { return 1.0f / sqrtf(x); }
+__device__ inline float exp2_32(float x) { return __builtin_amdgcn_exp2f(x); }
+__host__ inline float exp2_32(float x) { return exp2f(x); }
+__device__ inline float log2_32(float x) { return __builtin_amdgcn_logf(x); }
+__host__ inline float log2_32(float x) { return log2f(x); }
+
 constexpr int kTileW = 64;
 constexpr int kTileH = 4;
 constexpr int kBlock = kTileW * kTileH;
@@ -132,12 +152,13 @@ VDI_HD inline bool ray_setup(const Frame &F, double xc, double yc, Ray &r)
 // or +inf if it never does.  coord(t) = P(t) / Z(t) is monotone where Z > 0
 // but its asymptote is the ray's vanishing point: a line beyond it has its
 // only root on the branch behind V_O (Z < 0), which is not a crossing.
-VDI_HD inline double line_t(int m, int n, double P0, double Pp, double Z0, double Zp)
+VDI_HD inline double line_t(int m, double two_over_n, double P0, double Pp, double Z0, double Zp)
 {
-    const double c = -1.0 + 2.0 * m / n;
+    const double c = fma((double)m, two_over_n, -1.0);
     const double den = Pp - c * Zp;
-    const double t = (c * Z0 - P0) / den;
-    return (den != 0.0 && Z0 + t * Zp > 0.0) ? t : __builtin_huge_val();
+    if (den == 0.0) return __builtin_huge_val();
+    const double t = (c * Z0 - P0) * rcp64(den);
+    return Z0 + t * Zp > 0.0 ? t : __builtin_huge_val();
 }
 
 // Cell index of an NDC coordinate; a point exactly on a line belongs to the
@@ -156,7 +177,7 @@ VDI_HD inline float list_cos(const DevVDI &V, int ix, int iy)
 {
     const float x = (-1.0f + (2.0f * ix + 1.0f) / V.WO) * V.tx_o;
     const float y = (-1.0f + (2.0f * iy + 1.0f) / V.HO) * V.ty_o;
-    return 1.0f / sqrtf(1.0f + x * x + y * y);
+    return rsqrt32(1.0f + x * x + y * y);
 }
 
 // Depth slice holding depth z for a ray moving towards larger (fwd) or smaller z.
@@ -257,7 +278,7 @@ struct Accum {
 // generating ray in S), then front-to-back "over".
 VDI_HD inline void composite(Accum &A, float4 c, float l)
 {
-    const float at = c.w >= 1.0f ? 1.0f : 1.0f - exp2f(l * log2f(1.0f - c.w));
+    const float at = c.w >= 1.0f ? 1.0f : 1.0f - exp2_32(l * log2_32(1.0f - c.w));
     const float w = A.T * at;
     A.r = fmaf(w, c.x, A.r);
     A.g = fmaf(w, c.y, A.g);
@@ -281,7 +302,7 @@ VDI_HD inline float2 depth_at(const DevVDI &V, int j, uint64_t li) { return V.de
 // returns true once the ray has terminated.
 template <int FMT, int SEARCH, bool COUNT>
 VDI_HD bool do_list(const DevVDI &V, const Frame &F, int ix, int iy, int n, double ta, double tb, double Z0,
-                    double Zp, Accum &A, int &p, Counters &cnt)
+                    double Zp, double invZp, Accum &A, int &p, Counters &cnt)
 {
     const uint64_t li = (uint64_t)iy * V.WO + ix;
     if constexpr (COUNT) {
@@ -294,7 +315,7 @@ VDI_HD bool do_list(const DevVDI &V, const Frame &F, int ix, int iy, int n, doub
     const float2 *__restrict__ dep = V.depth;
     const uint64_t plane = V.plane;
     auto piece = [&](int j, float2 d, float4 c, double zl, double zh, double inv) -> bool {
-        composite(A, c, (float)((zh - zl) * inv) * cth / (d.y - d.x));
+        composite(A, c, (float)((zh - zl) * inv) * cth * rcp32(d.y - d.x));
         if constexpr (COUNT) {
             F.touched_slots[(uint64_t)j * plane + li] = 1;
             ++cnt.pieces;
@@ -302,7 +323,7 @@ VDI_HD bool do_list(const DevVDI &V, const Frame &F, int ix, int iy, int n, doub
         return A.T <= kTTerm;
     };
     if (Zp > kFlatZ) {
-        const double inv = 1.0 / Zp;
+        const double inv = invZp;
         int j;
         bool have = false;
         float2 d = make_float2(0.0f, 0.0f);
@@ -348,7 +369,7 @@ VDI_HD bool do_list(const DevVDI &V, const Frame &F, int ix, int iy, int n, doub
         p = last >= 0 ? last : min(j, n - 1);
     } else if (Zp < -kFlatZ) {
         // Travelling towards smaller depth: mirror image of the above.
-        const double inv = -1.0 / Zp;
+        const double inv = -invZp;
         int j;
         bool have = false;
         float2 d = make_float2(0.0f, 0.0f);
@@ -395,7 +416,7 @@ VDI_HD bool do_list(const DevVDI &V, const Frame &F, int ix, int iy, int n, doub
             if ((double)d.x <= za && za < (double)d.y) {
                 const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * plane + li, V.fmt);
                 p = j;
-                composite(A, c, (float)(tb - ta) * cth / (d.y - d.x));
+                composite(A, c, (float)(tb - ta) * cth * rcp32(d.y - d.x));
                 if constexpr (COUNT) {
                     F.touched_slots[(uint64_t)j * plane + li] = 1;
                     ++cnt.pieces;
@@ -428,14 +449,15 @@ VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, in
     const int sx = (Kx > 0.0) - (Kx < 0.0), sy = (Ky > 0.0) - (Ky < 0.0);
     const bool fwd = r.Zp >= 0.0, flat = fabs(r.Zp) < kFlatZ;
     const double inf = __builtin_huge_val();
+    const double invZp = flat ? 0.0 : rcp64(r.Zp);
     double t = r.t0, tx = inf, ty = inf, tz = inf;
     int ix = 0, iy = 0, mx = 0, my = 0, cz = 0;
     int ccx = -1, ccy = -1, ccz = -1;
     uint32_t cg = 0;
     auto slice_t = [&](int c) -> double {
         if (flat) return inf;
-        if (fwd) return c + 1 < V.gnz ? ((double)s_gz[c + 1] - F.Z0) / r.Zp : inf;
-        return c > 0 ? ((double)s_gz[c] - F.Z0) / r.Zp : inf;
+        if (fwd) return c + 1 < V.gnz ? ((double)s_gz[c + 1] - F.Z0) * invZp : inf;
+        return c > 0 ? ((double)s_gz[c] - F.Z0) * invZp : inf;
     };
     auto locate = [&](double tt) {
         const double z = F.Z0 + tt * r.Zp;
@@ -443,8 +465,8 @@ VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, in
         iy = cell_of((F.Y0 + tt * r.Yp) / z, HO, sy);
         mx = sx > 0 ? ix + 1 : ix;
         my = sy > 0 ? iy + 1 : iy;
-        tx = (sx != 0 && mx > 0 && mx < WO) ? line_t(mx, WO, F.X0, r.Xp, F.Z0, r.Zp) : inf;
-        ty = (sy != 0 && my > 0 && my < HO) ? line_t(my, HO, F.Y0, r.Yp, F.Z0, r.Zp) : inf;
+        tx = (sx != 0 && mx > 0 && mx < WO) ? line_t(mx, V.dcx, F.X0, r.Xp, F.Z0, r.Zp) : inf;
+        ty = (sy != 0 && my > 0 && my < HO) ? line_t(my, V.dcy, F.Y0, r.Yp, F.Z0, r.Zp) : inf;
         if constexpr (ESS) {
             cz = slice_of(s_gz, V.gnz, z, fwd);
             tz = slice_t(cz);
@@ -463,7 +485,7 @@ VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, in
                 cz += fwd ? 1 : -1;
                 tz = slice_t(cz);
             }
-            const int cx = ix / gk, cy = iy / gk;
+            const int cx = (int)((float)ix * V.inv_gk), cy = (int)((float)iy * V.inv_gk);
             if (cx != ccx || cy != ccy || cz != ccz) {
                 cg = V.grid[((uint64_t)cz * V.GH + cy) * V.GW + cx];
                 ccx = cx;
@@ -475,11 +497,11 @@ VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, in
                 double te = fmin(tz, r.t1);
                 if (sx != 0) {
                     const int m = sx > 0 ? min((cx + 1) * gk, WO) : cx * gk;
-                    if (m > 0 && m < WO) te = fmin(te, line_t(m, WO, F.X0, r.Xp, F.Z0, r.Zp));
+                    if (m > 0 && m < WO) te = fmin(te, line_t(m, V.dcx, F.X0, r.Xp, F.Z0, r.Zp));
                 }
                 if (sy != 0) {
                     const int m = sy > 0 ? min((cy + 1) * gk, HO) : cy * gk;
-                    if (m > 0 && m < HO) te = fmin(te, line_t(m, HO, F.Y0, r.Yp, F.Z0, r.Zp));
+                    if (m > 0 && m < HO) te = fmin(te, line_t(m, V.dcy, F.Y0, r.Yp, F.Z0, r.Zp));
                 }
                 if (te > t) {
                     t = te;
@@ -495,14 +517,14 @@ VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, in
         const int nx = stepx ? ix + sx : ix, ny = stepx ? iy : iy + sy;
         const bool more = tn < r.t1 && (unsigned)nx < (unsigned)WO && (unsigned)ny < (unsigned)HO;
         const int n_next = more ? V.count[(uint64_t)ny * WO + nx] : 0;
-        if (tn > t && do_list<FMT, SEARCH, COUNT>(V, F, ix, iy, n, t, tn, F.Z0, r.Zp, A, p, cnt)) break;
+        if (tn > t && do_list<FMT, SEARCH, COUNT>(V, F, ix, iy, n, t, tn, F.Z0, r.Zp, invZp, A, p, cnt)) break;
         if (!more) break;
         if (stepx) {
             mx += sx;
-            tx = (mx > 0 && mx < WO) ? line_t(mx, WO, F.X0, r.Xp, F.Z0, r.Zp) : inf;
+            tx = (mx > 0 && mx < WO) ? line_t(mx, V.dcx, F.X0, r.Xp, F.Z0, r.Zp) : inf;
         } else {
             my += sy;
-            ty = (my > 0 && my < HO) ? line_t(my, HO, F.Y0, r.Yp, F.Z0, r.Zp) : inf;
+            ty = (my > 0 && my < HO) ? line_t(my, V.dcy, F.Y0, r.Yp, F.Z0, r.Zp) : inf;
         }
         ix = nx;
         iy = ny;
@@ -529,6 +551,7 @@ VDI_HD float4 trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, 
         const bool fwd = r.Zp >= 0.0;
         const bool flat = fabs(r.Zp) < kFlatZ;
         const double inf = __builtin_huge_val();
+        const double invZp = flat ? 0.0 : rcp64(r.Zp);
         const double inv_k2 = 1.0 / (double)(k * k);
         const float2 *__restrict__ dep = V.depth;
         const uint64_t plane = V.plane;
@@ -537,19 +560,19 @@ VDI_HD float4 trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, 
         double tx, ty, tz;
         auto locate = [&](double tt) {
             const double z = F.Z0 + tt * r.Zp;
-            cx = cell_of((F.X0 + tt * r.Xp) / z, WO, sx) / k;
-            cy = cell_of((F.Y0 + tt * r.Yp) / z, HO, sy) / k;
+            cx = (int)((float)cell_of((F.X0 + tt * r.Xp) / z, WO, sx) * V.inv_gk);
+            cy = (int)((float)cell_of((F.Y0 + tt * r.Yp) / z, HO, sy) * V.inv_gk);
             cz = slice_of(s_gz, V.gnz, z, fwd);
             mx = sx > 0 ? min((cx + 1) * k, WO) : cx * k;
             my = sy > 0 ? min((cy + 1) * k, HO) : cy * k;
-            tx = (sx != 0 && mx > 0 && mx < WO) ? line_t(mx, WO, F.X0, r.Xp, F.Z0, r.Zp) : inf;
-            ty = (sy != 0 && my > 0 && my < HO) ? line_t(my, HO, F.Y0, r.Yp, F.Z0, r.Zp) : inf;
+            tx = (sx != 0 && mx > 0 && mx < WO) ? line_t(mx, V.dcx, F.X0, r.Xp, F.Z0, r.Zp) : inf;
+            ty = (sy != 0 && my > 0 && my < HO) ? line_t(my, V.dcy, F.Y0, r.Yp, F.Z0, r.Zp) : inf;
             if (flat)
                 tz = inf;
             else if (fwd)
-                tz = cz + 1 < V.gnz ? ((double)s_gz[cz + 1] - F.Z0) / r.Zp : inf;
+                tz = cz + 1 < V.gnz ? ((double)s_gz[cz + 1] - F.Z0) * invZp : inf;
             else
-                tz = cz > 0 ? ((double)s_gz[cz] - F.Z0) / r.Zp : inf;
+                tz = cz > 0 ? ((double)s_gz[cz] - F.Z0) * invZp : inf;
         };
         locate(t);
         int p = -1;
@@ -567,9 +590,9 @@ VDI_HD float4 trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, 
                     const double h = (tn - t) / n;
                     for (int q = 0; q < n; ++q) {
                         const double u = t + (q + 0.5) * h;
-                        const double z = F.Z0 + u * r.Zp;
-                        const int lx = min(max((int)floor(((F.X0 + u * r.Xp) / z + 1.0) * WO / 2.0), 0), WO - 1);
-                        const int ly = min(max((int)floor(((F.Y0 + u * r.Yp) / z + 1.0) * HO / 2.0), 0), HO - 1);
+                        const double z = F.Z0 + u * r.Zp, iz = rcp64(z);
+                        const int lx = min(max((int)floor(((F.X0 + u * r.Xp) * iz + 1.0) * (0.5 * WO)), 0), WO - 1);
+                        const int ly = min(max((int)floor(((F.Y0 + u * r.Yp) * iz + 1.0) * (0.5 * HO)), 0), HO - 1);
                         const uint64_t li = (uint64_t)ly * WO + lx;
                         const int nl = V.count[li];
                         if (nl == 0) continue;
@@ -580,7 +603,7 @@ VDI_HD float4 trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, 
                         p = j;
                         if ((double)fb.x > z) continue;
                         const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * plane + li, V.fmt);
-                        composite(A, c, (float)h * list_cos(V, lx, ly) / (fb.y - fb.x));
+                        composite(A, c, (float)h * list_cos(V, lx, ly) * rcp32(fb.y - fb.x));
                         if (A.T <= kTTerm) {
                             done = true;
                             break;
@@ -592,17 +615,17 @@ VDI_HD float4 trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, 
             if (tx <= ty && tx <= tz) {
                 cx += sx;
                 mx = sx > 0 ? min((cx + 1) * k, WO) : cx * k;
-                tx = (mx > 0 && mx < WO) ? line_t(mx, WO, F.X0, r.Xp, F.Z0, r.Zp) : inf;
+                tx = (mx > 0 && mx < WO) ? line_t(mx, V.dcx, F.X0, r.Xp, F.Z0, r.Zp) : inf;
             } else if (ty <= tz) {
                 cy += sy;
                 my = sy > 0 ? min((cy + 1) * k, HO) : cy * k;
-                ty = (my > 0 && my < HO) ? line_t(my, HO, F.Y0, r.Yp, F.Z0, r.Zp) : inf;
+                ty = (my > 0 && my < HO) ? line_t(my, V.dcy, F.Y0, r.Yp, F.Z0, r.Zp) : inf;
             } else {
                 cz += fwd ? 1 : -1;
                 if (fwd)
-                    tz = cz + 1 < V.gnz ? ((double)s_gz[cz + 1] - F.Z0) / r.Zp : inf;
+                    tz = cz + 1 < V.gnz ? ((double)s_gz[cz + 1] - F.Z0) * invZp : inf;
                 else
-                    tz = cz > 0 ? ((double)s_gz[cz] - F.Z0) / r.Zp : inf;
+                    tz = cz > 0 ? ((double)s_gz[cz] - F.Z0) * invZp : inf;
             }
             t = fmax(t, tn);
             if ((unsigned)cx >= (unsigned)V.GW || (unsigned)cy >= (unsigned)V.GH || (unsigned)cz >= (unsigned)V.gnz)
