@@ -31,7 +31,7 @@ W, H = 1920, 1080
 ANGLES = [5.0 * i for i in range(10)]
 MODES = [(1.0, 0.0), (2.0, 2.0), (4.0, 2.0)]
 METRIC = "VDI render Mpixels/s + HBM GB/s fraction; p50/p99 frame latency (served)"
-KERNEL_SRC = os.path.join(ROOT, "paper_2206_08660_amd", "csrc", "vdi_kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2206_08660_amd", "csrc", f) for f in ("vdi_kernels.hip", "vdi_trace.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_exact_1080p_traffic.json")
 
 
@@ -53,7 +53,11 @@ def parse():
 
 
 def kernel_hash() -> str:
-    return hashlib.sha1(open(KERNEL_SRC, "rb").read()).hexdigest()[:12]
+    """Hash of the render kernel's sources: stored counter figures apply only while it matches."""
+    h = hashlib.sha1()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:12]
 
 
 def main():
