@@ -220,11 +220,8 @@ def precision_leg(src, cams, out, exact_ms, torch, V):
 
 
 def served_leg(torch, V):
-    """Continuous-batching server (filled in by the serving module when built)."""
-    try:
-        from paper_2206_08660_amd import serve
-    except ImportError:
-        return None
+    """The continuous-batching server against one request at a time."""
+    from paper_2206_08660_amd import serve
     return serve.benchmark(log=log)
 
 

@@ -82,7 +82,8 @@ typedef struct {
  *   rgba_fmt_store      format kept in device memory (conversion from float32
  *                       rounds to nearest even).
  *   grid_k, grid_nz     empty-space grid (Section 4.3): cells of grid_k x grid_k
- *                       lists by one depth slice; grid_k 1..16, grid_nz 1..64.
+ *                       lists by one depth slice; grid_k 1..16, grid_nz 1..64,
+ *                       and fewer than 2^31 cells in all.
  *   grid_z  [grid_nz + 1] increasing float32 slice boundaries (linear V_O depth),
  *           or NULL to use grid_nz equal slices over the AABB corners' depth range.
  *   validate  non-zero: check every list (f < b, sorted, non-overlapping,
@@ -192,20 +193,27 @@ uint64_t vdi_plane_bytes(int32_t width, int32_t height, int32_t n_s, int32_t rgb
 const char *vdi_last_error(void);
 
 /* ------------------------------------------------------------------------
- * Serving (continuous batching).  A server owns one persistent kernel that
- * renders requests for any number of resident VDIs.  Requests are admitted
- * while slots and the device-memory budget allow; the work of admitted
- * requests of different resolution, viewpoint and preview level is spread over
- * the same running kernel as it arrives, and each request completes on its
- * own.  A request's image is identical to vdi_render's with the same arguments.
+ * Serving (continuous batching; a build addition, the paper's client renders
+ * one request at a time, Section 5).  A server renders requests for any
+ * number of resident VDIs.  Requests are admitted while request slots and the
+ * device-memory budget allow, and queued.  A scheduler thread owned by the
+ * server launches everything queued as one batch as soon as one of its
+ * streams is free: one kernel launch per (mode, colour format) group covers
+ * the tiles of all the group's requests, whatever their resolution,
+ * viewpoint and preview level, and one more upsamples those with D_I > 1.
+ * With two or more streams the next batch starts while the previous one
+ * drains.  A request is done when its batch is.  A request's image is
+ * identical to vdi_render's with the same arguments.
  * ------------------------------------------------------------------------ */
 typedef struct vdi_server_s *vdi_server_t;
 
 typedef struct {
     uint64_t submitted, completed, rejected_budget, rejected_slots;
     uint64_t bytes_in_flight, peak_bytes_in_flight;
-    int32_t inflight, peak_inflight;
-    int32_t kernel_running; /* 1 while the persistent kernel is resident */
+    uint64_t batches;       /* batches launched so far */
+    int32_t inflight, peak_inflight;  /* admitted and not yet done */
+    int32_t queued;         /* admitted, waiting for a free stream */
+    int32_t peak_batch;     /* most requests in one batch */
 } vdi_server_stats;
 
 /*
@@ -213,29 +221,34 @@ typedef struct {
  *   hbm_budget_bytes  admission budget for the memory of requests in flight
  *                     (output images plus preview scratch), > 0.
  *   max_inflight      request slots, 1..4096.
- *   workers           workgroups of the persistent kernel (0: one per compute unit x 4).
- * The kernel is launched on a stream of its own and runs until vdi_server_destroy.
+ *   streams           batches in flight at once, each on a stream of the
+ *                     server's own (0: two; at most 8).
+ * Returns VDI_ERR_ARG for arguments out of range and VDI_ERR_HIP / VDI_ERR_OOM
+ * when a stream, event, job table or the scheduler thread cannot be created.
  */
-int vdi_server_create(uint64_t hbm_budget_bytes, int32_t max_inflight, int32_t workers, vdi_server_t *out);
+int vdi_server_create(uint64_t hbm_budget_bytes, int32_t max_inflight, int32_t streams, vdi_server_t *out);
 
 /*
  * Submit a render request (same arguments as vdi_render).  Returns VDI_OK with
  * *ticket set, or VDI_ERR_BUDGET when the request does not fit the budget or
  * the free slots right now (nothing is queued; submit again later).  `out` is
- * a device pointer the caller keeps alive until the request is done.
+ * a device pointer the caller keeps alive until the request is done.  The
+ * server's streams do not wait for other streams: the VDI and `out` must be
+ * ready (their writers finished) when the request is submitted.
  */
 int vdi_server_submit(vdi_server_t s, vdi_t v, const vdi_camera *cam_VN, int32_t width, int32_t height, float D_I,
                       float D_R, float *out, uint64_t *ticket);
 
-/* *done = 1 once the request's image is complete and visible to later work. */
+/* *done = 1 once the request's image is complete and visible to later work.
+ * A failed batch (a HIP error) makes this and every later call return VDI_ERR_HIP. */
 int vdi_server_poll(vdi_server_t s, uint64_t ticket, int *done);
 
-/* Block until all admitted requests are done. */
+/* Block until all admitted requests are done (VDI_ERR_STATE after 60 s). */
 int vdi_server_drain(vdi_server_t s);
 
 int vdi_server_get_stats(vdi_server_t s, vdi_server_stats *stats);
 
-/* Drain, stop the persistent kernel, free everything.  NULL is a no-op. */
+/* Drain, stop the scheduler, free everything.  NULL is a no-op. */
 int vdi_server_destroy(vdi_server_t s);
 
 #ifdef __cplusplus

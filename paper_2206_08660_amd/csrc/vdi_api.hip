@@ -255,7 +255,7 @@ uint64_t vdi_plane_bytes(int32_t width, int32_t height, int32_t n_s, int32_t fmt
     if (width < 1 || height < 1 || n_s < 1) return 0;
     const uint64_t plane = (uint64_t)width * height;
     const uint64_t colour = fmt == VDI_F32 ? 16 : 8;
-    return plane + plane * (uint64_t)n_s * (8 + colour);
+    return plane + vdi::plane_elems(plane, n_s) * (8 + colour);
 }
 
 int vdi_lowres_size(int32_t width, int32_t height, float D_I, int32_t *w, int32_t *h)
@@ -281,6 +281,10 @@ int vdi_create(const vdi_desc *d, vdi_t *out)
         return fail(VDI_ERR_ARG, "16-bit colour input must be stored in the same format");
     if (d->grid_k < 1 || d->grid_k > VDI_MAX_GRID_K || d->grid_nz < 1 || d->grid_nz > VDI_MAX_GRID_NZ)
         return fail(VDI_ERR_ARG, "grid shape out of range (k 1..16, nz 1..64)");
+    // Cell indices are 32-bit in the kernels.
+    if ((uint64_t)d->grid_nz * ((d->width + d->grid_k - 1) / d->grid_k) * ((d->height + d->grid_k - 1) / d->grid_k) >=
+        (1ull << 31))
+        return fail(VDI_ERR_ARG, "count grid too large (needs fewer than 2^31 cells)");
     if (!finite3(d->aabb_min) || !finite3(d->aabb_max)) return fail(VDI_ERR_ARG, "non-finite AABB");
     for (int a = 0; a < 3; ++a)
         if (!(d->aabb_max[a] > d->aabb_min[a])) return fail(VDI_ERR_ARG, "empty AABB");
@@ -353,34 +357,40 @@ int vdi_create(const vdi_desc *d, vdi_t *out)
         free_vdi(v);
         return code;
     };
+    const uint64_t elems = vdi::plane_elems(plane, (int)ns);
+    D.sstride = vdi::kBrick ? (uint64_t)vdi::kBrick : plane;
     if ((e = hipMalloc((void **)&v->d_count, plane)) != hipSuccess) return bail(e, "hipMalloc count");
-    if ((e = hipMalloc((void **)&v->d_depth, plane * ns * sizeof(float2))) != hipSuccess) return bail(e, "hipMalloc depth");
-    if ((e = hipMalloc(&v->d_rgba, plane * ns * colour)) != hipSuccess) return bail(e, "hipMalloc rgba");
+    if ((e = hipMalloc((void **)&v->d_depth, elems * sizeof(float2))) != hipSuccess) return bail(e, "hipMalloc depth");
+    if ((e = hipMalloc(&v->d_rgba, elems * colour)) != hipSuccess) return bail(e, "hipMalloc rgba");
     if ((e = hipMalloc((void **)&v->d_grid, grid_bytes)) != hipSuccess) return bail(e, "hipMalloc grid");
     if ((e = hipMalloc((void **)&v->d_gz, gz.size() * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc grid_z");
     if ((e = hipMemcpy(v->d_count, d->count, plane, hipMemcpyHostToDevice)) != hipSuccess) return bail(e, "upload count");
-    if ((e = hipMemcpy(v->d_depth, d->depth, plane * ns * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
-        return bail(e, "upload depth");
     if ((e = hipMemcpy(v->d_gz, gz.data(), gz.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
         return bail(e, "upload grid_z");
-    if (d->rgba_fmt_in == d->rgba_fmt_store) {
-        if ((e = hipMemcpy(v->d_rgba, d->rgba, plane * ns * colour, hipMemcpyHostToDevice)) != hipSuccess)
-            return bail(e, "upload rgba");
-    } else {
-        // float32 -> 16-bit on the device, through a bounded staging buffer.
-        const uint64_t total = plane * ns, chunk = std::min<uint64_t>(total, 16ull << 20);
-        float4 *stage = nullptr;
-        if ((e = hipMalloc((void **)&stage, chunk * sizeof(float4))) != hipSuccess) return bail(e, "hipMalloc staging");
-        for (uint64_t off = 0; off < total && e == hipSuccess; off += chunk) {
-            const uint64_t n = std::min(chunk, total - off);
-            e = hipMemcpy(stage, static_cast<const float4 *>(d->rgba) + off, n * sizeof(float4), hipMemcpyHostToDevice);
-            if (e == hipSuccess)
-                e = vdi::launch_convert_rgba(stage, static_cast<uint2 *>(v->d_rgba) + off, n, d->rgba_fmt_store, 0);
-            if (e == hipSuccess) e = hipDeviceSynchronize();
+    {
+        // Whole slot planes go through a bounded staging buffer and are
+        // scattered into storage order (colour converted on the way).
+        const size_t colour_in = d->rgba_fmt_in == VDI_F32 ? 16 : 8;
+        const uint64_t per_chunk = std::max<uint64_t>(1, (256ull << 20) / (plane * 16));
+        const uint64_t slots = std::min<uint64_t>(ns, per_chunk);
+        void *stage = nullptr;
+        if ((e = hipMalloc(&stage, slots * plane * 16)) != hipSuccess) return bail(e, "hipMalloc staging");
+        for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+            const bool dep = pass == 0;
+            const size_t esz = dep ? sizeof(float2) : colour_in;
+            const char *src = static_cast<const char *>(dep ? (const void *)d->depth : d->rgba);
+            for (uint64_t j0 = 0; j0 < ns && e == hipSuccess; j0 += slots) {
+                const uint64_t nj = std::min(slots, ns - j0);
+                e = hipMemcpy(stage, src + j0 * plane * esz, nj * plane * esz, hipMemcpyHostToDevice);
+                if (e == hipSuccess)
+                    e = vdi::launch_scatter_slots(stage, d->rgba_fmt_in, dep ? (void *)v->d_depth : v->d_rgba,
+                                                  d->rgba_fmt_store, dep, nj * plane, D, (int32_t)j0, 0);
+                if (e == hipSuccess) e = hipDeviceSynchronize();
+            }
         }
         const hipError_t ef = hipFree(stage);
         if (e == hipSuccess) e = ef;
-        if (e != hipSuccess) return bail(e, "colour conversion");
+        if (e != hipSuccess) return bail(e, "upload planes");
     }
     D.count = v->d_count;
     D.depth = v->d_depth;
@@ -392,7 +402,7 @@ int vdi_create(const vdi_desc *d, vdi_t *out)
     uint64_t total = 0;
     for (uint64_t li = 0; li < plane; ++li) total += d->count[li];
     v->supersegments = total;
-    v->device_bytes = plane + plane * ns * (sizeof(float2) + colour) + grid_bytes + gz.size() * sizeof(float);
+    v->device_bytes = plane + elems * (sizeof(float2) + colour) + grid_bytes + gz.size() * sizeof(float);
     *out = v;
     return VDI_OK;
 }

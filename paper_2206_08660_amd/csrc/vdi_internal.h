@@ -12,17 +12,46 @@ namespace vdi {
 constexpr float kTTerm = 1e-5f;
 // |F_O . d| below this: the ray keeps a constant V_O depth.
 constexpr double kFlatZ = 1e-12;
+// A workgroup renders a tile of kTileW x kTileH rays; MI355X has kXcds XCDs,
+// which take the workgroups of a launch in turn.
+constexpr int kTileW = 64;
+constexpr int kTileH = 4;
+constexpr int kXcds = 8;
 
-// A resident VDI as the kernels see it.  Planes are slot-major: slot j of
-// list li lives at index j * plane + li, so one wavefront reading slot j of
-// 64 neighbouring lists touches contiguous memory.
+// Storage order of the depth and colour planes on the device.  Lists, taken
+// in row-major order, are grouped in bricks of kBrick; a brick stores slot 0
+// of its lists, then slot 1, and so on.  Slot j of list li is element
+// list_base(li) + j * kBrick, and a 128-byte line holds a few slots of a few
+// horizontally adjacent lists: the supersegments a ray meets next, whether it
+// runs along the list or across neighbouring lists.  kBrick = 0 keeps whole
+// slot planes (element j * WO * HO + li), the order of the input.
+#ifndef VDI_BRICK
+#define VDI_BRICK 4
+#endif
+constexpr int kBrick = VDI_BRICK;
+static_assert(kBrick == 0 || (kBrick & (kBrick - 1)) == 0, "brick width must be a power of two");
+
+__host__ __device__ inline uint64_t list_base(uint64_t li, int NS)
+{
+    if constexpr (kBrick == 0) return li;
+    return (li / kBrick) * ((uint64_t)NS * kBrick) + li % kBrick;
+}
+// Elements of one plane set (count of lists rounded up to whole bricks, times NS).
+__host__ __device__ inline uint64_t plane_elems(uint64_t lists, int NS)
+{
+    if constexpr (kBrick == 0) return lists * (uint64_t)NS;
+    return (lists + kBrick - 1) / kBrick * kBrick * (uint64_t)NS;
+}
+
+// A resident VDI as the kernels see it.
 struct DevVDI {
     int32_t WO, HO, NS;
     int32_t fmt;
     uint64_t plane;            // WO * HO
+    uint64_t sstride;          // element distance between slots j and j + 1 of a list
     const uint8_t *count;      // [HO][WO]
-    const float2 *depth;       // [NS][HO][WO] (f, b)
-    const void *rgba;          // [NS][HO][WO] float4 or 4 x 16-bit
+    const float2 *depth;       // (f, b), plane_elems(plane, NS) in brick order
+    const void *rgba;          // same order; float4 or 4 x 16-bit
     const uint32_t *grid;      // [gnz][GH][GW]
     int32_t gk, gnz, GW, GH;
     const float *gz;           // [gnz + 1] slice boundaries (device)
@@ -49,6 +78,23 @@ struct Frame {
     // counters (instrumented kernel only)
     uint8_t *touched_lists, *touched_slots;
     int32_t *ray_stats;
+};
+
+// One request of a batched launch (served form).  Blocks [tile0, tile0 +
+// ntiles) of the launch render its tiles; tile0 is a multiple of the XCD
+// count, so a block's XCD is the same as in a launch of its own.
+struct BatchJob {
+    DevVDI V;
+    Frame F;                   // rays on F.W x F.H, writing F.out
+    uint32_t tile0, ntiles;
+};
+
+// Bilinear upsampling of one request's low-resolution image in a batched launch.
+struct UpsampleJob {
+    const float4 *lo;          // [h][w]
+    float4 *out;               // [H][W]
+    int32_t w, h, W, H;
+    uint32_t tile0, ntiles;    // blocks of 64 x 4 output pixels
 };
 
 }  // namespace vdi
@@ -85,6 +131,15 @@ hipError_t launch_render_preview(const DevVDI &v, const Frame &f, hipStream_t st
 hipError_t launch_upsample(const float4 *lo, int32_t w, int32_t h, float4 *out, int32_t W, int32_t H,
                            hipStream_t stream);
 hipError_t launch_grid_build(const DevVDI &v, uint32_t *grid, hipStream_t stream);
-hipError_t launch_convert_rgba(const float4 *src, void *dst, uint64_t n, int32_t fmt, hipStream_t stream);
+// n elements of slot-major input planes, starting at slot j0 (n a multiple of
+// v.plane), into v's storage order; colour converted from fmt_in to fmt_store.
+hipError_t launch_scatter_slots(const void *src, int32_t fmt_in, void *dst, int32_t fmt_store, bool depth, uint64_t n,
+                                const DevVDI &v, int32_t j0, hipStream_t stream);
+// Batched launches: `jobs` is a device array of njobs records sorted by
+// tile0, all of colour format fmt; nblocks covers the last job's tiles.
+// Exact jobs use the seeded search with empty-space skipping.
+hipError_t launch_batch_render(const BatchJob *jobs, int32_t njobs, uint32_t nblocks, int32_t fmt, bool preview,
+                               hipStream_t stream);
+hipError_t launch_batch_upsample(const UpsampleJob *jobs, int32_t njobs, uint32_t nblocks, hipStream_t stream);
 
 }  // namespace vdi

@@ -6,11 +6,13 @@
 // Execution model.  One lane per ray; a 256-lane workgroup covers a 64 x 4
 // pixel tile, so each wavefront is 64 horizontally adjacent rays.  Their
 // projected lines in V_O are near-parallel and offset by about one list, so
-// at any step the wavefront reads the same slot of neighbouring lists: with
-// slot-major planes those loads coalesce, and lists revisited by the
-// neighbouring rays are served from L1/L2 (the paper's spatial smoothness).
-// Tiles are dealt to the 8 XCDs in interleaved bands of rows (xcd_tile), so
-// neighbouring tiles share an L2 and every XCD gets part of the image centre.
+// neighbouring lanes read the same or neighbouring lists at similar depths.
+// The planes are stored in bricks of four horizontally adjacent lists (see
+// list_base), so one 128-byte line holds several slots of several
+// neighbouring lists, and lists revisited by neighbouring rays are served from
+// L1/L2 (the paper's spatial smoothness).  Tiles are dealt to the 8 XCDs in
+// interleaved bands of rows (xcd_tile), so neighbouring tiles share an L2 and
+// every XCD gets part of the image centre.
 //
 // Precision.  Ray set-up, list crossings and supersegment overlaps run in
 // FP64 (the crossing depth of a ray with a list edge is ill-conditioned near
@@ -25,8 +27,16 @@
 namespace vdi {
 namespace {
 
+// The exact kernel is bound by the latency of its dependent loads (count ->
+// depth pair -> colour per list crossed): it is compiled for at least 6
+// wavefronts per SIMD (at most 80 VGPRs), which it reaches without spilling.
+#ifndef VDI_EXACT_WAVES
+#define VDI_EXACT_WAVES 6
+#endif
+#define VDI_EXACT_OCC __attribute__((amdgpu_waves_per_eu(VDI_EXACT_WAVES)))
+
 template <int FMT, int SEARCH, bool ESS, bool COUNT>
-__global__ __launch_bounds__(kBlock) void k_render_exact(DevVDI V, Frame F)
+__global__ __launch_bounds__(kBlock) VDI_EXACT_OCC void k_render_exact(DevVDI V, Frame F)
 {
     __shared__ float s_gz[VDI_MAX_GRID_NZ + 1];
     if constexpr (ESS) {
@@ -63,6 +73,60 @@ __global__ __launch_bounds__(kBlock) void k_render_preview(DevVDI V, Frame F)
 }
 
 // ---------------------------------------------------------------------------
+// Batched launches (served form).  Block b belongs to the last job whose
+// tile0 <= b; the job table is read-only for the launch, so its uniform
+// loads go through the scalar cache like kernel arguments.  Inside a job the
+// block renders exactly what k_render_exact / k_render_preview would.
+// ---------------------------------------------------------------------------
+template <typename J>
+__device__ __forceinline__ const J &job_of(const J *__restrict__ jobs, int njobs, uint32_t b)
+{
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].tile0 <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return jobs[lo];
+}
+
+template <int FMT, bool PREVIEW>
+__global__ __launch_bounds__(kBlock) VDI_EXACT_OCC void k_render_batch(const BatchJob *__restrict__ jobs, int njobs)
+{
+    __shared__ float s_gz[VDI_MAX_GRID_NZ + 1];
+    const BatchJob &J = job_of(jobs, njobs, blockIdx.x);
+    const uint32_t local = blockIdx.x - J.tile0;
+    if (local >= J.ntiles) return;  // padding block: the whole workgroup leaves
+    for (int i = threadIdx.x; i <= J.V.gnz; i += kBlock) s_gz[i] = J.V.gz[i];
+    __syncthreads();
+    const int tiles_x = (J.F.W + kTileW - 1) / kTileW, tiles_y = (J.F.H + kTileH - 1) / kTileH;
+    const int tile = xcd_tile((int)local, tiles_x, tiles_y);
+    const int px = (tile % tiles_x) * kTileW + (threadIdx.x % kTileW);
+    const int py = (tile / tiles_x) * kTileH + (threadIdx.x / kTileW);
+    if (px >= J.F.W || py >= J.F.H) return;
+    float4 o;
+    if constexpr (PREVIEW) {
+        o = trace_preview<FMT>(J.V, J.F, s_gz, px, py);
+    } else {
+        Counters cnt = {0, 0};
+        o = trace_exact<FMT, VDI_SEARCH_SEEDED, true, false>(J.V, J.F, s_gz, px, py, cnt);
+    }
+    J.F.out[(uint64_t)py * J.F.W + px] = o;
+}
+
+__global__ __launch_bounds__(256) void k_upsample_batch(const UpsampleJob *__restrict__ jobs, int njobs)
+{
+    const UpsampleJob &J = job_of(jobs, njobs, blockIdx.x);
+    const uint32_t local = blockIdx.x - J.tile0;
+    if (local >= J.ntiles) return;
+    const int tiles_x = (J.W + 63) / 64;
+    const int x = (int)(local % (uint32_t)tiles_x) * 64 + (int)(threadIdx.x & 63);
+    const int y = (int)(local / (uint32_t)tiles_x) * 4 + (int)(threadIdx.x >> 6);
+    if (x >= J.W || y >= J.H) return;
+    J.out[(uint64_t)y * J.W + x] = upsample_px(J.lo, J.w, J.h, J.W, J.H, x, y);
+}
+
+// ---------------------------------------------------------------------------
 // Bilinear upsampling, half-pixel centres, clamped (Section 4.4, Fig. 7)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_upsample(const float4 *__restrict__ lo, int w, int h,
@@ -90,10 +154,10 @@ __global__ __launch_bounds__(256) void k_grid_build(DevVDI V, uint32_t *__restri
     __syncthreads();
     const int lx = cx * k + (int)threadIdx.x % k, ly = cy * k + (int)threadIdx.x / k;
     if ((int)threadIdx.x < k * k && lx < V.WO && ly < V.HO) {
-        const uint64_t li = (uint64_t)ly * V.WO + lx;
+        const uint64_t li = (uint64_t)ly * V.WO + lx, lb = list_base(li, V.NS);
         const int n = V.count[li];
         for (int j = 0; j < n; ++j) {
-            const float2 fb = V.depth[(uint64_t)j * V.plane + li];
+            const float2 fb = V.depth[(uint64_t)j * V.sstride + lb];
             for (int c = 0; c < V.gnz; ++c)
                 if (fb.x < s_gz[c + 1] && fb.y > s_gz[c]) atomicAdd(&s_cnt[c], 1u);
         }
@@ -104,27 +168,36 @@ __global__ __launch_bounds__(256) void k_grid_build(DevVDI V, uint32_t *__restri
 }
 
 // ---------------------------------------------------------------------------
-// Colour storage conversion, float32 -> binary16 / bfloat16, round to nearest even
+// Upload: slots [j0, j0 + n / plane) of slot-major input planes are scattered
+// into the device's brick order, converting colour float32 -> binary16 /
+// bfloat16 (round to nearest even) where asked.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_convert(const float4 *__restrict__ src, uint2 *__restrict__ dst, uint64_t n,
-                                                 int fmt)
+__device__ inline uint2 to16(float4 v, int fmt)
+{
+    uint2 o;
+    if (fmt == VDI_F16) {
+        const __half2 rg = __floats2half2_rn(v.x, v.y), ba = __floats2half2_rn(v.z, v.w);
+        o.x = *reinterpret_cast<const uint32_t *>(&rg);
+        o.y = *reinterpret_cast<const uint32_t *>(&ba);
+    } else {
+        const __hip_bfloat16 r = __float2bfloat16(v.x), g = __float2bfloat16(v.y);
+        const __hip_bfloat16 b = __float2bfloat16(v.z), a = __float2bfloat16(v.w);
+        o.x = (uint32_t)(*reinterpret_cast<const uint16_t *>(&r)) | ((uint32_t)(*reinterpret_cast<const uint16_t *>(&g)) << 16);
+        o.y = (uint32_t)(*reinterpret_cast<const uint16_t *>(&b)) | ((uint32_t)(*reinterpret_cast<const uint16_t *>(&a)) << 16);
+    }
+    return o;
+}
+
+// S -> D element by element; CONV: store S as is, or a float4 as 16-bit format CONV.
+template <typename S, typename D, int CONV>
+__global__ __launch_bounds__(256) void k_scatter(const S *__restrict__ src, D *__restrict__ dst, uint64_t n,
+                                                 uint64_t plane, int NS, int j0, uint64_t sstride)
 {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-        const float4 v = src[i];
-        uint2 o;
-        if (fmt == VDI_F16) {
-            const __half2 rg = __floats2half2_rn(v.x, v.y), ba = __floats2half2_rn(v.z, v.w);
-            o.x = *reinterpret_cast<const uint32_t *>(&rg);
-            o.y = *reinterpret_cast<const uint32_t *>(&ba);
-        } else {
-            const __hip_bfloat16 r = __float2bfloat16(v.x), g = __float2bfloat16(v.y);
-            const __hip_bfloat16 b = __float2bfloat16(v.z), a = __float2bfloat16(v.w);
-            o.x = (uint32_t)(*reinterpret_cast<const uint16_t *>(&r)) |
-                  ((uint32_t)(*reinterpret_cast<const uint16_t *>(&g)) << 16);
-            o.y = (uint32_t)(*reinterpret_cast<const uint16_t *>(&b)) |
-                  ((uint32_t)(*reinterpret_cast<const uint16_t *>(&a)) << 16);
-        }
-        dst[i] = o;
+        const uint64_t j = j0 + i / plane, li = i % plane;
+        const uint64_t o = list_base(li, NS) + j * sstride;
+        if constexpr (CONV == 0) dst[o] = src[i];
+        else dst[o] = to16(src[i], CONV);
     }
 }
 
@@ -190,6 +263,32 @@ hipError_t launch_upsample(const float4 *lo, int32_t w, int32_t h, float4 *out, 
     return hipGetLastError();
 }
 
+hipError_t launch_batch_render(const BatchJob *jobs, int32_t njobs, uint32_t nblocks, int32_t fmt, bool preview,
+                               hipStream_t s)
+{
+    const dim3 g(nblocks);
+    if (preview) {
+        switch (fmt) {
+        case VDI_F16: k_render_batch<VDI_F16, true><<<g, kBlock, 0, s>>>(jobs, njobs); break;
+        case VDI_BF16: k_render_batch<VDI_BF16, true><<<g, kBlock, 0, s>>>(jobs, njobs); break;
+        default: k_render_batch<VDI_F32, true><<<g, kBlock, 0, s>>>(jobs, njobs); break;
+        }
+    } else {
+        switch (fmt) {
+        case VDI_F16: k_render_batch<VDI_F16, false><<<g, kBlock, 0, s>>>(jobs, njobs); break;
+        case VDI_BF16: k_render_batch<VDI_BF16, false><<<g, kBlock, 0, s>>>(jobs, njobs); break;
+        default: k_render_batch<VDI_F32, false><<<g, kBlock, 0, s>>>(jobs, njobs); break;
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_upsample(const UpsampleJob *jobs, int32_t njobs, uint32_t nblocks, hipStream_t s)
+{
+    k_upsample_batch<<<dim3(nblocks), 256, 0, s>>>(jobs, njobs);
+    return hipGetLastError();
+}
+
 hipError_t launch_grid_build(const DevVDI &v, uint32_t *grid, hipStream_t s)
 {
     const int threads = ((v.gk * v.gk + 63) / 64) * 64;
@@ -197,11 +296,28 @@ hipError_t launch_grid_build(const DevVDI &v, uint32_t *grid, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_convert_rgba(const float4 *src, void *dst, uint64_t n, int32_t fmt, hipStream_t s)
+hipError_t launch_scatter_slots(const void *src, int32_t fmt_in, void *dst, int32_t fmt_store, bool depth, uint64_t n,
+                                const DevVDI &v, int32_t j0, hipStream_t s)
 {
     const uint64_t blocks = (n + 255) / 256;
-    const unsigned g = (unsigned)(blocks < 65536 ? blocks : 65536);
-    k_convert<<<g, 256, 0, s>>>(src, reinterpret_cast<uint2 *>(dst), n, fmt);
+    const dim3 g((unsigned)(blocks < 65536 ? blocks : 65536));
+    const uint64_t plane = v.plane, st = v.sstride;
+    const int NS = v.NS;
+    if (depth)
+        k_scatter<float2, float2, 0><<<g, 256, 0, s>>>(static_cast<const float2 *>(src), static_cast<float2 *>(dst), n,
+                                                       plane, NS, j0, st);
+    else if (fmt_store == VDI_F32)
+        k_scatter<float4, float4, 0><<<g, 256, 0, s>>>(static_cast<const float4 *>(src), static_cast<float4 *>(dst), n,
+                                                       plane, NS, j0, st);
+    else if (fmt_in != VDI_F32)
+        k_scatter<uint2, uint2, 0><<<g, 256, 0, s>>>(static_cast<const uint2 *>(src), static_cast<uint2 *>(dst), n,
+                                                     plane, NS, j0, st);
+    else if (fmt_store == VDI_F16)
+        k_scatter<float4, uint2, VDI_F16><<<g, 256, 0, s>>>(static_cast<const float4 *>(src), static_cast<uint2 *>(dst),
+                                                            n, plane, NS, j0, st);
+    else
+        k_scatter<float4, uint2, VDI_BF16><<<g, 256, 0, s>>>(static_cast<const float4 *>(src), static_cast<uint2 *>(dst),
+                                                             n, plane, NS, j0, st);
     return hipGetLastError();
 }
 

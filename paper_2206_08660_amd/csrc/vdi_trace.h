@@ -37,10 +37,7 @@ __host__ inline float exp2_32(float x) { return exp2f(x); }
 __device__ inline float log2_32(float x) { return __builtin_amdgcn_logf(x); }
 __host__ inline float log2_32(float x) { return log2f(x); }
 
-constexpr int kTileW = 64;
-constexpr int kTileH = 4;
 constexpr int kBlock = kTileW * kTileH;
-constexpr int kXcds = 8;
 
 VDI_HD inline double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
@@ -199,22 +196,23 @@ VDI_HD inline int slice_of(const float *gz, int gnz, double z, bool fwd)
 // First-supersegment search (Section 4.2, supplement Alg. S2)
 // ---------------------------------------------------------------------------
 // Smallest j in [0, n) with b_j > z (n if none).  Back depths increase with j
-// because supersegments are sorted and disjoint.
+// because supersegments are sorted and disjoint.  Slot j of the list is
+// dep[base + j * stride].
 template <int SEARCH>
-VDI_HD inline int first_back_above(const float2 *__restrict__ dep, uint64_t plane, uint64_t li, int n,
+VDI_HD inline int first_back_above(const float2 *__restrict__ dep, uint64_t stride, uint64_t base, int n,
                                                 double z, int p)
 {
     if constexpr (SEARCH == VDI_SEARCH_LINEAR) {
         int j = 0;
-        while (j < n && (double)dep[(uint64_t)j * plane + li].y <= z) ++j;
+        while (j < n && (double)dep[(uint64_t)j * stride + base].y <= z) ++j;
         return j;
     }
     int lo = 0, hi = n;
     if constexpr (SEARCH == VDI_SEARCH_SEEDED) {
         if (p >= 0 && p < n) {
             // Both candidate back depths are fetched before either is compared.
-            const float b1 = dep[(uint64_t)p * plane + li].y;
-            const float b0 = p > 0 ? dep[(uint64_t)(p - 1) * plane + li].y : -__builtin_huge_valf();
+            const float b1 = dep[(uint64_t)p * stride + base].y;
+            const float b0 = p > 0 ? dep[(uint64_t)(p - 1) * stride + base].y : -__builtin_huge_valf();
             if ((double)b0 > z)
                 hi = p - 1;  // the answer is at most p-1
             else if ((double)b1 > z)
@@ -225,7 +223,7 @@ VDI_HD inline int first_back_above(const float2 *__restrict__ dep, uint64_t plan
     }
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if ((double)dep[(uint64_t)mid * plane + li].y > z)
+        if ((double)dep[(uint64_t)mid * stride + base].y > z)
             hi = mid;
         else
             lo = mid + 1;
@@ -236,19 +234,19 @@ VDI_HD inline int first_back_above(const float2 *__restrict__ dep, uint64_t plan
 // Largest j in [0, n) with f_j < z (-1 if none): the first supersegment met by
 // a ray travelling towards smaller depth.
 template <int SEARCH>
-VDI_HD inline int last_front_below(const float2 *__restrict__ dep, uint64_t plane, uint64_t li, int n,
+VDI_HD inline int last_front_below(const float2 *__restrict__ dep, uint64_t stride, uint64_t base, int n,
                                                 double z, int p)
 {
     if constexpr (SEARCH == VDI_SEARCH_LINEAR) {
         int j = n - 1;
-        while (j >= 0 && (double)dep[(uint64_t)j * plane + li].x >= z) --j;
+        while (j >= 0 && (double)dep[(uint64_t)j * stride + base].x >= z) --j;
         return j;
     }
     int lo = 0, hi = n;  // search the first j with f_j >= z
     if constexpr (SEARCH == VDI_SEARCH_SEEDED) {
         if (p >= 0 && p < n) {
-            const float f1 = dep[(uint64_t)p * plane + li].x;
-            const float f2 = p + 1 < n ? dep[(uint64_t)(p + 1) * plane + li].x : __builtin_huge_valf();
+            const float f1 = dep[(uint64_t)p * stride + base].x;
+            const float f2 = p + 1 < n ? dep[(uint64_t)(p + 1) * stride + base].x : __builtin_huge_valf();
             if ((double)f1 >= z)
                 hi = p;
             else if ((double)f2 >= z)
@@ -259,7 +257,7 @@ VDI_HD inline int last_front_below(const float2 *__restrict__ dep, uint64_t plan
     }
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if ((double)dep[(uint64_t)mid * plane + li].x >= z)
+        if ((double)dep[(uint64_t)mid * stride + base].x >= z)
             hi = mid;
         else
             lo = mid + 1;
@@ -290,7 +288,8 @@ struct Counters {
     int32_t lists, pieces;
 };
 
-VDI_HD inline float2 depth_at(const DevVDI &V, int j, uint64_t li) { return V.depth[(uint64_t)j * V.plane + li]; }
+// Depth pair of slot j of the list whose storage starts at lb (list_base).
+VDI_HD inline float2 depth_at(const DevVDI &V, int j, uint64_t lb) { return V.depth[(uint64_t)j * V.sstride + lb]; }
 
 // Composite the part of list (ix, iy) that a ray with dz/dt = Zp crosses
 // between parameters ta and tb (Sections 4.2, Eq. 2).  n is the list's count
@@ -313,11 +312,11 @@ VDI_HD bool do_list(const DevVDI &V, const Frame &F, int ix, int iy, int n, doub
     const double za = Z0 + ta * Zp, zb = Z0 + tb * Zp;
     const float cth = list_cos(V, ix, iy);
     const float2 *__restrict__ dep = V.depth;
-    const uint64_t plane = V.plane;
+    const uint64_t stride = V.sstride, lb = list_base(li, V.NS);
     auto piece = [&](int j, float2 d, float4 c, double zl, double zh, double inv) -> bool {
         composite(A, c, (float)((zh - zl) * inv) * cth * rcp32(d.y - d.x));
         if constexpr (COUNT) {
-            F.touched_slots[(uint64_t)j * plane + li] = 1;
+            F.touched_slots[(uint64_t)j * V.plane + li] = 1;
             ++cnt.pieces;
         }
         return A.T <= kTTerm;
@@ -328,10 +327,10 @@ VDI_HD bool do_list(const DevVDI &V, const Frame &F, int ix, int iy, int n, doub
         bool have = false;
         float2 d = make_float2(0.0f, 0.0f);
         if (SEARCH == VDI_SEARCH_SEEDED && p >= 0 && p < n) {
-            const float2 dp = depth_at(V, p, li);
-            const float2 dq = p > 0 ? depth_at(V, p - 1, li) : make_float2(-__builtin_huge_valf(), -__builtin_huge_valf());
+            const float2 dp = depth_at(V, p, lb);
+            const float2 dq = p > 0 ? depth_at(V, p - 1, lb) : make_float2(-__builtin_huge_valf(), -__builtin_huge_valf());
             if ((double)dq.y > za) {
-                j = first_back_above<VDI_SEARCH_BINARY>(dep, plane, li, p - 1, za, -1);
+                j = first_back_above<VDI_SEARCH_BINARY>(dep, stride, lb, p - 1, za, -1);
                 if (j == p - 1) {
                     d = dq;
                     have = true;
@@ -341,19 +340,19 @@ VDI_HD bool do_list(const DevVDI &V, const Frame &F, int ix, int iy, int n, doub
                 d = dp;
                 have = true;
             } else {
-                j = p + 1 + first_back_above<VDI_SEARCH_BINARY>(dep, plane, li + (uint64_t)(p + 1) * plane, n - p - 1,
+                j = p + 1 + first_back_above<VDI_SEARCH_BINARY>(dep, stride, lb + (uint64_t)(p + 1) * stride, n - p - 1,
                                                                  za, -1);
             }
         } else {
-            j = first_back_above<SEARCH>(dep, plane, li, n, za, -1);
+            j = first_back_above<SEARCH>(dep, stride, lb, n, za, -1);
         }
         int last = -1;
-        if (j < n && !have) d = depth_at(V, j, li);
+        if (j < n && !have) d = depth_at(V, j, lb);
         while (j < n) {
             if ((double)d.x >= zb) break;
-            const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * plane + li, V.fmt);
+            const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * stride + lb, V.fmt);
             const bool more = (double)d.y < zb && j + 1 < n;
-            const float2 dn = more ? depth_at(V, j + 1, li) : d;
+            const float2 dn = more ? depth_at(V, j + 1, lb) : d;
             const double zl = fmax(za, (double)d.x), zh = fmin(zb, (double)d.y);
             if (zh > zl) {
                 last = j;
@@ -374,28 +373,28 @@ VDI_HD bool do_list(const DevVDI &V, const Frame &F, int ix, int iy, int n, doub
         bool have = false;
         float2 d = make_float2(0.0f, 0.0f);
         if (SEARCH == VDI_SEARCH_SEEDED && p >= 0 && p < n) {
-            const float2 dp = depth_at(V, p, li);
-            const float2 dq = p + 1 < n ? depth_at(V, p + 1, li) : make_float2(__builtin_huge_valf(), __builtin_huge_valf());
+            const float2 dp = depth_at(V, p, lb);
+            const float2 dq = p + 1 < n ? depth_at(V, p + 1, lb) : make_float2(__builtin_huge_valf(), __builtin_huge_valf());
             if ((double)dp.x >= za) {
-                j = last_front_below<VDI_SEARCH_BINARY>(dep, plane, li, p, za, -1);
+                j = last_front_below<VDI_SEARCH_BINARY>(dep, stride, lb, p, za, -1);
             } else if ((double)dq.x >= za) {
                 j = p;
                 d = dp;
                 have = true;
             } else {
-                j = p + 2 + last_front_below<VDI_SEARCH_BINARY>(dep, plane, li + (uint64_t)(p + 2) * plane, n - p - 2,
+                j = p + 2 + last_front_below<VDI_SEARCH_BINARY>(dep, stride, lb + (uint64_t)(p + 2) * stride, n - p - 2,
                                                                  za, -1);
             }
         } else {
-            j = last_front_below<SEARCH>(dep, plane, li, n, za, -1);
+            j = last_front_below<SEARCH>(dep, stride, lb, n, za, -1);
         }
         int last = -1;
-        if (j >= 0 && !have) d = depth_at(V, j, li);
+        if (j >= 0 && !have) d = depth_at(V, j, lb);
         while (j >= 0) {
             if ((double)d.y <= zb) break;
-            const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * plane + li, V.fmt);
+            const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * stride + lb, V.fmt);
             const bool more = (double)d.x > zb && j > 0;
-            const float2 dn = more ? depth_at(V, j - 1, li) : d;
+            const float2 dn = more ? depth_at(V, j - 1, lb) : d;
             const double zl = fmax(zb, (double)d.x), zh = fmin(za, (double)d.y);
             if (zh > zl) {
                 last = j;
@@ -412,13 +411,13 @@ VDI_HD bool do_list(const DevVDI &V, const Frame &F, int ix, int iy, int n, doub
     } else {
         // Constant depth: the supersegment holding za covers the whole piece.
         for (int j = 0; j < n; ++j) {
-            const float2 d = depth_at(V, j, li);
+            const float2 d = depth_at(V, j, lb);
             if ((double)d.x <= za && za < (double)d.y) {
-                const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * plane + li, V.fmt);
+                const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * stride + lb, V.fmt);
                 p = j;
                 composite(A, c, (float)(tb - ta) * cth * rcp32(d.y - d.x));
                 if constexpr (COUNT) {
-                    F.touched_slots[(uint64_t)j * plane + li] = 1;
+                    F.touched_slots[(uint64_t)j * V.plane + li] = 1;
                     ++cnt.pieces;
                 }
                 return A.T <= kTTerm;
@@ -451,8 +450,10 @@ VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, in
     const double inf = __builtin_huge_val();
     const double invZp = flat ? 0.0 : rcp64(r.Zp);
     double t = r.t0, tx = inf, ty = inf, tz = inf;
-    int ix = 0, iy = 0, mx = 0, my = 0, cz = 0;
-    int ccx = -1, ccy = -1, ccz = -1;
+    // (ix, iy): current list; the next x (y) grid line crossed is ix + (sx > 0).
+    int ix = 0, iy = 0, cz = 0;
+    const int ox = sx > 0, oy = sy > 0;
+    int ccell = -1;  // grid cell whose count cg holds (fewer than 2^31 cells)
     uint32_t cg = 0;
     auto slice_t = [&](int c) -> double {
         if (flat) return inf;
@@ -463,8 +464,7 @@ VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, in
         const double z = F.Z0 + tt * r.Zp;
         ix = cell_of((F.X0 + tt * r.Xp) / z, WO, sx);
         iy = cell_of((F.Y0 + tt * r.Yp) / z, HO, sy);
-        mx = sx > 0 ? ix + 1 : ix;
-        my = sy > 0 ? iy + 1 : iy;
+        const int mx = ix + ox, my = iy + oy;
         tx = (sx != 0 && mx > 0 && mx < WO) ? line_t(mx, V.dcx, F.X0, r.Xp, F.Z0, r.Zp) : inf;
         ty = (sy != 0 && my > 0 && my < HO) ? line_t(my, V.dcy, F.Y0, r.Yp, F.Z0, r.Zp) : inf;
         if constexpr (ESS) {
@@ -486,11 +486,10 @@ VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, in
                 tz = slice_t(cz);
             }
             const int cx = (int)((float)ix * V.inv_gk), cy = (int)((float)iy * V.inv_gk);
-            if (cx != ccx || cy != ccy || cz != ccz) {
-                cg = V.grid[((uint64_t)cz * V.GH + cy) * V.GW + cx];
-                ccx = cx;
-                ccy = cy;
-                ccz = cz;
+            const int cell = (cz * V.GH + cy) * V.GW + cx;
+            if (cell != ccell) {
+                cg = V.grid[cell];
+                ccell = cell;
             }
             if (cg == 0u) {
                 // Empty-space skipping: cross the empty cell in one step.
@@ -520,10 +519,10 @@ VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, in
         if (tn > t && do_list<FMT, SEARCH, COUNT>(V, F, ix, iy, n, t, tn, F.Z0, r.Zp, invZp, A, p, cnt)) break;
         if (!more) break;
         if (stepx) {
-            mx += sx;
+            const int mx = nx + ox;
             tx = (mx > 0 && mx < WO) ? line_t(mx, V.dcx, F.X0, r.Xp, F.Z0, r.Zp) : inf;
         } else {
-            my += sy;
+            const int my = ny + oy;
             ty = (my > 0 && my < HO) ? line_t(my, V.dcy, F.Y0, r.Yp, F.Z0, r.Zp) : inf;
         }
         ix = nx;
@@ -554,7 +553,7 @@ VDI_HD float4 trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, 
         const double invZp = flat ? 0.0 : rcp64(r.Zp);
         const double inv_k2 = 1.0 / (double)(k * k);
         const float2 *__restrict__ dep = V.depth;
-        const uint64_t plane = V.plane;
+        const uint64_t stride = V.sstride;
         double t = r.t0;
         int cx, cy, cz, mx, my;
         double tx, ty, tz;
@@ -597,12 +596,13 @@ VDI_HD float4 trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, 
                         const int nl = V.count[li];
                         if (nl == 0) continue;
                         // Point location: the supersegment with f <= z < b.
-                        const int j = first_back_above<VDI_SEARCH_SEEDED>(dep, plane, li, nl, z, p);
+                        const uint64_t lb = list_base(li, V.NS);
+                        const int j = first_back_above<VDI_SEARCH_SEEDED>(dep, stride, lb, nl, z, p);
                         if (j >= nl) continue;
-                        const float2 fb = dep[(uint64_t)j * plane + li];
+                        const float2 fb = dep[(uint64_t)j * stride + lb];
                         p = j;
                         if ((double)fb.x > z) continue;
-                        const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * plane + li, V.fmt);
+                        const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * stride + lb, V.fmt);
                         composite(A, c, (float)h * list_cos(V, lx, ly) * rcp32(fb.y - fb.x));
                         if (A.T <= kTTerm) {
                             done = true;

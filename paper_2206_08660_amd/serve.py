@@ -3,12 +3,13 @@
 `Server` wraps the vdi_server_* calls of include/vdi.h.  `benchmark()` runs
 the served workload: four resident VDIs (two 1280x720 / N_S=20 and two
 1920x1080 / N_S=50, generating views 90 degrees apart, FP16 colour), 2000
-requests with Poisson arrivals at 600 requests/s, viewpoint deviation
-U[0, 30] degrees with random sign, output uniform over {1280x720 exact,
-1920x1080 exact, 1920x1080 D_I=2/D_R=2}, admission budget 64 GB.  The same
-trace is then rendered one request at a time with vdi_render for comparison.
-Arrival times are drawn in advance (open loop); a request's latency runs from
-its arrival to the moment the host sees it complete.
+requests with viewpoint deviation U[0, 30] degrees with random sign, output
+uniform over {1280x720 exact, 1920x1080 exact, 1920x1080 D_I=2/D_R=2},
+admission budget 64 GiB.  Arrivals are Poisson at 600 requests/s (latency)
+and then all at t = 0 (throughput at saturation).  Each trace is also
+rendered one request at a time with vdi_render for comparison.  Arrival
+times are drawn in advance (open loop); a request's latency runs from its
+arrival to the moment the host sees it complete.
 """
 from __future__ import annotations
 
@@ -27,9 +28,9 @@ OUTPUTS = [(1280, 720, 1.0, 0.0), (1920, 1080, 1.0, 0.0), (1920, 1080, 2.0, 2.0)
 class Server:
     """A continuous-batching server on the current device."""
 
-    def __init__(self, budget_bytes: int, max_inflight: int = 64, workers: int = 0):
+    def __init__(self, budget_bytes: int, max_inflight: int = 64, streams: int = 0):
         h = ctypes.c_void_p()
-        V._check(V.lib().vdi_server_create(int(budget_bytes), int(max_inflight), int(workers), ctypes.byref(h)))
+        V._check(V.lib().vdi_server_create(int(budget_bytes), int(max_inflight), int(streams), ctypes.byref(h)))
         self._h = h
 
     def submit(self, vdi: "V.Vdi", cam, width: int, height: int, d_i: float, d_r: float, out) -> Optional[int]:
@@ -94,15 +95,22 @@ def load_vdis(store: str = "f16", log: Callable = print):
     return srcs
 
 
-def run_served(handles, bases, trace, budget: int, max_inflight: int, log: Callable = print):
-    """Open-loop served run; returns (latencies [s], makespan [s], stats, outputs by request)."""
+def run_served(handles, bases, trace, budget: int, max_inflight: int, keep=(), log: Callable = print):
+    """Open-loop served run; returns (latencies [s], makespan [s], stats, {request: image} for `keep`).
+
+    Output images come from buffers allocated before the clock starts and
+    reused once their request is done; the images of the requests in `keep`
+    are retained instead."""
     import torch
 
     import inputs
     arrivals, which, yaw, outsel = trace
     n = len(arrivals)
-    bufs = {}
-    pool = {k: [] for k in range(len(OUTPUTS))}
+    keep = set(int(i) for i in keep)
+    counts = np.bincount(np.asarray(outsel, dtype=np.int64), minlength=len(OUTPUTS))
+    pool = {k: [torch.empty((OUTPUTS[k][1], OUTPUTS[k][0], 4), dtype=torch.float32, device="cuda")
+                for _ in range(min(max_inflight, int(counts[k])) + len(keep))] for k in range(len(OUTPUTS))}
+    torch.cuda.synchronize()
     lat = np.zeros(n)
     out_of = {}
     with Server(budget, max_inflight) as srv:
@@ -115,8 +123,10 @@ def run_served(handles, bases, trace, budget: int, max_inflight: int, log: Calla
             # admit every request that has arrived, while it fits
             while nxt < n and arrivals[nxt] <= now:
                 k = int(outsel[nxt])
+                if not pool[k]:
+                    break
                 W, H, di, dr = OUTPUTS[k]
-                buf = pool[k].pop() if pool[k] else torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
+                buf = pool[k].pop()
                 cam = inputs.orbit_camera(float(yaw[nxt]), bases[int(which[nxt])])
                 t = srv.submit(handles[int(which[nxt])], cam, W, H, di, dr, buf)
                 if t is None:
@@ -128,7 +138,10 @@ def run_served(handles, bases, trace, budget: int, max_inflight: int, log: Calla
                 if srv.poll(t):
                     i, k, buf = pending.pop(t)
                     lat[i] = (time.perf_counter() - t0) - arrivals[i]
-                    out_of[i] = buf
+                    if i in keep:
+                        out_of[i] = buf
+                    else:
+                        pool[k].append(buf)
                     done_count += 1
             if not pending and nxt < n:
                 wait = arrivals[nxt] - (time.perf_counter() - t0)
@@ -165,6 +178,8 @@ def run_unbatched(handles, bases, trace):
 
 def benchmark(n: int = 2000, rate: float = 600.0, budget: int = 64 * 2 ** 30, max_inflight: int = 256,
               log: Callable = print) -> dict:
+    """Open-loop latency at `rate` requests/s, then throughput at saturation
+    (all n requests present at t = 0), served and one request at a time."""
     import torch
     srcs = load_vdis(log=log)
     handles = [V.Vdi(s, store="f16") for _, _, s in srcs]
@@ -176,22 +191,26 @@ def benchmark(n: int = 2000, rate: float = 600.0, budget: int = 64 * 2 ** 30, ma
     run_served(handles, bases, (warm[0] - warm[0][0], *warm[1:]), budget, max_inflight)
     run_unbatched(handles, bases, (warm[0] * 0, *warm[1:]))
     torch.cuda.synchronize()
-    lat, makespan, stats, _ = run_served(handles, bases, trace, budget, max_inflight, log)
-    log(f"served: {n} requests in {makespan:.2f}s, p50 {np.percentile(lat, 50)*1e3:.2f} ms, "
-        f"p99 {np.percentile(lat, 99)*1e3:.2f} ms, peak in flight {stats['peak_inflight']}")
-    ulat, umake = run_unbatched(handles, bases, trace)
-    log(f"unbatched: {n} requests in {umake:.2f}s, p50 {np.percentile(ulat, 50)*1e3:.2f} ms, "
-        f"p99 {np.percentile(ulat, 99)*1e3:.2f} ms")
+    out = {"workload": "4 resident FP16 VDIs (2x 1280x720/N_S=20, 2x 1920x1080/N_S=50; V_O 0 and 90 deg); "
+                       f"{n} requests, yaw U[0,30] deg +-, outputs 720p exact / 1080p exact / 1080p D_I=2,D_R=2; "
+                       f"admission budget {budget / 2 ** 30:g} GiB, {max_inflight} slots"}
+    for name, tr in ((f"poisson_{rate:g}_per_s", trace), ("saturation", (trace[0] * 0.0, *trace[1:]))):
+        lat, makespan, stats, _ = run_served(handles, bases, tr, budget, max_inflight, log=log)
+        log(f"{name} served: {n} requests in {makespan:.2f}s, p50 {np.percentile(lat, 50)*1e3:.2f} ms, "
+            f"p99 {np.percentile(lat, 99)*1e3:.2f} ms, {stats['batches']} batches (peak {stats['peak_batch']}), "
+            f"peak in flight {stats['peak_inflight']}")
+        ulat, umake = run_unbatched(handles, bases, tr)
+        log(f"{name} unbatched: {n} requests in {umake:.2f}s, p50 {np.percentile(ulat, 50)*1e3:.2f} ms, "
+            f"p99 {np.percentile(ulat, 99)*1e3:.2f} ms")
+        out[name] = {
+            "served": {**_percentiles(lat), "Mpixels_per_s": round(px / makespan / 1e6, 1),
+                       "requests_per_s": round(n / makespan, 1), "batches": stats["batches"],
+                       "peak_batch": stats["peak_batch"], "peak_inflight": stats["peak_inflight"],
+                       "peak_bytes_in_flight": stats["peak_bytes_in_flight"],
+                       "rejected_budget": stats["rejected_budget"], "rejected_slots": stats["rejected_slots"]},
+            "unbatched": {**_percentiles(ulat), "Mpixels_per_s": round(px / umake / 1e6, 1),
+                          "requests_per_s": round(n / umake, 1)},
+        }
     for h in handles:
         h.close()
-    return {
-        "workload": "4 resident FP16 VDIs (2x 1280x720/N_S=20, 2x 1920x1080/N_S=50; V_O 0 and 90 deg); "
-                    f"{n} requests, Poisson {rate:g}/s, yaw U[0,30] deg +-, outputs 720p exact / 1080p exact / "
-                    "1080p D_I=2,D_R=2; admission budget 64 GB",
-        "served": {**_percentiles(lat), "Mpixels_per_s": round(px / makespan / 1e6, 1),
-                   "requests_per_s": round(n / makespan, 1), "peak_inflight": stats["peak_inflight"],
-                   "peak_bytes_in_flight": stats["peak_bytes_in_flight"],
-                   "rejected_budget": stats["rejected_budget"], "rejected_slots": stats["rejected_slots"]},
-        "unbatched": {**_percentiles(ulat), "Mpixels_per_s": round(px / umake / 1e6, 1),
-                      "requests_per_s": round(n / umake, 1)},
-    }
+    return out

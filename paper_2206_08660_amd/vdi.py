@@ -66,7 +66,8 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
                 ("rejected_budget", ctypes.c_uint64), ("rejected_slots", ctypes.c_uint64),
                 ("bytes_in_flight", ctypes.c_uint64), ("peak_bytes_in_flight", ctypes.c_uint64),
-                ("inflight", ctypes.c_int32), ("peak_inflight", ctypes.c_int32), ("kernel_running", ctypes.c_int32)]
+                ("batches", ctypes.c_uint64), ("inflight", ctypes.c_int32), ("peak_inflight", ctypes.c_int32),
+                ("queued", ctypes.c_int32), ("peak_batch", ctypes.c_int32)]
 
 
 _lib = None

@@ -74,3 +74,29 @@ def test_create_rejects_bad_descriptors_before_any_device_work():
 
 def test_destroy_null_is_noop():
     assert V.lib().vdi_destroy(None) == V.VDI_OK
+
+
+def test_create_rejects_count_grid_of_2_31_cells():
+    lib = V.lib()
+    h = ctypes.c_void_p()
+    d = V.Desc()
+    d.width, d.height, d.max_supersegments = 32768, 32768, 4
+    fake = 16   # never dereferenced: the grid shape is checked before the planes are read
+    d.count, d.depth, d.rgba = fake, fake, fake
+    d.grid_k, d.grid_nz = 1, 2          # 2 * 2^30 = 2^31 cells
+    assert lib.vdi_create(ctypes.byref(d), ctypes.byref(h)) == V.VDI_ERR_ARG
+    assert "2^31" in V.last_error()
+
+
+def test_server_create_rejects_bad_arguments_before_any_device_work():
+    lib = V.lib()
+    h = ctypes.c_void_p()
+    assert lib.vdi_server_create(1 << 30, 4, 0, None) == V.VDI_ERR_ARG
+    assert lib.vdi_server_create(0, 4, 0, ctypes.byref(h)) == V.VDI_ERR_ARG
+    assert lib.vdi_server_create(1 << 30, 0, 0, ctypes.byref(h)) == V.VDI_ERR_ARG
+    assert lib.vdi_server_create(1 << 30, 4097, 0, ctypes.byref(h)) == V.VDI_ERR_ARG
+    assert lib.vdi_server_create(1 << 30, 4, -1, ctypes.byref(h)) == V.VDI_ERR_ARG
+    assert lib.vdi_server_create(1 << 30, 4, 9, ctypes.byref(h)) == V.VDI_ERR_ARG
+    assert "streams" in V.last_error()
+    assert h.value is None
+    assert lib.vdi_server_destroy(None) == V.VDI_OK

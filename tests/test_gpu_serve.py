@@ -57,8 +57,10 @@ def test_mixed_requests_match_single_renders(handles):
         srv.drain()
         assert all(srv.poll(t) for t in tickets)
         st = srv.stats()
-        say(f"[gpu] served {st['completed']} requests, peak in flight {st['peak_inflight']}")
-        assert st["completed"] == len(reqs) and st["inflight"] == 0 and st["peak_inflight"] > 1
+        say(f"[gpu] served {st['completed']} requests in {st['batches']} batches (largest {st['peak_batch']}), "
+            f"peak in flight {st['peak_inflight']}")
+        assert st["completed"] == len(reqs) and st["inflight"] == 0 and st["queued"] == 0
+        assert st["peak_inflight"] > 1 and 1 <= st["batches"] <= len(reqs) and st["peak_batch"] >= 1
     for (hi, yaw, W, H, di, dr), buf in zip(reqs, outs):
         alone = handles[hi].render(inputs.orbit_camera(yaw), W, H, di, dr)
         torch.cuda.synchronize()
@@ -98,9 +100,10 @@ def test_open_loop_trace_small(handles):
     from paper_2206_08660_amd import serve
     arrivals, which, yaw, outsel = serve.make_trace(60, 2000.0, seed=11, nvdi=2)
     bases = [0.0, 0.0]
-    lat, makespan, stats, outs = serve.run_served(handles, bases, (arrivals, which, yaw, outsel), 2 ** 34, 32)
-    assert len(outs) == 60 and (lat >= 0).all()
-    for i in (0, 17, 42, 59):
+    keep = (0, 17, 42, 59)
+    lat, makespan, stats, outs = serve.run_served(handles, bases, (arrivals, which, yaw, outsel), 2 ** 34, 32, keep=keep)
+    assert sorted(outs) == list(keep) and (lat >= 0).all() and stats["completed"] == 60
+    for i in keep:
         W, H, di, dr = serve.OUTPUTS[int(outsel[i])]
         alone = handles[int(which[i])].render(inputs.orbit_camera(float(yaw[i]), bases[int(which[i])]), W, H, di, dr)
         torch.cuda.synchronize()
