@@ -201,8 +201,8 @@ const char *vdi_last_error(void);
  * streams is free: one kernel launch per (mode, colour format) group covers
  * the tiles of all the group's requests, whatever their resolution,
  * viewpoint and preview level, and one more upsamples those with D_I > 1.
- * With two or more streams the next batch starts while the previous one
- * drains.  A request is done when its batch is.  A request's image is
+ * With two or more streams the next batches start while earlier ones
+ * drain.  A request is done when its batch is.  A request's image is
  * identical to vdi_render's with the same arguments.
  * ------------------------------------------------------------------------ */
 typedef struct vdi_server_s *vdi_server_t;
@@ -222,7 +222,7 @@ typedef struct {
  *                     (output images plus preview scratch), > 0.
  *   max_inflight      request slots, 1..4096.
  *   streams           batches in flight at once, each on a stream of the
- *                     server's own (0: two; at most 8).
+ *                     server's own (0: three; at most 8).
  * Returns VDI_ERR_ARG for arguments out of range and VDI_ERR_HIP / VDI_ERR_OOM
  * when a stream, event, job table or the scheduler thread cannot be created.
  */
@@ -247,6 +247,10 @@ int vdi_server_poll(vdi_server_t s, uint64_t ticket, int *done);
 int vdi_server_drain(vdi_server_t s);
 
 int vdi_server_get_stats(vdi_server_t s, vdi_server_stats *stats);
+
+/* Zero the counters (submitted, completed, rejections, batches) and restart
+ * the peaks from the current in-flight state; requests in flight are kept. */
+int vdi_server_reset_stats(vdi_server_t s);
 
 /* Drain, stop the scheduler, free everything.  NULL is a no-op. */
 int vdi_server_destroy(vdi_server_t s);

@@ -39,13 +39,16 @@ namespace vdi {
 namespace {
 
 constexpr int kMaxStreams = 8;
-constexpr int kDefaultStreams = 2;
+constexpr int kDefaultStreams = 3;
 constexpr int kMaxSlots = 4096;
 constexpr int kMaxBatch = 256;                 // requests per batch
 // Render tiles per batch (about four 1920 x 1080 frames): enough to fill the
 // tail of each launch, small enough that a request does not wait long for
 // the rest of its batch.  A larger single request forms a batch of its own.
-constexpr uint64_t kBatchTiles = 1ull << 15;
+#ifndef VDI_BATCH_TILES
+#define VDI_BATCH_TILES (1ull << 15)
+#endif
+constexpr uint64_t kBatchTiles = VDI_BATCH_TILES;
 // Upsampling tiles per batch: keeps every launch far below 2^32 work-items.
 constexpr uint64_t kBatchUpTiles = 1ull << 22;
 
@@ -302,7 +305,7 @@ int vdi_server_submit(vdi_server_t s, vdi_t v, const vdi_camera *cam, int32_t W,
     vdi::Request r;
     rc = vdi::make_frame(v, *cam, w, h, (double)W / (double)H, r.job.F);
     if (rc) return rc;
-    std::lock_guard<std::mutex> lock(s->mu);
+    std::unique_lock<std::mutex> lock(s->mu);
     if (s->err) return vdi::report(s);
     if (s->st.inflight >= s->max_inflight) {
         s->st.rejected_slots++;
@@ -320,9 +323,24 @@ int vdi_server_submit(vdi_server_t s, vdi_t v, const vdi_camera *cam, int32_t W,
             r.lowres = it->second;
             s->free_lowres.erase(it);
         } else {
+            // A new scratch buffer: allocated without the lock, so that the
+            // scheduler keeps launching and retiring batches meanwhile.
+            lock.unlock();
             const hipError_t e = hipMalloc((void **)&r.lowres, lowres_bytes);
             if (e != hipSuccess) return vdi::hip_error(e, "preview scratch");
+            lock.lock();
             s->all_lowres.push_back(r.lowres);
+            if (s->err) {
+                s->free_lowres.emplace(lowres_bytes, r.lowres);
+                return vdi::report(s);
+            }
+            // Admission is checked again: other requests may have been admitted meanwhile.
+            if (s->st.inflight >= s->max_inflight || s->st.bytes_in_flight + bytes > s->budget) {
+                s->free_lowres.emplace(lowres_bytes, r.lowres);
+                if (s->st.inflight >= s->max_inflight) s->st.rejected_slots++;
+                else s->st.rejected_budget++;
+                return vdi::set_error(VDI_ERR_BUDGET, "no room after allocating preview scratch; submit again");
+            }
         }
     }
     r.job.V = v->dev;
@@ -377,6 +395,18 @@ int vdi_server_get_stats(vdi_server_t s, vdi_server_stats *out)
     if (!s || !out) return vdi::set_error(VDI_ERR_ARG, "null argument");
     std::lock_guard<std::mutex> lock(s->mu);
     *out = s->st;
+    return VDI_OK;
+}
+
+int vdi_server_reset_stats(vdi_server_t s)
+{
+    if (!s) return vdi::set_error(VDI_ERR_ARG, "null server");
+    std::lock_guard<std::mutex> lock(s->mu);
+    vdi_server_stats &st = s->st;
+    st.submitted = st.completed = st.rejected_budget = st.rejected_slots = st.batches = 0;
+    st.peak_bytes_in_flight = st.bytes_in_flight;
+    st.peak_inflight = st.inflight;
+    st.peak_batch = 0;
     return VDI_OK;
 }
 

@@ -13,7 +13,9 @@ arrival to the moment the host sees it complete.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
+import gc
 import time
 from typing import Callable, Optional
 
@@ -57,6 +59,9 @@ class Server:
         V._check(V.lib().vdi_server_get_stats(self._h, ctypes.byref(s)))
         return {f: getattr(s, f) for f, _ in V.ServerStats._fields_}
 
+    def reset_stats(self):
+        V._check(V.lib().vdi_server_reset_stats(self._h))
+
     def close(self):
         if self._h is not None:
             h, self._h = self._h, None
@@ -79,6 +84,20 @@ def make_trace(n: int = 2000, rate: float = 600.0, seed: int = TRACE_SEED, nvdi:
     return arrivals, which, yaw, out
 
 
+@contextlib.contextmanager
+def _no_gc():
+    """Timed loops run without Python's cyclic garbage collector, whose
+    occasional full passes would stall the host loop for tens of ms."""
+    was = gc.isenabled()
+    gc.collect()
+    gc.disable()
+    try:
+        yield
+    finally:
+        if was:
+            gc.enable()
+
+
 def _percentiles(lat):
     lat = np.asarray(lat) * 1e3
     return {"p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
@@ -95,12 +114,14 @@ def load_vdis(store: str = "f16", log: Callable = print):
     return srcs
 
 
-def run_served(handles, bases, trace, budget: int, max_inflight: int, keep=(), log: Callable = print):
+def run_served(handles, bases, trace, budget: int, max_inflight: int, keep=(), server: Optional[Server] = None,
+               log: Callable = print):
     """Open-loop served run; returns (latencies [s], makespan [s], stats, {request: image} for `keep`).
 
     Output images come from buffers allocated before the clock starts and
     reused once their request is done; the images of the requests in `keep`
-    are retained instead."""
+    are retained instead.  With `server` the run uses that (already warm)
+    server, whose counters are reset first; otherwise a new one."""
     import torch
 
     import inputs
@@ -110,45 +131,52 @@ def run_served(handles, bases, trace, budget: int, max_inflight: int, keep=(), l
     counts = np.bincount(np.asarray(outsel, dtype=np.int64), minlength=len(OUTPUTS))
     pool = {k: [torch.empty((OUTPUTS[k][1], OUTPUTS[k][0], 4), dtype=torch.float32, device="cuda")
                 for _ in range(min(max_inflight, int(counts[k])) + len(keep))] for k in range(len(OUTPUTS))}
+    cams = [inputs.orbit_camera(float(yaw[i]), bases[int(which[i])]) for i in range(n)]
     torch.cuda.synchronize()
     lat = np.zeros(n)
     out_of = {}
-    with Server(budget, max_inflight) as srv:
-        pending = {}
-        nxt = 0
-        t0 = time.perf_counter()
-        done_count = 0
-        while done_count < n:
-            now = time.perf_counter() - t0
-            # admit every request that has arrived, while it fits
-            while nxt < n and arrivals[nxt] <= now:
-                k = int(outsel[nxt])
-                if not pool[k]:
-                    break
-                W, H, di, dr = OUTPUTS[k]
-                buf = pool[k].pop()
-                cam = inputs.orbit_camera(float(yaw[nxt]), bases[int(which[nxt])])
-                t = srv.submit(handles[int(which[nxt])], cam, W, H, di, dr, buf)
-                if t is None:
-                    pool[k].append(buf)
-                    break
-                pending[t] = (nxt, k, buf)
-                nxt += 1
-            for t in list(pending):
-                if srv.poll(t):
-                    i, k, buf = pending.pop(t)
-                    lat[i] = (time.perf_counter() - t0) - arrivals[i]
-                    if i in keep:
-                        out_of[i] = buf
-                    else:
+    own = server is None
+    srv = Server(budget, max_inflight) if own else server
+    srv.reset_stats()
+    try:
+        with _no_gc():
+            pending = {}
+            nxt = 0
+            done_count = 0
+            t0 = time.perf_counter()
+            while done_count < n:
+                now = time.perf_counter() - t0
+                # admit every request that has arrived, while it fits
+                while nxt < n and arrivals[nxt] <= now:
+                    k = int(outsel[nxt])
+                    if not pool[k]:
+                        break
+                    W, H, di, dr = OUTPUTS[k]
+                    buf = pool[k].pop()
+                    t = srv.submit(handles[int(which[nxt])], cams[nxt], W, H, di, dr, buf)
+                    if t is None:
                         pool[k].append(buf)
-                    done_count += 1
-            if not pending and nxt < n:
-                wait = arrivals[nxt] - (time.perf_counter() - t0)
-                if wait > 2e-4:
-                    time.sleep(wait - 1e-4)
-        makespan = time.perf_counter() - t0
+                        break
+                    pending[t] = (nxt, k, buf)
+                    nxt += 1
+                for t in list(pending):
+                    if srv.poll(t):
+                        i, k, buf = pending.pop(t)
+                        lat[i] = (time.perf_counter() - t0) - arrivals[i]
+                        if i in keep:
+                            out_of[i] = buf
+                        else:
+                            pool[k].append(buf)
+                        done_count += 1
+                if not pending and nxt < n:
+                    wait = arrivals[nxt] - (time.perf_counter() - t0)
+                    if wait > 2e-4:
+                        time.sleep(wait - 1e-4)
+            makespan = time.perf_counter() - t0
         stats = srv.stats()
+    finally:
+        if own:
+            srv.close()
     return lat, makespan, stats, out_of
 
 
@@ -161,19 +189,22 @@ def run_unbatched(handles, bases, trace):
     n = len(arrivals)
     bufs = {k: torch.empty((OUTPUTS[k][1], OUTPUTS[k][0], 4), dtype=torch.float32, device="cuda")
             for k in range(len(OUTPUTS))}
+    cams = [inputs.orbit_camera(float(yaw[i]), bases[int(which[i])]) for i in range(n)]
+    torch.cuda.synchronize()
     lat = np.zeros(n)
-    t0 = time.perf_counter()
-    for i in range(n):
-        wait = arrivals[i] - (time.perf_counter() - t0)
-        if wait > 0:
-            time.sleep(wait)
-        k = int(outsel[i])
-        W, H, di, dr = OUTPUTS[k]
-        handles[int(which[i])].render(inputs.orbit_camera(float(yaw[i]), bases[int(which[i])]), W, H, di, dr,
-                                      out=bufs[k])
-        torch.cuda.synchronize()
-        lat[i] = (time.perf_counter() - t0) - arrivals[i]
-    return lat, time.perf_counter() - t0
+    with _no_gc():
+        t0 = time.perf_counter()
+        for i in range(n):
+            wait = arrivals[i] - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+            k = int(outsel[i])
+            W, H, di, dr = OUTPUTS[k]
+            handles[int(which[i])].render(cams[i], W, H, di, dr, out=bufs[k])
+            torch.cuda.synchronize()
+            lat[i] = (time.perf_counter() - t0) - arrivals[i]
+        makespan = time.perf_counter() - t0
+    return lat, makespan
 
 
 def benchmark(n: int = 2000, rate: float = 600.0, budget: int = 64 * 2 ** 30, max_inflight: int = 256,
@@ -186,16 +217,17 @@ def benchmark(n: int = 2000, rate: float = 600.0, budget: int = 64 * 2 ** 30, ma
     bases = [b for _, b, _ in srcs]
     trace = make_trace(n, rate)
     px = sum(OUTPUTS[int(k)][0] * OUTPUTS[int(k)][1] for k in trace[3])
-    # warm both paths on a few requests
-    warm = tuple(a[:16] for a in trace)
-    run_served(handles, bases, (warm[0] - warm[0][0], *warm[1:]), budget, max_inflight)
-    run_unbatched(handles, bases, (warm[0] * 0, *warm[1:]))
+    # One long-running server; both paths are warmed on the first 64 requests.
+    srv = Server(budget, max_inflight)
+    warm = tuple(a[:64] for a in trace)
+    run_served(handles, bases, (warm[0] * 0.0, *warm[1:]), budget, max_inflight, server=srv)
+    run_unbatched(handles, bases, (warm[0] * 0.0, *warm[1:]))
     torch.cuda.synchronize()
     out = {"workload": "4 resident FP16 VDIs (2x 1280x720/N_S=20, 2x 1920x1080/N_S=50; V_O 0 and 90 deg); "
                        f"{n} requests, yaw U[0,30] deg +-, outputs 720p exact / 1080p exact / 1080p D_I=2,D_R=2; "
                        f"admission budget {budget / 2 ** 30:g} GiB, {max_inflight} slots"}
     for name, tr in ((f"poisson_{rate:g}_per_s", trace), ("saturation", (trace[0] * 0.0, *trace[1:]))):
-        lat, makespan, stats, _ = run_served(handles, bases, tr, budget, max_inflight, log=log)
+        lat, makespan, stats, _ = run_served(handles, bases, tr, budget, max_inflight, server=srv, log=log)
         log(f"{name} served: {n} requests in {makespan:.2f}s, p50 {np.percentile(lat, 50)*1e3:.2f} ms, "
             f"p99 {np.percentile(lat, 99)*1e3:.2f} ms, {stats['batches']} batches (peak {stats['peak_batch']}), "
             f"peak in flight {stats['peak_inflight']}")
@@ -211,6 +243,7 @@ def benchmark(n: int = 2000, rate: float = 600.0, budget: int = 64 * 2 ** 30, ma
             "unbatched": {**_percentiles(ulat), "Mpixels_per_s": round(px / umake / 1e6, 1),
                           "requests_per_s": round(n / umake, 1)},
         }
+    srv.close()
     for h in handles:
         h.close()
     return out

@@ -28,7 +28,8 @@ SEARCH = {"seeded": 0, "binary": 1, "linear": 2}
 # Every symbol include/vdi.h declares.
 EXPORTS = ("vdi_create", "vdi_render", "vdi_render_ex", "vdi_render_counters", "vdi_get_grid", "vdi_get_info",
            "vdi_destroy", "vdi_lowres_size", "vdi_plane_bytes", "vdi_last_error", "vdi_server_create",
-           "vdi_server_submit", "vdi_server_poll", "vdi_server_drain", "vdi_server_get_stats", "vdi_server_destroy")
+           "vdi_server_submit", "vdi_server_poll", "vdi_server_drain", "vdi_server_get_stats",
+           "vdi_server_reset_stats", "vdi_server_destroy")
 
 
 class VdiError(RuntimeError):
@@ -98,6 +99,7 @@ def lib() -> ctypes.CDLL:
         L.vdi_server_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
         L.vdi_server_drain.argtypes = [P]
         L.vdi_server_get_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
+        L.vdi_server_reset_stats.argtypes = [P]
         L.vdi_server_destroy.argtypes = [P]
         _lib = L
     return _lib

@@ -93,6 +93,11 @@ def test_admission_by_budget_and_slots(handles):
             assert srv.stats()["rejected_slots"] >= 1
         srv.drain()
         assert srv.poll(t)
+        assert srv.stats()["completed"] >= 1
+        srv.reset_stats()
+        st = srv.stats()
+        assert st["completed"] == 0 and st["submitted"] == 0 and st["batches"] == 0
+        assert st["peak_inflight"] == 0 and st["inflight"] == 0
 
 
 def test_open_loop_trace_small(handles):
