@@ -47,10 +47,11 @@ extern "C" {
 #define VDI_F16 1  /* 4 x IEEE binary16 (round to nearest even), 8 bytes */
 #define VDI_BF16 2 /* 4 x bfloat16 (round to nearest even), 8 bytes */
 
-/* First-supersegment search (Section 4.2; all three give the same image). */
+/* First-supersegment search (Section 4.2; all four give the same image). */
 #define VDI_SEARCH_SEEDED 0 /* seeded by the index found in the previous list (supplement Alg. S2) */
 #define VDI_SEARCH_BINARY 1 /* binary search over the whole list, from the middle */
 #define VDI_SEARCH_LINEAR 2 /* linear scan from the list's near end */
+#define VDI_SEARCH_WINDOW 3 /* seeded, with 8 slots around the seed compared at once (default) */
 
 #define VDI_MAX_SUPERSEGMENTS 255
 #define VDI_MAX_GRID_NZ 64
@@ -154,7 +155,7 @@ int vdi_create(const vdi_desc *desc, vdi_t *out);
 int vdi_render(vdi_t v, const vdi_camera *cam_VN, int32_t width, int32_t height, float D_I, float D_R,
                float *out_rgba, void *hip_stream);
 
-/* vdi_render with explicit options (opts NULL = defaults: ESS on, seeded search). */
+/* vdi_render with explicit options (opts NULL = defaults: ESS on, window search). */
 int vdi_render_ex(vdi_t v, const vdi_camera *cam_VN, int32_t width, int32_t height, float D_I, float D_R,
                   const vdi_render_opts *opts, float *out_rgba, void *hip_stream);
 

@@ -118,7 +118,7 @@ int build_frame(const vdi_s *v, const vdi_camera &cam, int w, int h, double aspe
     f.W = w;
     f.H = h;
     f.ess = 1;
-    f.search = VDI_SEARCH_SEEDED;
+    f.search = VDI_SEARCH_WINDOW;
     return VDI_OK;
 }
 
@@ -126,7 +126,7 @@ int check_opts(const vdi_render_opts *opts, vdi::Frame &f)
 {
     if (!opts) return VDI_OK;
     if (opts->ess != 0 && opts->ess != 1) return fail(VDI_ERR_ARG, "opts.ess must be 0 or 1");
-    if (opts->search < VDI_SEARCH_SEEDED || opts->search > VDI_SEARCH_LINEAR)
+    if (opts->search < VDI_SEARCH_SEEDED || opts->search > VDI_SEARCH_WINDOW)
         return fail(VDI_ERR_ARG, "opts.search must be a VDI_SEARCH_* value");
     f.ess = opts->ess;
     f.search = opts->search;

@@ -137,7 +137,7 @@ hipError_t launch_scatter_slots(const void *src, int32_t fmt_in, void *dst, int3
                                 const DevVDI &v, int32_t j0, hipStream_t stream);
 // Batched launches: `jobs` is a device array of njobs records sorted by
 // tile0, all of colour format fmt; nblocks covers the last job's tiles.
-// Exact jobs use the seeded search with empty-space skipping.
+// Exact jobs use the window search with empty-space skipping.
 hipError_t launch_batch_render(const BatchJob *jobs, int32_t njobs, uint32_t nblocks, int32_t fmt, bool preview,
                                hipStream_t stream);
 hipError_t launch_batch_upsample(const UpsampleJob *jobs, int32_t njobs, uint32_t nblocks, hipStream_t stream);

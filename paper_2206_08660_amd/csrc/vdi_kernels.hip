@@ -109,7 +109,7 @@ __global__ __launch_bounds__(kBlock) VDI_EXACT_OCC void k_render_batch(const Bat
         o = trace_preview<FMT>(J.V, J.F, s_gz, px, py);
     } else {
         Counters cnt = {0, 0};
-        o = trace_exact<FMT, VDI_SEARCH_SEEDED, true, false>(J.V, J.F, s_gz, px, py, cnt);
+        o = trace_exact<FMT, VDI_SEARCH_WINDOW, true, false>(J.V, J.F, s_gz, px, py, cnt);
     }
     J.F.out[(uint64_t)py * J.F.W + px] = o;
 }
@@ -213,6 +213,10 @@ hipError_t launch_exact_fmt(const DevVDI &v, const Frame &f, dim3 grid, hipStrea
     case VDI_SEARCH_LINEAR:
         if (ess) k_render_exact<FMT, VDI_SEARCH_LINEAR, true, COUNT><<<grid, kBlock, 0, s>>>(v, f);
         else k_render_exact<FMT, VDI_SEARCH_LINEAR, false, COUNT><<<grid, kBlock, 0, s>>>(v, f);
+        break;
+    case VDI_SEARCH_WINDOW:
+        if (ess) k_render_exact<FMT, VDI_SEARCH_WINDOW, true, COUNT><<<grid, kBlock, 0, s>>>(v, f);
+        else k_render_exact<FMT, VDI_SEARCH_WINDOW, false, COUNT><<<grid, kBlock, 0, s>>>(v, f);
         break;
     default:
         if (ess) k_render_exact<FMT, VDI_SEARCH_SEEDED, true, COUNT><<<grid, kBlock, 0, s>>>(v, f);

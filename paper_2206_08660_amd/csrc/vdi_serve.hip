@@ -347,7 +347,7 @@ int vdi_server_submit(vdi_server_t s, vdi_t v, const vdi_camera *cam, int32_t W,
     r.job.F.out = down ? r.lowres : reinterpret_cast<float4 *>(out);
     r.job.F.DR = D_R;
     r.job.F.ess = 1;
-    r.job.F.search = VDI_SEARCH_SEEDED;
+    r.job.F.search = VDI_SEARCH_WINDOW;
     r.job.tile0 = 0;
     r.job.ntiles = vdi::tiles_of(w, h);
     r.fmt = v->dev.fmt;

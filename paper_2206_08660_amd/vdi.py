@@ -23,7 +23,7 @@ VDI_ERR_BUDGET = -4
 VDI_ERR_STATE = -5
 
 FORMATS = {"f32": 0, "f16": 1, "bf16": 2}
-SEARCH = {"seeded": 0, "binary": 1, "linear": 2}
+SEARCH = {"seeded": 0, "binary": 1, "linear": 2, "window": 3}
 
 # Every symbol include/vdi.h declares.
 EXPORTS = ("vdi_create", "vdi_render", "vdi_render_ex", "vdi_render_counters", "vdi_get_grid", "vdi_get_info",
@@ -185,7 +185,7 @@ class Vdi:
         return self._h
 
     def render(self, cam, width: int, height: int, d_i: float = 1.0, d_r: float = 0.0, out=None, stream=None,
-               ess: bool = True, search: str = "seeded"):
+               ess: bool = True, search: str = "window"):
         """Render into a float32 [height, width, 4] device tensor (allocated if
         `out` is None) on `stream` (default: torch's current stream)."""
         import torch
@@ -199,7 +199,7 @@ class Vdi:
                                    ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
         return out
 
-    def render_counters(self, cam, width: int, height: int, ess: bool = False, search: str = "seeded",
+    def render_counters(self, cam, width: int, height: int, ess: bool = False, search: str = "window",
                         stream=None):
         """Instrumented exact render: (image, touched_lists [H_O, W_O] u8,
         touched_slots [N_S, H_O, W_O] u8, ray_stats [H, W, 2] i32), all torch CUDA tensors."""

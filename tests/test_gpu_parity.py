@@ -65,7 +65,7 @@ def test_tiny_exact_full_frame(tiny, tiny_h, theta):
     cam = inputs.orbit_camera(theta)
     ref = oracle.render_exact(tiny, cam, 128, 128)
     for ess in (True, False):
-        for search in ("seeded", "binary", "linear"):
+        for search in ("window", "seeded", "binary", "linear"):
             img = gpu_render(tiny_h, cam, 128, 128, ess=ess, search=search)
             err = np.abs(img - ref).max()
             assert err <= TOL, (theta, ess, search, err)
@@ -106,7 +106,7 @@ def test_random_vdi_exact(seed, theta):
     ref = oracle.render_exact(v, cam, 70, 44)
     with V.Vdi(v, validate=True) as h:
         for ess in (True, False):
-            for search in ("seeded", "binary", "linear"):
+            for search in ("window", "seeded", "binary", "linear"):
                 img = gpu_render(h, cam, 70, 44, ess=ess, search=search)
                 assert np.abs(img - ref).max() <= TOL, (ess, search)
 

@@ -1,7 +1,7 @@
 """HIP path vs the FP64 oracle on the full-size workloads (needs an MI355X).
 
 Frames are rendered whole on the GPU in the configuration the benchmark
-times (ESS on, seeded search); the oracle computes a stratified sample of
+times (ESS on, window search); the oracle computes a stratified sample of
 their pixels one by one.  Precision forms: FP16/BF16 colour storage against
 the oracle fed the same rounded colours (<= 1e-4), and PSNR against the
 oracle on the FP32 colours (>= 50 dB).
@@ -83,7 +83,7 @@ def test_720p_exact_sampled(w720, h720, theta):
     img = frame(h720, cam, 1280, 720)
     assert np.abs(img[pix] - ref).max() <= TOL
     if theta == 20.0:
-        for ess, search in [(False, "seeded"), (True, "binary"), (True, "linear"), (False, "linear")]:
+        for ess, search in [(True, "seeded"), (False, "window"), (True, "binary"), (True, "linear"), (False, "linear")]:
             other = frame(h720, cam, 1280, 720, ess=ess, search=search)
             assert np.abs(other - img).max() <= 1e-6, (ess, search)
 
