@@ -294,19 +294,25 @@ VDI_HD inline float float_above(double z)
     return (double)f < z ? nextafterf(f, __builtin_huge_valf()) : f;
 }
 
-// Smallest j in [0, n) with b_j > z (n if none), window placed around p.
+// A ray moving to larger depth usually finds its answer at or after the
+// previous list's index p, one moving to smaller depth at or before it.
+VDI_HD inline int win_start_fwd(int p) { return p - (kWin / 2 - 1); }
+VDI_HD inline int win_start_bwd(int p) { return p - kWin / 2; }
+
+// Smallest j in [0, n) with b_j > z (n if none); the window starts at slot
+// `start`, moved inside the list.
 // The window lies inside the list and its loads share one base address
 // (immediate offsets, all issued before the first compare).  Every case ends
 // in the same bisection, over an empty range when the window decided:
 // [0, w0) below the window, [w0 + kWin, n) above it, the whole list when it
 // is shorter than the window.
 VDI_HD inline int first_back_above_win(const float2 *__restrict__ dep, uint64_t stride, uint64_t base, int n, double z,
-                                       int p)
+                                       int start)
 {
     const float zb = float_below(z);  // b > z  <=>  b > zb
     int lo = 0, hi = n;
     if (n >= kWin) {
-        const int w0 = max(0, min(p - (kWin / 2 - 1), n - kWin));
+        const int w0 = max(0, min(start, n - kWin));
         const float2 *w = dep + base + (uint64_t)w0 * stride;
         float b[kWin];
 #pragma unroll
@@ -332,15 +338,15 @@ VDI_HD inline int first_back_above_win(const float2 *__restrict__ dep, uint64_t 
     return lo;
 }
 
-// Largest j in [0, n) with f_j < z (-1 if none), window placed around p: one
+// Largest j in [0, n) with f_j < z (-1 if none), window from `start`: one
 // less than the first j with f_j >= z, found as above.
 VDI_HD inline int last_front_below_win(const float2 *__restrict__ dep, uint64_t stride, uint64_t base, int n, double z,
-                                       int p)
+                                       int start)
 {
     const float za = float_above(z);  // f < z  <=>  f < za
     int lo = 0, hi = n;
     if (n >= kWin) {
-        const int w0 = max(0, min(p - kWin / 2, n - kWin));
+        const int w0 = max(0, min(start, n - kWin));
         const float2 *w = dep + base + (uint64_t)w0 * stride;
         float f[kWin];
 #pragma unroll
@@ -444,7 +450,7 @@ VDI_HD bool do_list(const DevVDI &V, const Frame &F, int ix, int iy, int n, doub
         bool have = false;
         float2 d = make_float2(0.0f, 0.0f);
         if constexpr (SEARCH == VDI_SEARCH_WINDOW) {
-            j = first_back_above_win(dep, stride, lb, n, za, p);
+            j = first_back_above_win(dep, stride, lb, n, za, win_start_fwd(p));
         } else if (SEARCH == VDI_SEARCH_SEEDED && p >= 0 && p < n) {
             const float2 dp = depth_at(V, p, lb);
             const float2 dq = p > 0 ? depth_at(V, p - 1, lb) : make_float2(-__builtin_huge_valf(), -__builtin_huge_valf());
@@ -501,7 +507,7 @@ VDI_HD bool do_list(const DevVDI &V, const Frame &F, int ix, int iy, int n, doub
         bool have = false;
         float2 d = make_float2(0.0f, 0.0f);
         if constexpr (SEARCH == VDI_SEARCH_WINDOW) {
-            j = last_front_below_win(dep, stride, lb, n, za, p);
+            j = last_front_below_win(dep, stride, lb, n, za, win_start_bwd(p));
         } else if (SEARCH == VDI_SEARCH_SEEDED && p >= 0 && p < n) {
             const float2 dp = depth_at(V, p, lb);
             const float2 dq = p + 1 < n ? depth_at(V, p + 1, lb) : make_float2(__builtin_huge_valf(), __builtin_huge_valf());
@@ -726,27 +732,44 @@ VDI_HD float4 trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, 
                     // D_R >= 1e-4 keeps x far below this bound; it only caps the loop.
                     const int n = (int)fmin(fmax(ceil(x), 1.0), 16777216.0);
                     const double h = (tn - t) / n;
-                    for (int q = 0; q < n; ++q) {
-                        const double u = t + (q + 0.5) * h;
-                        const double z = F.Z0 + u * r.Zp, iz = rcp64(z);
+                    // List of sample q (its count is fetched one sample ahead).
+                    auto sample_list = [&](int q, double &u, double &z) -> uint64_t {
+                        u = t + (q + 0.5) * h;
+                        z = F.Z0 + u * r.Zp;
+                        const double iz = rcp64(z);
                         const int lx = min(max((int)floor(((F.X0 + u * r.Xp) * iz + 1.0) * (0.5 * WO)), 0), WO - 1);
                         const int ly = min(max((int)floor(((F.Y0 + u * r.Yp) * iz + 1.0) * (0.5 * HO)), 0), HO - 1);
-                        const uint64_t li = (uint64_t)ly * WO + lx;
-                        const int nl = V.count[li];
-                        if (nl == 0) continue;
-                        // Point location: the supersegment with f <= z < b.
-                        const uint64_t lb = list_base(li, V.NS);
-                        const int j = first_back_above<VDI_SEARCH_SEEDED>(dep, stride, lb, nl, z, p);
-                        if (j >= nl) continue;
-                        const float2 fb = dep[(uint64_t)j * stride + lb];
-                        p = j;
-                        if ((double)fb.x > z) continue;
-                        const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * stride + lb, V.fmt);
-                        composite(A, c, (float)h * list_cos(V, lx, ly) * rcp32(fb.y - fb.x));
-                        if (A.T <= kTTerm) {
-                            done = true;
-                            break;
+                        return (uint64_t)ly * WO + lx;
+                    };
+                    double u, z;
+                    uint64_t li = sample_list(0, u, z);
+                    int nl = V.count[li];
+                    for (int q = 0; q < n; ++q) {
+                        double un = 0.0, zn = 0.0;
+                        const uint64_t lin = q + 1 < n ? sample_list(q + 1, un, zn) : li;
+                        const int nln = q + 1 < n ? (int)V.count[lin] : 0;
+                        if (nl > 0) {
+                            // Point location: the supersegment with f <= z < b.
+                            const uint64_t lb = list_base(li, V.NS);
+                            const int j = first_back_above_win(dep, stride, lb, nl, z, fwd ? win_start_fwd(p) : win_start_bwd(p));
+                            if (j < nl) {
+                                const float2 fb = dep[(uint64_t)j * stride + lb];
+                                p = j;
+                                if ((double)fb.x <= z) {
+                                    const int lx = (int)(li % (uint64_t)WO), ly = (int)(li / (uint64_t)WO);
+                                    const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * stride + lb, V.fmt);
+                                    composite(A, c, (float)h * list_cos(V, lx, ly) * rcp32(fb.y - fb.x));
+                                    if (A.T <= kTTerm) {
+                                        done = true;
+                                        break;
+                                    }
+                                }
+                            }
                         }
+                        li = lin;
+                        nl = nln;
+                        u = un;
+                        z = zn;
                     }
                 }
             }
