@@ -101,34 +101,67 @@ def main():
         log("profile pass done")
         return
 
-    def step(handle):
-        for (th, di, dr) in renders:
+    # Every render of the timed steps is bracketed by HIP events on the
+    # launch stream; per-render times are their averages over the steps.
+    def step(handle, events=None):
+        for k, (th, di, dr) in enumerate(renders):
+            if events is not None:
+                events[k][0].record(stream)
             handle.render(cams[th], W, H, di, dr, out=out)
+            if events is not None:
+                events[k][1].record(stream)
 
     for _ in range(args.warmup):
         step(h)
     torch.cuda.synchronize()
     log(f"warmup {args.warmup} steps done; timing {args.steps} steps")
+    evs = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in renders]
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(h)
+    for i in range(args.steps):
+        step(h, evs[i])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_step = 1e3 * elapsed / args.steps
     mpix = len(renders) * W * H * args.steps / elapsed / 1e6
     log(f"step {ms_step:.3f} ms, {mpix:.1f} Mpixels/s")
+    per = {r: float(np.mean([evs[i][k][0].elapsed_time(evs[i][k][1]) for i in range(args.steps)]))
+           for k, r in enumerate(renders)}
+    per_p99 = {r: float(np.percentile([evs[i][k][0].elapsed_time(evs[i][k][1]) for i in range(args.steps)], 99))
+               for k, r in enumerate(renders)}
 
-    # Per-render launch times with HIP events on the launch stream.
-    reps = 10
-    per = {}
-    for (th, di, dr) in renders:
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
-        for e0, e1 in ev:
+    # The same exact frames with the 256 MB Infinity Cache flushed before each
+    # (a 512 MB buffer written between frames).
+    flush = torch.empty(2 ** 27, dtype=torch.float32, device="cuda")
+    flushed = {}
+    for th in ANGLES:
+        ts = []
+        for _ in range(5):
+            flush.fill_(float(th))
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            h.render(cams[th], W, H, di, dr, out=out)
+            h.render(cams[th], W, H, 1.0, 0.0, out=out)
             e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        flushed[th] = float(np.median(ts))
+    del flush
+    # A measured bandwidth peak: a 1 GiB device-to-device copy (2 GiB moved).
+    a = torch.empty(2 ** 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    cts = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        b.copy_(a)
+        e1.record(stream)
         torch.cuda.synchronize()
-        per[(th, di, dr)] = float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev]))
+        cts.append(e0.elapsed_time(e1))
+    copy_gbs = 2 * a.numel() * 4 / (float(np.median(cts)) / 1e3) / 1e9
+    del a, b
+    log(f"copy kernel: {copy_gbs:.0f} GB/s")
     exact_ms = {th: per[(th, 1.0, 0.0)] for th in ANGLES}
     mode_ms = {f"D_I={di:g},D_R={dr:g}": sum(per[(th, di, dr)] for th in ANGLES) for (di, dr) in MODES}
     log("per-mode ms (sum over 10 angles): " + ", ".join(f"{k}: {v:.3f}" for k, v in mode_ms.items()))
@@ -138,11 +171,14 @@ def main():
     # (f, b) pairs; per supersegment composited, its colour; plus the output.
     count_d = torch.from_numpy(np.ascontiguousarray(src.count)).cuda().to(torch.int64)
     balg = {}
+    visits = {}
     for th in ANGLES:
         _, tl, ts, st = h.render_counters(cams[th], W, H, ess=True)
         touched = tl.bool()
         balg[th] = int(touched.sum().item() + 8 * count_d[touched].sum().item() + 16 * ts.sum(dtype=torch.int64).item()
                        + 16 * W * H)
+        sums = st.reshape(-1, 2).to(torch.int64).sum(dim=0).tolist()
+        visits[th] = (int(sums[0]), int(sums[1]))
         del tl, ts, st
     torch.cuda.synchronize()
     total_b = sum(balg.values())
@@ -157,6 +193,13 @@ def main():
         "exact_ms": {f"{th:g}": round(exact_ms[th], 4) for th in ANGLES},
         "exact_balg_MB": {f"{th:g}": round(balg[th] / 1e6, 2) for th in ANGLES},
         "exact_GBs": {f"{th:g}": round(balg[th] / exact_ms[th] / 1e6, 1) for th in ANGLES},
+        "exact_hbm_frac": {f"{th:g}": round(balg[th] / exact_ms[th] / 1e6 / HBM_PEAK_GBS, 4) for th in ANGLES},
+        "exact_ms_p99": {f"{th:g}": round(per_p99[(th, 1.0, 0.0)], 4) for th in ANGLES},
+        "exact_ms_mall_flushed": {f"{th:g}": round(flushed[th], 4) for th in ANGLES},
+        "exact_hbm_frac_mall_flushed": {f"{th:g}": round(balg[th] / flushed[th] / 1e6 / HBM_PEAK_GBS, 4)
+                                        for th in ANGLES},
+        "exact_list_visits_M": {f"{th:g}": round(visits[th][0] / 1e6, 2) for th in ANGLES},
+        "exact_pieces_M": {f"{th:g}": round(visits[th][1] / 1e6, 2) for th in ANGLES},
         "preview_D_I2_D_R2_ms": {f"{th:g}": round(per[(th, 2.0, 2.0)], 4) for th in ANGLES},
         "preview_D_I4_D_R2_ms": {f"{th:g}": round(per[(th, 4.0, 2.0)], 4) for th in ANGLES},
         "mode_ms_per_10_angles": {k: round(v, 3) for k, v in mode_ms.items()},
@@ -179,11 +222,14 @@ def main():
                                "{exact, D_I=2/D_R=2, D_I=4/D_R=2}; output 1920x1080",
                    "frames_per_step": len(renders), "vdi_supersegments": int(info.supersegments),
                    "vdi_device_GiB": round(info.device_bytes / 2 ** 30, 3),
+                   "preview_rays": {f"D_I={di:g}": int(np.prod(V.lowres_size(W, H, di))) for (di, dr) in MODES if dr > 0},
                    "vdi_create_ms": round(upload_s * 1e3, 1)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_render_exact (exact mode, FP32 colour, ESS, window search)",
                      "algorithmic_bytes_per_launch": int(total_b / len(ANGLES)),
+                     "copy_kernel_GBs": round(copy_gbs, 1),
+                     "frac_of_copy_kernel": round(achieved / copy_gbs, 4),
                      "launch_ms": round(1e3 * total_s / len(ANGLES), 4)},
         "breakdown": breakdown,
     }
