@@ -47,6 +47,7 @@ def parse():
     p.add_argument("--skip-cpu-baseline", action="store_true")
     p.add_argument("--skip-served", action="store_true")
     p.add_argument("--skip-precision", action="store_true")
+    p.add_argument("--skip-replace", action="store_true")
     p.add_argument("--profile-pass", action="store_true",
                    help="short run for rocprofv3: one 1 GiB copy (counter calibration) and one exact render per angle")
     return p.parse_args()
@@ -238,6 +239,8 @@ def main():
         result["precision"] = precision_leg(src, cams, out, exact_ms, torch, V)
     if not args.skip_served:
         result["served"] = served_leg(torch, V)
+    if not args.skip_replace:
+        result["replacement"] = replace_leg(h, cams[20.0], out, stream, torch, V)
     h.close()
     if not args.skip_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline_leg(src, cams, per, result.get("precision"), np, torch, V)
@@ -267,6 +270,59 @@ def precision_leg(src, cams, out, exact_ms, torch, V):
                         "device_GiB": round(hq.info().device_bytes / 2 ** 30, 3)}
         log(f"{fmt}: exact sweep {res[fmt]['exact_ms_sum_10_angles']:.3f} ms "
             f"(x{res[fmt]['speedup_vs_f32']} vs f32)")
+    return res
+
+
+def replace_leg(h, cam, out, stream, torch, V):
+    """Double-buffered replacement: a second 1080p FP32 VDI (generated 90
+    degrees away) is uploaded into the resident one from another thread while
+    the main thread keeps rendering exact 1920x1080 frames."""
+    import threading
+
+    import numpy as np
+
+    import inputs
+    b = inputs.load_workload("1080p", base_deg=90.0, keep_dvr=False)
+
+    def frame_ms(n):
+        ts = []
+        for _ in range(n):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            h.render(cam, W, H, out=out)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return ts
+
+    idle = frame_ms(20)
+    call = {}
+
+    def replace():
+        t = time.perf_counter()
+        h.replace_begin(b, stream=stream)
+        call["ms"] = 1e3 * (time.perf_counter() - t)
+
+    torch.cuda.synchronize()
+    th = threading.Thread(target=replace)
+    t0 = time.perf_counter()
+    th.start()
+    during = []
+    while True:
+        during += frame_ms(1)
+        if not th.is_alive() and h.replace_poll():
+            break
+    swap_ms = 1e3 * (time.perf_counter() - t0)
+    th.join()
+    after = frame_ms(20)
+    res = {"workload": "1080p FP32 VDI (2.3 GiB) replaced by one generated 90 deg away, from a second thread, "
+                       "while rendering 1920x1080 exact frames at 20 deg",
+           "begin_to_swap_ms": round(swap_ms, 1), "replace_begin_host_ms": round(call.get("ms", -1.0), 1),
+           "frames_during_upload": len(during), "frame_ms_idle": round(float(np.median(idle)), 4),
+           "frame_ms_during_upload": round(float(np.median(during)), 4),
+           "frame_ms_after_swap": round(float(np.median(after)), 4)}
+    log(f"replacement: swapped after {swap_ms:.0f} ms; {len(during)} frames meanwhile at "
+        f"{res['frame_ms_during_upload']} ms (idle {res['frame_ms_idle']} ms)")
     return res
 
 

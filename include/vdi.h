@@ -114,7 +114,7 @@ typedef struct {
 typedef struct {
     int32_t width, height, max_supersegments, rgba_fmt;
     int32_t grid_k, grid_nz, grid_w, grid_h;
-    uint64_t device_bytes; /* count + depth + colour planes + grid */
+    uint64_t device_bytes; /* count + depth + colour planes + grid (twice, plus staging, once a replacement was made) */
     uint64_t supersegments; /* sum of count */
 } vdi_info_t;
 
@@ -183,6 +183,37 @@ int vdi_get_info(vdi_t v, vdi_info_t *info);
  * memory.  NULL is a no-op.  Destroying the same handle twice is undefined.
  */
 int vdi_destroy(vdi_t v);
+
+/* ------------------------------------------------------------------------
+ * Replacing a resident VDI while rendering (double buffering, the client
+ * half of the paper's remote session, Section 5: a new VDI arrives from the
+ * server while the client keeps rendering the old one).
+ * ------------------------------------------------------------------------ */
+
+/*
+ * Start uploading `desc` into the back buffers of v: a VDI with the same
+ * width, height, max_supersegments, stored colour format and grid shape,
+ * possibly generated from another view (camera_VO, AABB and grid_z may
+ * differ).  The upload runs on a stream of v's own, after the work already
+ * enqueued on `stream` (the caller's render stream for v; NULL = default
+ * stream), and the back buffers are allocated by the first call.  Renders of
+ * v keep using the current VDI until vdi_replace_poll swaps the new one in.
+ * Returns when the host arrays have been read: the caller may free them.
+ * Renders of v on other streams and requests of a server that use v must be
+ * complete before the call (their work may still read the back buffers, which
+ * held the VDI before the last swap).
+ * Errors: VDI_ERR_ARG (null arguments, an invalid descriptor as for
+ * vdi_create, or another shape), VDI_ERR_STATE (a replacement is pending),
+ * VDI_ERR_OOM, VDI_ERR_HIP.
+ */
+int vdi_replace_begin(vdi_t v, const vdi_desc *desc, void *stream);
+
+/*
+ * If the pending replacement's upload has finished, make the new VDI the one
+ * later renders and queries use, and set *swapped = 1; otherwise (still
+ * uploading, or nothing pending) set *swapped = 0.  Never waits.
+ */
+int vdi_replace_poll(vdi_t v, int32_t *swapped);
 
 /* Image size used for downsampling factor D_I (round half up, at least 1). */
 int vdi_lowres_size(int32_t width, int32_t height, float D_I, int32_t *w, int32_t *h);

@@ -83,16 +83,16 @@ int make_basis(const vdi_camera &c, Basis &b)
 
 double dot(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
-// Frame constants for rays on a w x h grid with aspect `aspect`.
-int build_frame(const vdi_s *v, const vdi_camera &cam, int w, int h, double aspect, vdi::Frame &f)
+// Frame constants for rays on a w x h grid with aspect `aspect`, for the VDI set S.
+int build_frame(const vdi::VdiSet &S, const vdi_camera &cam, int w, int h, double aspect, vdi::Frame &f)
 {
     Basis o, n;
-    int rc = make_basis(v->cam_o, o);
+    int rc = make_basis(S.cam_o, o);
     if (rc) return rc;
     rc = make_basis(cam, n);
     if (rc) return rc;
     memset(&f, 0, sizeof f);
-    const double aspect_o = (double)v->dev.WO / (double)v->dev.HO;
+    const double aspect_o = (double)S.dev.WO / (double)S.dev.HO;
     for (int a = 0; a < 3; ++a) {
         f.FO[a] = o.F[a];
         f.RO[a] = o.R[a];
@@ -101,12 +101,12 @@ int build_frame(const vdi_s *v, const vdi_camera &cam, int w, int h, double aspe
         f.FN[a] = n.F[a];
         f.RN[a] = n.R[a];
         f.UN[a] = n.U[a];
-        f.bmin[a] = v->bmin[a];
-        f.bmax[a] = v->bmax[a];
+        f.bmin[a] = S.bmin[a];
+        f.bmax[a] = S.bmax[a];
     }
     f.sx_o = 1.0 / (o.th * aspect_o);
     f.sy_o = 1.0 / o.th;
-    f.near_o = v->cam_o.near_plane;
+    f.near_o = S.cam_o.near_plane;
     double rel[3];
     for (int a = 0; a < 3; ++a) rel[a] = n.eye[a] - o.eye[a];
     f.X0 = dot(o.R, rel) * f.sx_o;
@@ -160,8 +160,9 @@ int render_impl(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, float D_I,
     if (rc) return rc;
     int32_t w, h;
     lowres_dims(W, H, D_I, &w, &h);
+    const vdi::VdiSet S = vdi::current(v);
     vdi::Frame f;
-    rc = build_frame(v, *cam, w, h, (double)W / (double)H, f);
+    rc = build_frame(S, *cam, w, h, (double)W / (double)H, f);
     if (rc) return rc;
     rc = check_opts(opts, f);
     if (rc) return rc;
@@ -171,7 +172,7 @@ int render_impl(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, float D_I,
     if (down) HIP_OR_FAIL(hipMallocAsync((void **)&lo, (size_t)w * h * sizeof(float4), s), "preview scratch");
     f.out = down ? lo : reinterpret_cast<float4 *>(out);
     f.DR = D_R;
-    hipError_t e = D_R > 0.0f ? vdi::launch_render_preview(v->dev, f, s) : vdi::launch_render_exact(v->dev, f, false, s);
+    hipError_t e = D_R > 0.0f ? vdi::launch_render_preview(S.dev, f, s) : vdi::launch_render_exact(S.dev, f, false, s);
     if (e == hipSuccess && down) e = vdi::launch_upsample(lo, w, h, reinterpret_cast<float4 *>(out), W, H, s);
     if (down) {
         hipError_t e2 = hipFreeAsync(lo, s);
@@ -209,16 +210,167 @@ int validate_lists(const vdi_desc *d)
     return VDI_OK;
 }
 
+void free_set(vdi::VdiSet &S)
+{
+    // Errors are ignored: every pointer was allocated here or is null.
+    (void)hipFree(S.d_count);
+    (void)hipFree(S.d_depth);
+    (void)hipFree(S.d_rgba);
+    (void)hipFree(S.d_grid);
+    (void)hipFree(S.d_gz);
+    S = vdi::VdiSet();
+}
+
 void free_vdi(vdi_s *v)
 {
     if (!v) return;
-    // Errors are ignored: every pointer was allocated here or is null.
-    (void)hipFree(v->d_count);
-    (void)hipFree(v->d_depth);
-    (void)hipFree(v->d_rgba);
-    (void)hipFree(v->d_grid);
-    (void)hipFree(v->d_gz);
+    free_set(v->cur);
+    free_set(v->back);
+    if (v->stage) (void)hipFree(v->stage);
+    if (v->start) (void)hipEventDestroy(v->start);
+    if (v->ready) (void)hipEventDestroy(v->ready);
+    if (v->copy) (void)hipStreamDestroy(v->copy);
     delete v;
+}
+
+// Checks of a descriptor common to vdi_create and vdi_replace_begin; on
+// success fills the V_O basis and the grid slice boundaries.
+int check_desc(const vdi_desc *d, Basis &ob, std::vector<float> &gz)
+{
+    if (d->width < 1 || d->height < 1 || d->width > 32768 || d->height > 32768)
+        return fail(VDI_ERR_ARG, "VDI size %dx%d out of range", d->width, d->height);
+    if (d->max_supersegments < 1 || d->max_supersegments > VDI_MAX_SUPERSEGMENTS)
+        return fail(VDI_ERR_ARG, "max_supersegments must be in [1, 255]");
+    if (!d->count || !d->depth || !d->rgba) return fail(VDI_ERR_ARG, "null VDI plane");
+    if (d->rgba_fmt_in < VDI_F32 || d->rgba_fmt_in > VDI_BF16 || d->rgba_fmt_store < VDI_F32 ||
+        d->rgba_fmt_store > VDI_BF16)
+        return fail(VDI_ERR_ARG, "unknown colour format");
+    if (d->rgba_fmt_in != VDI_F32 && d->rgba_fmt_in != d->rgba_fmt_store)
+        return fail(VDI_ERR_ARG, "16-bit colour input must be stored in the same format");
+    if (d->grid_k < 1 || d->grid_k > VDI_MAX_GRID_K || d->grid_nz < 1 || d->grid_nz > VDI_MAX_GRID_NZ)
+        return fail(VDI_ERR_ARG, "grid shape out of range (k 1..16, nz 1..64)");
+    // Cell indices are 32-bit in the kernels.
+    if ((uint64_t)d->grid_nz * ((d->width + d->grid_k - 1) / d->grid_k) * ((d->height + d->grid_k - 1) / d->grid_k) >=
+        (1ull << 31))
+        return fail(VDI_ERR_ARG, "count grid too large (needs fewer than 2^31 cells)");
+    if (!finite3(d->aabb_min) || !finite3(d->aabb_max)) return fail(VDI_ERR_ARG, "non-finite AABB");
+    for (int a = 0; a < 3; ++a)
+        if (!(d->aabb_max[a] > d->aabb_min[a])) return fail(VDI_ERR_ARG, "empty AABB");
+    int rc = make_basis(d->camera_VO, ob);
+    if (rc) return rc;
+    const uint64_t plane = (uint64_t)d->width * d->height;
+    for (uint64_t li = 0; li < plane; ++li)
+        if (d->count[li] > d->max_supersegments) return fail(VDI_ERR_ARG, "a list count exceeds max_supersegments");
+    if (d->validate) {
+        rc = validate_lists(d);
+        if (rc) return rc;
+    }
+    // Grid slice boundaries.
+    gz.assign(d->grid_nz + 1, 0.0f);
+    if (d->grid_z) {
+        for (int c = 0; c <= d->grid_nz; ++c) {
+            gz[c] = d->grid_z[c];
+            if (!isfinite(gz[c]) || (c > 0 && !(gz[c] > gz[c - 1])))
+                return fail(VDI_ERR_ARG, "grid_z must be finite and strictly increasing");
+        }
+    } else {
+        double lo = INFINITY, hi = -INFINITY;
+        for (int m = 0; m < 8; ++m) {
+            double p[3] = {(m & 1) ? d->aabb_max[0] : d->aabb_min[0], (m & 2) ? d->aabb_max[1] : d->aabb_min[1],
+                           (m & 4) ? d->aabb_max[2] : d->aabb_min[2]};
+            double rel[3] = {p[0] - ob.eye[0], p[1] - ob.eye[1], p[2] - ob.eye[2]};
+            const double z = dot(ob.F, rel);
+            lo = std::min(lo, z);
+            hi = std::max(hi, z);
+        }
+        lo -= 1e-3;
+        hi += 1e-3;
+        for (int c = 0; c <= d->grid_nz; ++c) gz[c] = (float)(lo + (hi - lo) * c / d->grid_nz);
+    }
+    return VDI_OK;
+}
+
+uint64_t set_bytes_of(const vdi_desc *d)
+{
+    const uint64_t plane = (uint64_t)d->width * d->height;
+    const uint64_t colour = d->rgba_fmt_store == VDI_F32 ? 16 : 8;
+    const uint64_t gw = (d->width + d->grid_k - 1) / d->grid_k, gh = (d->height + d->grid_k - 1) / d->grid_k;
+    return plane + vdi::plane_elems(plane, d->max_supersegments) * (8 + colour) +
+           (uint64_t)d->grid_nz * gw * gh * sizeof(uint32_t) + (uint64_t)(d->grid_nz + 1) * sizeof(float);
+}
+
+// Upload d into the set S on stream st: allocate S's buffers if it has none,
+// copy the count plane and slice boundaries, stage whole slot planes through
+// `stage` (stage_bytes) and scatter them into storage order (colour
+// converted on the way), then build the count grid.  Enqueues only; the
+// caller synchronises.  `gz` must stay valid until the work has run.
+hipError_t upload_set(vdi::VdiSet &S, const vdi_desc *d, const Basis &ob, const std::vector<float> &gz, hipStream_t st,
+                      void *stage, uint64_t stage_bytes, const char **what)
+{
+    const uint64_t plane = (uint64_t)d->width * d->height;
+    const uint64_t ns = (uint64_t)d->max_supersegments;
+    const size_t colour = d->rgba_fmt_store == VDI_F32 ? 16 : 8;
+    vdi::DevVDI &D = S.dev;
+    D.WO = d->width;
+    D.HO = d->height;
+    D.NS = d->max_supersegments;
+    D.fmt = d->rgba_fmt_store;
+    D.plane = plane;
+    D.sstride = vdi::kBrick ? (uint64_t)vdi::kBrick : plane;
+    D.gk = d->grid_k;
+    D.gnz = d->grid_nz;
+    D.GW = (d->width + d->grid_k - 1) / d->grid_k;
+    D.GH = (d->height + d->grid_k - 1) / d->grid_k;
+    D.tx_o = (float)(ob.th * ((double)d->width / d->height));
+    D.ty_o = (float)ob.th;
+    D.dcx = 2.0 / d->width;
+    D.dcy = 2.0 / d->height;
+    D.inv_gk = nextafterf(1.0f / (float)d->grid_k, INFINITY);
+    S.cam_o = d->camera_VO;
+    memcpy(S.bmin, d->aabb_min, sizeof S.bmin);
+    memcpy(S.bmax, d->aabb_max, sizeof S.bmax);
+    const uint64_t elems = vdi::plane_elems(plane, (int)ns);
+    const size_t grid_bytes = (size_t)D.gnz * D.GH * D.GW * sizeof(uint32_t);
+    hipError_t e = hipSuccess;
+    if (!S.d_count) {
+        *what = "device allocation";
+        if (e == hipSuccess) e = hipMalloc((void **)&S.d_count, plane);
+        if (e == hipSuccess) e = hipMalloc((void **)&S.d_depth, elems * sizeof(float2));
+        if (e == hipSuccess) e = hipMalloc(&S.d_rgba, elems * colour);
+        if (e == hipSuccess) e = hipMalloc((void **)&S.d_grid, grid_bytes);
+        if (e == hipSuccess) e = hipMalloc((void **)&S.d_gz, gz.size() * sizeof(float));
+        if (e != hipSuccess) return e;
+    }
+    D.count = S.d_count;
+    D.depth = S.d_depth;
+    D.rgba = S.d_rgba;
+    D.grid = S.d_grid;
+    D.gz = S.d_gz;
+    *what = "upload";
+    e = hipMemcpyAsync(S.d_count, d->count, plane, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(S.d_gz, gz.data(), gz.size() * sizeof(float), hipMemcpyHostToDevice, st);
+    const size_t colour_in = d->rgba_fmt_in == VDI_F32 ? 16 : 8;
+    const uint64_t slots = std::max<uint64_t>(1, std::min<uint64_t>(ns, stage_bytes / (plane * 16)));
+    for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+        const bool dep = pass == 0;
+        const size_t esz = dep ? sizeof(float2) : colour_in;
+        const char *src = static_cast<const char *>(dep ? (const void *)d->depth : d->rgba);
+        for (uint64_t j0 = 0; j0 < ns && e == hipSuccess; j0 += slots) {
+            const uint64_t nj = std::min(slots, ns - j0);
+            // Stream order keeps the staging buffer from being refilled before it is scattered.
+            e = hipMemcpyAsync(stage, src + j0 * plane * esz, nj * plane * esz, hipMemcpyHostToDevice, st);
+            if (e == hipSuccess)
+                e = vdi::launch_scatter_slots(stage, d->rgba_fmt_in, dep ? (void *)S.d_depth : S.d_rgba, d->rgba_fmt_store,
+                                              dep, nj * plane, D, (int32_t)j0, st);
+        }
+    }
+    if (e != hipSuccess) return e;
+    *what = "grid build";
+    e = vdi::launch_grid_build(D, S.d_grid, st);
+    uint64_t total = 0;
+    for (uint64_t li = 0; li < plane; ++li) total += d->count[li];
+    S.supersegments = total;
+    return e;
 }
 
 }  // namespace
@@ -240,9 +392,14 @@ int check_render_args(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, floa
     return ::check_args(v, cam, W, H, D_I, D_R, out);
 }
 void lowres_size(int32_t W, int32_t H, float D_I, int32_t *w, int32_t *h) { ::lowres_dims(W, H, D_I, w, h); }
-int make_frame(const vdi_s *v, const vdi_camera &cam, int w, int h, double aspect, Frame &f)
+int make_frame(const VdiSet &S, const vdi_camera &cam, int w, int h, double aspect, Frame &f)
 {
-    return ::build_frame(v, cam, w, h, aspect, f);
+    return ::build_frame(S, cam, w, h, aspect, f);
+}
+VdiSet current(vdi_s *v)
+{
+    std::lock_guard<std::mutex> lock(v->mu);
+    return v->cur;
 }
 }  // namespace vdi
 
@@ -269,141 +426,99 @@ int vdi_create(const vdi_desc *d, vdi_t *out)
 {
     g_err.clear();
     if (!d || !out) return fail(VDI_ERR_ARG, "null argument");
-    if (d->width < 1 || d->height < 1 || d->width > 32768 || d->height > 32768)
-        return fail(VDI_ERR_ARG, "VDI size %dx%d out of range", d->width, d->height);
-    if (d->max_supersegments < 1 || d->max_supersegments > VDI_MAX_SUPERSEGMENTS)
-        return fail(VDI_ERR_ARG, "max_supersegments must be in [1, 255]");
-    if (!d->count || !d->depth || !d->rgba) return fail(VDI_ERR_ARG, "null VDI plane");
-    if (d->rgba_fmt_in < VDI_F32 || d->rgba_fmt_in > VDI_BF16 || d->rgba_fmt_store < VDI_F32 ||
-        d->rgba_fmt_store > VDI_BF16)
-        return fail(VDI_ERR_ARG, "unknown colour format");
-    if (d->rgba_fmt_in != VDI_F32 && d->rgba_fmt_in != d->rgba_fmt_store)
-        return fail(VDI_ERR_ARG, "16-bit colour input must be stored in the same format");
-    if (d->grid_k < 1 || d->grid_k > VDI_MAX_GRID_K || d->grid_nz < 1 || d->grid_nz > VDI_MAX_GRID_NZ)
-        return fail(VDI_ERR_ARG, "grid shape out of range (k 1..16, nz 1..64)");
-    // Cell indices are 32-bit in the kernels.
-    if ((uint64_t)d->grid_nz * ((d->width + d->grid_k - 1) / d->grid_k) * ((d->height + d->grid_k - 1) / d->grid_k) >=
-        (1ull << 31))
-        return fail(VDI_ERR_ARG, "count grid too large (needs fewer than 2^31 cells)");
-    if (!finite3(d->aabb_min) || !finite3(d->aabb_max)) return fail(VDI_ERR_ARG, "non-finite AABB");
-    for (int a = 0; a < 3; ++a)
-        if (!(d->aabb_max[a] > d->aabb_min[a])) return fail(VDI_ERR_ARG, "empty AABB");
     Basis ob;
-    int rc = make_basis(d->camera_VO, ob);
+    std::vector<float> gz;
+    int rc = check_desc(d, ob, gz);
     if (rc) return rc;
-
-    const uint64_t plane = (uint64_t)d->width * d->height;
-    for (uint64_t li = 0; li < plane; ++li)
-        if (d->count[li] > d->max_supersegments) return fail(VDI_ERR_ARG, "a list count exceeds max_supersegments");
-    if (d->validate) {
-        rc = validate_lists(d);
-        if (rc) return rc;
-    }
-    // Grid slice boundaries.
-    std::vector<float> gz(d->grid_nz + 1);
-    if (d->grid_z) {
-        for (int c = 0; c <= d->grid_nz; ++c) {
-            gz[c] = d->grid_z[c];
-            if (!isfinite(gz[c]) || (c > 0 && !(gz[c] > gz[c - 1])))
-                return fail(VDI_ERR_ARG, "grid_z must be finite and strictly increasing");
-        }
-    } else {
-        double lo = INFINITY, hi = -INFINITY;
-        for (int m = 0; m < 8; ++m) {
-            double p[3] = {(m & 1) ? d->aabb_max[0] : d->aabb_min[0], (m & 2) ? d->aabb_max[1] : d->aabb_min[1],
-                           (m & 4) ? d->aabb_max[2] : d->aabb_min[2]};
-            double rel[3] = {p[0] - ob.eye[0], p[1] - ob.eye[1], p[2] - ob.eye[2]};
-            const double z = dot(ob.F, rel);
-            lo = std::min(lo, z);
-            hi = std::max(hi, z);
-        }
-        lo -= 1e-3;
-        hi += 1e-3;
-        for (int c = 0; c <= d->grid_nz; ++c) gz[c] = (float)(lo + (hi - lo) * c / d->grid_nz);
-    }
-
     vdi_s *v = new (std::nothrow) vdi_s();
     if (!v) return fail(VDI_ERR_OOM, "host allocation");
-    hipError_t e0;
-    if ((e0 = hipGetDevice(&v->device)) != hipSuccess) {
+    hipError_t e = hipGetDevice(&v->device);
+    if (e != hipSuccess) {
         delete v;
-        return hip_fail(e0, "hipGetDevice");
+        return hip_fail(e, "hipGetDevice");
     }
-    v->cam_o = d->camera_VO;
-    memcpy(v->bmin, d->aabb_min, sizeof v->bmin);
-    memcpy(v->bmax, d->aabb_max, sizeof v->bmax);
-    vdi::DevVDI &D = v->dev;
-    D.WO = d->width;
-    D.HO = d->height;
-    D.NS = d->max_supersegments;
-    D.fmt = d->rgba_fmt_store;
-    D.plane = plane;
-    D.gk = d->grid_k;
-    D.gnz = d->grid_nz;
-    D.GW = (d->width + d->grid_k - 1) / d->grid_k;
-    D.GH = (d->height + d->grid_k - 1) / d->grid_k;
-    D.tx_o = (float)(ob.th * ((double)d->width / d->height));
-    D.ty_o = (float)ob.th;
-    D.dcx = 2.0 / d->width;
-    D.dcy = 2.0 / d->height;
-    D.inv_gk = nextafterf(1.0f / (float)d->grid_k, INFINITY);
-
-    const uint64_t ns = (uint64_t)d->max_supersegments;
-    const size_t colour = d->rgba_fmt_store == VDI_F32 ? 16 : 8;
-    const size_t grid_bytes = (size_t)D.gnz * D.GH * D.GW * sizeof(uint32_t);
-    hipError_t e;
-    auto bail = [&](hipError_t err, const char *what) {
-        int code = hip_fail(err, what);
-        free_vdi(v);
-        return code;
-    };
-    const uint64_t elems = vdi::plane_elems(plane, (int)ns);
-    D.sstride = vdi::kBrick ? (uint64_t)vdi::kBrick : plane;
-    if ((e = hipMalloc((void **)&v->d_count, plane)) != hipSuccess) return bail(e, "hipMalloc count");
-    if ((e = hipMalloc((void **)&v->d_depth, elems * sizeof(float2))) != hipSuccess) return bail(e, "hipMalloc depth");
-    if ((e = hipMalloc(&v->d_rgba, elems * colour)) != hipSuccess) return bail(e, "hipMalloc rgba");
-    if ((e = hipMalloc((void **)&v->d_grid, grid_bytes)) != hipSuccess) return bail(e, "hipMalloc grid");
-    if ((e = hipMalloc((void **)&v->d_gz, gz.size() * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc grid_z");
-    if ((e = hipMemcpy(v->d_count, d->count, plane, hipMemcpyHostToDevice)) != hipSuccess) return bail(e, "upload count");
-    if ((e = hipMemcpy(v->d_gz, gz.data(), gz.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
-        return bail(e, "upload grid_z");
-    {
-        // Whole slot planes go through a bounded staging buffer and are
-        // scattered into storage order (colour converted on the way).
-        const size_t colour_in = d->rgba_fmt_in == VDI_F32 ? 16 : 8;
-        const uint64_t per_chunk = std::max<uint64_t>(1, (256ull << 20) / (plane * 16));
-        const uint64_t slots = std::min<uint64_t>(ns, per_chunk);
-        void *stage = nullptr;
-        if ((e = hipMalloc(&stage, slots * plane * 16)) != hipSuccess) return bail(e, "hipMalloc staging");
-        for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
-            const bool dep = pass == 0;
-            const size_t esz = dep ? sizeof(float2) : colour_in;
-            const char *src = static_cast<const char *>(dep ? (const void *)d->depth : d->rgba);
-            for (uint64_t j0 = 0; j0 < ns && e == hipSuccess; j0 += slots) {
-                const uint64_t nj = std::min(slots, ns - j0);
-                e = hipMemcpy(stage, src + j0 * plane * esz, nj * plane * esz, hipMemcpyHostToDevice);
-                if (e == hipSuccess)
-                    e = vdi::launch_scatter_slots(stage, d->rgba_fmt_in, dep ? (void *)v->d_depth : v->d_rgba,
-                                                  d->rgba_fmt_store, dep, nj * plane, D, (int32_t)j0, 0);
-                if (e == hipSuccess) e = hipDeviceSynchronize();
-            }
-        }
+    const uint64_t plane = (uint64_t)d->width * d->height;
+    const uint64_t stage_bytes = std::max<uint64_t>(256ull << 20, plane * 16);
+    void *stage = nullptr;
+    const char *what = "staging";
+    e = hipMalloc(&stage, stage_bytes);
+    if (e == hipSuccess) e = upload_set(v->cur, d, ob, gz, 0, stage, stage_bytes, &what);
+    if (e == hipSuccess) what = "upload", e = hipDeviceSynchronize();
+    if (stage) {
         const hipError_t ef = hipFree(stage);
         if (e == hipSuccess) e = ef;
-        if (e != hipSuccess) return bail(e, "upload planes");
     }
-    D.count = v->d_count;
-    D.depth = v->d_depth;
-    D.rgba = v->d_rgba;
-    D.grid = v->d_grid;
-    D.gz = v->d_gz;
-    if ((e = vdi::launch_grid_build(D, v->d_grid, 0)) != hipSuccess) return bail(e, "grid build");
-    if ((e = hipDeviceSynchronize()) != hipSuccess) return bail(e, "grid build");
-    uint64_t total = 0;
-    for (uint64_t li = 0; li < plane; ++li) total += d->count[li];
-    v->supersegments = total;
-    v->device_bytes = plane + elems * (sizeof(float2) + colour) + grid_bytes + gz.size() * sizeof(float);
+    if (e != hipSuccess) {
+        rc = hip_fail(e, what);
+        free_vdi(v);
+        return rc;
+    }
+    v->set_bytes = set_bytes_of(d);
     *out = v;
+    return VDI_OK;
+}
+
+int vdi_replace_begin(vdi_t v, const vdi_desc *d, void *stream)
+{
+    g_err.clear();
+    if (!v || !d) return fail(VDI_ERR_ARG, "null argument");
+    Basis ob;
+    std::vector<float> gz;
+    int rc = check_desc(d, ob, gz);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lock(v->mu);
+        const vdi::DevVDI &C = v->cur.dev;
+        if (d->width != C.WO || d->height != C.HO || d->max_supersegments != C.NS || d->rgba_fmt_store != C.fmt ||
+            d->grid_k != C.gk || d->grid_nz != C.gnz)
+            return fail(VDI_ERR_ARG, "the replacement must have the shape, N_S, colour format and grid of the VDI");
+        if (v->pending) return fail(VDI_ERR_STATE, "a replacement is already pending");
+        v->pending = true;
+        v->enqueued = false;
+        v->gz_host = gz;
+    }
+    // From here only this call touches the back set and the copy stream.
+    const uint64_t plane = (uint64_t)d->width * d->height;
+    const char *what = "replacement set-up";
+    hipError_t e = hipSetDevice(v->device);
+    if (e == hipSuccess && !v->copy) {
+        e = hipStreamCreateWithFlags(&v->copy, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&v->start, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&v->ready, hipEventDisableTiming);
+        if (e == hipSuccess) {
+            v->stage_bytes = std::max<uint64_t>(256ull << 20, plane * 16);
+            e = hipMalloc(&v->stage, v->stage_bytes);
+        }
+    }
+    // The back set may be the one renders used before the last swap: the
+    // upload waits for the work already enqueued on the caller's stream.
+    if (e == hipSuccess) e = hipEventRecord(v->start, static_cast<hipStream_t>(stream));
+    if (e == hipSuccess) e = hipStreamWaitEvent(v->copy, v->start, 0);
+    if (e == hipSuccess) e = upload_set(v->back, d, ob, v->gz_host, v->copy, v->stage, v->stage_bytes, &what);
+    if (e == hipSuccess) what = "replacement", e = hipEventRecord(v->ready, v->copy);
+    std::lock_guard<std::mutex> lock(v->mu);
+    if (e != hipSuccess) {
+        v->pending = false;
+        return hip_fail(e, what);
+    }
+    v->enqueued = true;
+    return VDI_OK;
+}
+
+int vdi_replace_poll(vdi_t v, int32_t *swapped)
+{
+    g_err.clear();
+    if (!v || !swapped) return fail(VDI_ERR_ARG, "null argument");
+    *swapped = 0;
+    std::lock_guard<std::mutex> lock(v->mu);
+    if (!v->pending || !v->enqueued) return VDI_OK;
+    const hipError_t q = hipEventQuery(v->ready);
+    if (q == hipErrorNotReady) return VDI_OK;
+    v->pending = false;
+    v->enqueued = false;
+    if (q != hipSuccess) return hip_fail(q, "replacement upload");
+    std::swap(v->cur, v->back);
+    *swapped = 1;
     return VDI_OK;
 }
 
@@ -427,8 +542,9 @@ int vdi_render_counters(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, co
     int rc = check_args(v, cam, W, H, 1.0f, 0.0f, out);
     if (rc) return rc;
     if (!touched_lists || !touched_slots) return fail(VDI_ERR_ARG, "null counter buffer");
+    const vdi::VdiSet S = vdi::current(v);
     vdi::Frame f;
-    rc = build_frame(v, *cam, W, H, (double)W / (double)H, f);
+    rc = build_frame(S, *cam, W, H, (double)W / (double)H, f);
     if (rc) return rc;
     rc = check_opts(opts, f);
     if (rc) return rc;
@@ -437,7 +553,7 @@ int vdi_render_counters(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, co
     f.touched_lists = touched_lists;
     f.touched_slots = touched_slots;
     f.ray_stats = ray_stats;
-    HIP_OR_FAIL(vdi::launch_render_exact(v->dev, f, true, static_cast<hipStream_t>(stream)), "counter render launch");
+    HIP_OR_FAIL(vdi::launch_render_exact(S.dev, f, true, static_cast<hipStream_t>(stream)), "counter render launch");
     return VDI_OK;
 }
 
@@ -445,10 +561,11 @@ int vdi_get_grid(vdi_t v, uint32_t *host_out, size_t capacity)
 {
     g_err.clear();
     if (!v || !host_out) return fail(VDI_ERR_ARG, "null argument");
-    const size_t n = (size_t)v->dev.gnz * v->dev.GH * v->dev.GW;
+    const vdi::VdiSet S = vdi::current(v);
+    const size_t n = (size_t)S.dev.gnz * S.dev.GH * S.dev.GW;
     if (capacity < n) return fail(VDI_ERR_ARG, "grid needs %zu elements", n);
     HIP_OR_FAIL(hipSetDevice(v->device), "hipSetDevice");
-    HIP_OR_FAIL(hipMemcpy(host_out, v->d_grid, n * sizeof(uint32_t), hipMemcpyDeviceToHost), "grid download");
+    HIP_OR_FAIL(hipMemcpy(host_out, S.d_grid, n * sizeof(uint32_t), hipMemcpyDeviceToHost), "grid download");
     return VDI_OK;
 }
 
@@ -456,16 +573,18 @@ int vdi_get_info(vdi_t v, vdi_info_t *info)
 {
     g_err.clear();
     if (!v || !info) return fail(VDI_ERR_ARG, "null argument");
-    info->width = v->dev.WO;
-    info->height = v->dev.HO;
-    info->max_supersegments = v->dev.NS;
-    info->rgba_fmt = v->dev.fmt;
-    info->grid_k = v->dev.gk;
-    info->grid_nz = v->dev.gnz;
-    info->grid_w = v->dev.GW;
-    info->grid_h = v->dev.GH;
-    info->device_bytes = v->device_bytes;
-    info->supersegments = v->supersegments;
+    std::lock_guard<std::mutex> lock(v->mu);
+    const vdi::VdiSet &S = v->cur;
+    info->width = S.dev.WO;
+    info->height = S.dev.HO;
+    info->max_supersegments = S.dev.NS;
+    info->rgba_fmt = S.dev.fmt;
+    info->grid_k = S.dev.gk;
+    info->grid_nz = S.dev.gnz;
+    info->grid_w = S.dev.GW;
+    info->grid_h = S.dev.GH;
+    info->device_bytes = v->set_bytes * (v->back.d_count ? 2 : 1) + (v->stage ? v->stage_bytes : 0);
+    info->supersegments = S.supersegments;
     return VDI_OK;
 }
 

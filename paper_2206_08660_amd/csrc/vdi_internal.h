@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+#include <vector>
+
 #include "vdi.h"
 
 namespace vdi {
@@ -99,18 +102,38 @@ struct UpsampleJob {
 
 }  // namespace vdi
 
-// A resident VDI (the object behind vdi_t).
-struct vdi_s {
-    vdi::DevVDI dev;
-    vdi_camera cam_o;
-    float bmin[3], bmax[3];
-    int device;
+namespace vdi {
+// One set of device buffers of a resident VDI, with the metadata of the view
+// it was generated from.
+struct VdiSet {
+    DevVDI dev{};
+    vdi_camera cam_o{};
+    float bmin[3]{}, bmax[3]{};
     uint8_t *d_count = nullptr;
     float2 *d_depth = nullptr;
     void *d_rgba = nullptr;
     uint32_t *d_grid = nullptr;
     float *d_gz = nullptr;
-    uint64_t device_bytes = 0, supersegments = 0;
+    uint64_t supersegments = 0;
+};
+}  // namespace vdi
+
+// A resident VDI (the object behind vdi_t).  Renders use `cur`; a
+// replacement uploads into `back` on the copy stream and the two are swapped
+// once the upload has finished (vdi_replace_begin / vdi_replace_poll).
+struct vdi_s {
+    vdi::VdiSet cur, back;
+    int device = 0;
+    uint64_t set_bytes = 0;          // device bytes of one set
+    std::mutex mu;                   // guards cur, back and the replacement state
+    hipStream_t copy = nullptr;      // replacement uploads
+    hipEvent_t start = nullptr;      // caller's stream reached vdi_replace_begin
+    hipEvent_t ready = nullptr;      // the pending upload has finished
+    void *stage = nullptr;           // staging buffer of replacement uploads
+    uint64_t stage_bytes = 0;
+    bool pending = false;            // a replacement was started and not yet swapped in
+    bool enqueued = false;           // ... and all of its work is on the copy stream
+    std::vector<float> gz_host;      // slice boundaries of the pending upload
 };
 
 namespace vdi {
@@ -123,7 +146,9 @@ int check_render_args(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, floa
 // Ray-grid size for downsampling factor D_I.
 void lowres_size(int32_t W, int32_t H, float D_I, int32_t *w, int32_t *h);
 // Frame constants for rays on a w x h grid of camera `cam` with aspect `aspect`.
-int make_frame(const vdi_s *v, const vdi_camera &cam, int w, int h, double aspect, Frame &f);
+int make_frame(const VdiSet &s, const vdi_camera &cam, int w, int h, double aspect, Frame &f);
+// Copy of v's current set, taken under its lock.
+VdiSet current(vdi_s *v);
 
 // Launchers (vdi_kernels.hip).  All run on `stream` and return the launch status.
 hipError_t launch_render_exact(const DevVDI &v, const Frame &f, bool counters, hipStream_t stream);

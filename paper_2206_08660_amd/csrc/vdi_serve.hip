@@ -303,7 +303,8 @@ int vdi_server_submit(vdi_server_t s, vdi_t v, const vdi_camera *cam, int32_t W,
     const uint64_t lowres_bytes = down ? (uint64_t)w * h * sizeof(float4) : 0;
     const uint64_t bytes = (uint64_t)W * H * sizeof(float4) + lowres_bytes;
     vdi::Request r;
-    rc = vdi::make_frame(v, *cam, w, h, (double)W / (double)H, r.job.F);
+    const vdi::VdiSet S = vdi::current(v);
+    rc = vdi::make_frame(S, *cam, w, h, (double)W / (double)H, r.job.F);
     if (rc) return rc;
     std::unique_lock<std::mutex> lock(s->mu);
     if (s->err) return vdi::report(s);
@@ -343,14 +344,14 @@ int vdi_server_submit(vdi_server_t s, vdi_t v, const vdi_camera *cam, int32_t W,
             }
         }
     }
-    r.job.V = v->dev;
+    r.job.V = S.dev;
     r.job.F.out = down ? r.lowres : reinterpret_cast<float4 *>(out);
     r.job.F.DR = D_R;
     r.job.F.ess = 1;
     r.job.F.search = VDI_SEARCH_WINDOW;
     r.job.tile0 = 0;
     r.job.ntiles = vdi::tiles_of(w, h);
-    r.fmt = v->dev.fmt;
+    r.fmt = S.dev.fmt;
     r.preview = D_R > 0.0f;
     r.down = down;
     if (down) r.up = vdi::UpsampleJob{r.lowres, reinterpret_cast<float4 *>(out), w, h, W, H, 0, vdi::tiles_of(W, H)};

@@ -29,7 +29,7 @@ SEARCH = {"seeded": 0, "binary": 1, "linear": 2, "window": 3}
 EXPORTS = ("vdi_create", "vdi_render", "vdi_render_ex", "vdi_render_counters", "vdi_get_grid", "vdi_get_info",
            "vdi_destroy", "vdi_lowres_size", "vdi_plane_bytes", "vdi_last_error", "vdi_server_create",
            "vdi_server_submit", "vdi_server_poll", "vdi_server_drain", "vdi_server_get_stats",
-           "vdi_server_reset_stats", "vdi_server_destroy")
+           "vdi_server_reset_stats", "vdi_server_destroy", "vdi_replace_begin", "vdi_replace_poll")
 
 
 class VdiError(RuntimeError):
@@ -89,6 +89,8 @@ def lib() -> ctypes.CDLL:
         L.vdi_get_grid.argtypes = [P, P, ctypes.c_size_t]
         L.vdi_get_info.argtypes = [P, ctypes.POINTER(Info)]
         L.vdi_destroy.argtypes = [P]
+        L.vdi_replace_begin.argtypes = [P, ctypes.POINTER(Desc), P]
+        L.vdi_replace_poll.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
         L.vdi_lowres_size.argtypes = [I32, I32, F, ctypes.POINTER(I32), ctypes.POINTER(I32)]
         L.vdi_plane_bytes.argtypes = [I32, I32, I32, I32]
         L.vdi_plane_bytes.restype = ctypes.c_uint64
@@ -146,6 +148,30 @@ def _opts(ess: bool, search: str) -> Opts:
     return Opts(1 if ess else 0, SEARCH[search])
 
 
+def _desc(src, store: str, validate: bool, rgba_in, fmt_in: str):
+    """vdi_desc for src, and the arrays it points to (kept alive by the caller)."""
+    count = np.ascontiguousarray(src.count, dtype=np.uint8)
+    depth = np.ascontiguousarray(src.depth, dtype=np.float32)
+    rgba = np.ascontiguousarray(src.rgba if rgba_in is None else rgba_in)
+    if fmt_in == "f32":
+        rgba = rgba.astype(np.float32, copy=False)
+    gz = None if src.grid_z is None else np.ascontiguousarray(src.grid_z, dtype=np.float32)
+    d = Desc()
+    d.width, d.height, d.max_supersegments = src.width, src.height, src.ns
+    d.camera_VO = camera(src.camera)
+    d.aabb_min[:] = [float(x) for x in src.bmin]
+    d.aabb_max[:] = [float(x) for x in src.bmax]
+    d.count = count.ctypes.data
+    d.depth = depth.ctypes.data
+    d.rgba = rgba.ctypes.data
+    d.rgba_fmt_in = FORMATS[fmt_in]
+    d.rgba_fmt_store = FORMATS[store]
+    d.grid_k, d.grid_nz = src.grid_k, src.grid_nz
+    d.grid_z = None if gz is None else gz.ctypes.data
+    d.validate = 1 if validate else 0
+    return d, (count, depth, rgba, gz)
+
+
 class Vdi:
     """A VDI resident in device memory (vdi_create ... vdi_destroy)."""
 
@@ -154,29 +180,24 @@ class Vdi:
         """src: any object with width, height, ns, camera, bmin, bmax, count,
         depth, rgba, grid_k, grid_nz, grid_z (e.g. inputs.VDI)."""
         self._h = None
-        count = np.ascontiguousarray(src.count, dtype=np.uint8)
-        depth = np.ascontiguousarray(src.depth, dtype=np.float32)
-        rgba = np.ascontiguousarray(src.rgba if rgba_in is None else rgba_in)
-        if fmt_in == "f32":
-            rgba = rgba.astype(np.float32, copy=False)
-        gz = None if src.grid_z is None else np.ascontiguousarray(src.grid_z, dtype=np.float32)
-        d = Desc()
-        d.width, d.height, d.max_supersegments = src.width, src.height, src.ns
-        d.camera_VO = camera(src.camera)
-        d.aabb_min[:] = [float(x) for x in src.bmin]
-        d.aabb_max[:] = [float(x) for x in src.bmax]
-        d.count = count.ctypes.data
-        d.depth = depth.ctypes.data
-        d.rgba = rgba.ctypes.data
-        d.rgba_fmt_in = FORMATS[fmt_in]
-        d.rgba_fmt_store = FORMATS[store]
-        d.grid_k, d.grid_nz = src.grid_k, src.grid_nz
-        d.grid_z = None if gz is None else gz.ctypes.data
-        d.validate = 1 if validate else 0
+        d, _keep = _desc(src, store, validate, rgba_in, fmt_in)
         h = ctypes.c_void_p()
         _check(lib().vdi_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
         self.width, self.height, self.ns, self.store = src.width, src.height, src.ns, store
+
+    def replace_begin(self, src, stream=None, validate: bool = False, rgba_in: Optional[np.ndarray] = None,
+                      fmt_in: str = "f32"):
+        """Start uploading another VDI of the same shape (vdi_replace_begin),
+        after the work enqueued on `stream` (default: torch's current stream)."""
+        d, _keep = _desc(src, self.store, validate, rgba_in, fmt_in)
+        _check(lib().vdi_replace_begin(self.handle, ctypes.byref(d), _stream_handle(stream)))
+
+    def replace_poll(self) -> bool:
+        """True once the replacement has been swapped in (vdi_replace_poll)."""
+        sw = ctypes.c_int32()
+        _check(lib().vdi_replace_poll(self.handle, ctypes.byref(sw)))
+        return bool(sw.value)
 
     @property
     def handle(self) -> ctypes.c_void_p:

@@ -100,3 +100,13 @@ def test_server_create_rejects_bad_arguments_before_any_device_work():
     assert "streams" in V.last_error()
     assert h.value is None
     assert lib.vdi_server_destroy(None) == V.VDI_OK
+
+
+def test_replace_rejects_null_arguments_before_any_device_work():
+    lib = V.lib()
+    d = V.Desc()
+    assert lib.vdi_replace_begin(None, ctypes.byref(d), None) == V.VDI_ERR_ARG
+    assert lib.vdi_replace_begin(ctypes.c_void_p(1), None, None) == V.VDI_ERR_ARG
+    sw = ctypes.c_int32(7)
+    assert lib.vdi_replace_poll(None, ctypes.byref(sw)) == V.VDI_ERR_ARG
+    assert lib.vdi_replace_poll(ctypes.c_void_p(1), None) == V.VDI_ERR_ARG
