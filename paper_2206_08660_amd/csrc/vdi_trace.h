@@ -623,7 +623,51 @@ VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, in
     // Every iteration moves one list or jumps a grid cell; the cap only
     // guards against a loop that does not advance.
     const int max_iter = 4 * (WO + HO) + 4 * V.gnz + 64;
+    // Crossing of the next cell boundary in x (y) for a ray in cell column c.
+    auto cell_tx = [&](int c) -> double {
+        if (sx == 0) return inf;
+        const int m = sx > 0 ? min((c + 1) * gk, WO) : c * gk;
+        return (m > 0 && m < WO) ? line_t(m, V.dcx, F.X0, r.Xp, F.Z0, r.Zp) : inf;
+    };
+    auto cell_ty = [&](int c) -> double {
+        if (sy == 0) return inf;
+        const int m = sy > 0 ? min((c + 1) * gk, HO) : c * gk;
+        return (m > 0 && m < HO) ? line_t(m, V.dcy, F.Y0, r.Yp, F.Z0, r.Zp) : inf;
+    };
+    // Cell mode (empty-space skipping): one empty grid cell per iteration, a
+    // crossing and a grid load, no division; lanes in cell mode and in list
+    // mode advance together.  Where a non-empty cell is entered the ray is
+    // located again and walks lists.
+    bool cellmode = false;
     for (int it = 0; it < max_iter; ++it) {
+        if constexpr (ESS) {
+            if (cellmode) {
+                const double te = fmin(fmin(tx, ty), fmin(tz, r.t1));
+                if (te >= r.t1) break;
+                if (tx <= ty && tx <= tz) {
+                    ix += sx;
+                    tx = cell_tx(ix);
+                } else if (ty <= tz) {
+                    iy += sy;
+                    ty = cell_ty(iy);
+                } else {
+                    cz += fwd ? 1 : -1;
+                    tz = slice_t(cz);
+                }
+                if ((unsigned)ix >= (unsigned)V.GW || (unsigned)iy >= (unsigned)V.GH || (unsigned)cz >= (unsigned)V.gnz)
+                    break;
+                t = fmax(t, te);
+                const int cell = (cz * V.GH + iy) * V.GW + ix;
+                const uint32_t g = V.grid[cell];
+                if (g != 0u) {
+                    cellmode = false;
+                    locate(t);
+                    n = V.count[(uint64_t)iy * WO + ix];
+                    ccell = -1;
+                }
+                continue;
+            }
+        }
         const double tn = fmin(fmin(tx, ty), r.t1);
         if constexpr (ESS) {
             while (tz <= t) {
@@ -637,21 +681,18 @@ VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, in
                 ccell = cell;
             }
             if (cg == 0u) {
-                // Empty-space skipping: cross the empty cell in one step.
-                double te = fmin(tz, r.t1);
-                if (sx != 0) {
-                    const int m = sx > 0 ? min((cx + 1) * gk, WO) : cx * gk;
-                    if (m > 0 && m < WO) te = fmin(te, line_t(m, V.dcx, F.X0, r.Xp, F.Z0, r.Zp));
-                }
-                if (sy != 0) {
-                    const int m = sy > 0 ? min((cy + 1) * gk, HO) : cy * gk;
-                    if (m > 0 && m < HO) te = fmin(te, line_t(m, V.dcy, F.Y0, r.Yp, F.Z0, r.Zp));
-                }
-                if (te > t) {
-                    t = te;
-                    if (t >= r.t1) break;
-                    locate(t);
-                    n = V.count[(uint64_t)iy * WO + ix];
+                // Empty-space skipping: switch to walking cells (ix, iy become
+                // the cell indices, tx, ty the crossings of cell boundaries),
+                // unless the ray sits on the cell's exit (a located position
+                // rounded onto a cell boundary): then the list step below
+                // moves it across.
+                const double ctx = cell_tx(cx), cty = cell_ty(cy);
+                if (fmin(fmin(ctx, cty), fmin(tz, r.t1)) > t) {
+                    ix = cx;
+                    iy = cy;
+                    tx = ctx;
+                    ty = cty;
+                    cellmode = true;
                     continue;
                 }
             }
