@@ -15,10 +15,13 @@ namespace vdi {
 constexpr float kTTerm = 1e-5f;
 // |F_O . d| below this: the ray keeps a constant V_O depth.
 constexpr double kFlatZ = 1e-12;
-// A workgroup renders a tile of kTileW x kTileH rays; MI355X has kXcds XCDs,
-// which take the workgroups of a launch in turn.
+// A workgroup renders a tile of kTileW x kTileH rays (one wavefront); MI355X
+// has kXcds XCDs, which take the workgroups of a launch in turn.
+#ifndef VDI_TILE_H
+#define VDI_TILE_H 1
+#endif
 constexpr int kTileW = 64;
-constexpr int kTileH = 4;
+constexpr int kTileH = VDI_TILE_H;
 constexpr int kXcds = 8;
 
 // Storage order of the depth and colour planes on the device.  Lists, taken
@@ -97,7 +100,7 @@ struct UpsampleJob {
     const float4 *lo;          // [h][w]
     float4 *out;               // [H][W]
     int32_t w, h, W, H;
-    uint32_t tile0, ntiles;    // blocks of 64 x 4 output pixels
+    uint32_t tile0, ntiles;    // blocks of 256 threads, 64 x 4 output pixels each
 };
 
 }  // namespace vdi

@@ -3,8 +3,10 @@
 // bilinear upsampling, the count grid (Section 4.3) and colour storage
 // conversion.  The per-ray code they run is in vdi_trace.h.
 //
-// Execution model.  One lane per ray; a 256-lane workgroup covers a 64 x 4
-// pixel tile, so each wavefront is 64 horizontally adjacent rays.  Their
+// Execution model.  One lane per ray; a workgroup is one wavefront covering
+// a tile of 64 horizontally adjacent pixels (kTileW x kTileH), so a CU slot
+// is freed as soon as its 64 rays are done (with 64 x 4 tiles the finished
+// wavefronts of a tile wait for its slowest one: 6% slower).  Their
 // projected lines in V_O are near-parallel and offset by about one list, so
 // neighbouring lanes read the same or neighbouring lists at similar depths.
 // The planes are stored in bricks of four horizontally adjacent lists (see

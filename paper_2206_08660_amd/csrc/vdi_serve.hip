@@ -42,11 +42,12 @@ constexpr int kMaxStreams = 8;
 constexpr int kDefaultStreams = 3;
 constexpr int kMaxSlots = 4096;
 constexpr int kMaxBatch = 256;                 // requests per batch
-// Render tiles per batch (about four 1920 x 1080 frames): enough to fill the
-// tail of each launch, small enough that a request does not wait long for
-// the rest of its batch.  A larger single request forms a batch of its own.
+// Render tiles per batch (8M rays, about four 1920 x 1080 frames): enough to
+// fill the tail of each launch, small enough that a request does not wait
+// long for the rest of its batch.  A larger single request forms a batch of
+// its own.
 #ifndef VDI_BATCH_TILES
-#define VDI_BATCH_TILES (1ull << 15)
+#define VDI_BATCH_TILES ((1ull << 23) / (kTileW * kTileH))
 #endif
 constexpr uint64_t kBatchTiles = VDI_BATCH_TILES;
 // Upsampling tiles per batch: keeps every launch far below 2^32 work-items.
