@@ -48,6 +48,7 @@ def parse():
     p.add_argument("--skip-served", action="store_true")
     p.add_argument("--skip-precision", action="store_true")
     p.add_argument("--skip-replace", action="store_true")
+    p.add_argument("--skip-paced", action="store_true")
     p.add_argument("--profile-pass", action="store_true",
                    help="short run for rocprofv3: one 1 GiB copy (counter calibration) and one exact render per angle")
     return p.parse_args()
@@ -239,6 +240,8 @@ def main():
         result["precision"] = precision_leg(src, cams, out, exact_ms, torch, V)
     if not args.skip_served:
         result["served"] = served_leg(torch, V)
+    if not args.skip_paced:
+        result["paced"] = paced_leg(h, out, stream, np)
     if not args.skip_replace:
         result["replacement"] = replace_leg(h, cams[20.0], out, stream, torch, V)
     h.close()
@@ -270,6 +273,40 @@ def precision_leg(src, cams, out, exact_ms, torch, V):
                         "device_GiB": round(hq.info().device_bytes / 2 ** 30, 3)}
         log(f"{fmt}: exact sweep {res[fmt]['exact_ms_sum_10_angles']:.3f} ms "
             f"(x{res[fmt]['speedup_vs_f32']} vs f32)")
+    return res
+
+
+def paced_leg(h, out, stream, np):
+    """Frame-time-paced preview (PI controller on D_I, D_R = 2 fixed): the
+    plant (frame time against D_I at three viewpoints), then a session of 80
+    frames at 5 deg, 120 at 40 deg and 80 at 5 deg with the target set to 85%
+    of the 40-degree frame at full resolution."""
+    import inputs
+    from paper_2206_08660_amd.pace import Pace, run_session
+    d_r = 2.0
+    fixed = lambda d: Pace(1e6, d_i_min=d, d_i_max=d, d_i_start=d)
+    plant = {}
+    for th in (5.0, 25.0, 40.0):
+        cam = inputs.orbit_camera(th)
+        plant[f"{th:g}"] = {f"{d:g}": round(float(np.median([t for _, t in run_session(
+            h, [cam] * 10, W, H, d_r, fixed(d), out=out, stream=stream)][3:])), 4) for d in (1.0, 2.0, 4.0, 8.0)}
+    target = 0.85 * plant["40"]["1"]
+    easy, hard = inputs.orbit_camera(5.0), inputs.orbit_camera(40.0)
+    with Pace(target, d_i_max=8.0) as p:
+        trace = run_session(h, [easy] * 80 + [hard] * 120 + [easy] * 80, W, H, d_r, p, out=out, stream=stream)
+    d_i = np.array([d for d, _ in trace])
+    ms = np.array([t for _, t in trace])
+    rel = np.abs(ms[100:200] / target - 1.0)
+    res = {"workload": "1080p FP32 VDI, 1920x1080 preview with D_R = 2, D_I by the PI controller (kp 0.1, ki 0.3, "
+                       "D_I in [1, 8]); 80 frames at 5 deg, 120 at 40 deg, 80 at 5 deg",
+           "plant_frame_ms_by_deg_and_D_I": plant, "target_ms": round(target, 4),
+           "easy_D_I_mean": round(float(d_i[10:80].mean()), 3), "easy_frame_ms_median": round(float(np.median(ms[10:80])), 4),
+           "hard_D_I_mean": round(float(d_i[100:200].mean()), 3),
+           "hard_frame_ms_median": round(float(np.median(ms[100:200])), 4),
+           "hard_rel_err_median": round(float(np.median(rel)), 4), "hard_within_10pct": round(float(np.mean(rel < 0.1)), 3),
+           "easy_again_D_I_mean": round(float(d_i[220:].mean()), 3)}
+    log(f"paced: target {res['target_ms']} ms; hard view D_I {res['hard_D_I_mean']} at {res['hard_frame_ms_median']} ms, "
+        f"easy view D_I {res['easy_D_I_mean']}; plant at 40 deg {plant['40']}")
     return res
 
 

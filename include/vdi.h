@@ -215,6 +215,33 @@ int vdi_replace_begin(vdi_t v, const vdi_desc *desc, void *stream);
  */
 int vdi_replace_poll(vdi_t v, int32_t *swapped);
 
+/* ------------------------------------------------------------------------
+ * Frame-time control of preview rendering (Section 4.4; the application of
+ * Section 5 holds a user-chosen frame rate with a PI controller on the image
+ * downsampling D_I while the user keeps D_R).  Host-side only.
+ *
+ * The time of a downsampled frame is close to proportional to its number of
+ * rays, (W/D_I)(H/D_I), so the controller acts on x = ln D_I with the error
+ * e = ln(frame_ms / target_ms), in velocity form:
+ *     x <- x + kp (e - e_prev) + ki e,   clamped to [ln D_I_min, ln D_I_max]
+ * (the clamp also keeps the integral action from winding up).  With the
+ * model plant ln(frame) = c - 2x, kp = 0.1 and ki = 0.3 place the error's
+ * poles at 0.56 and -0.36.
+ * ------------------------------------------------------------------------ */
+typedef struct vdi_pace_s *vdi_pace_t;
+
+/* target_ms > 0; kp, ki >= 0, finite; 1 <= D_I_min <= D_I_start <= D_I_max.
+ * Errors: VDI_ERR_ARG, VDI_ERR_OOM. */
+int vdi_pace_create(float target_ms, float kp, float ki, float D_I_min, float D_I_max, float D_I_start,
+                    vdi_pace_t *out);
+
+/* Feed the time of the frame just rendered (> 0, finite) and get the D_I for
+ * the next one. */
+int vdi_pace_update(vdi_pace_t p, float frame_ms, float *next_D_I);
+
+/* NULL is a no-op. */
+int vdi_pace_destroy(vdi_pace_t p);
+
 /* Image size used for downsampling factor D_I (round half up, at least 1). */
 int vdi_lowres_size(int32_t width, int32_t height, float D_I, int32_t *w, int32_t *h);
 

@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -152,6 +153,39 @@ int check_args(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, float D_I, 
     return VDI_OK;
 }
 
+// Stream-ordered memory pool of the library on `device`, for the low-res
+// scratch of downsampled renders.  Freed blocks stay in the pool (release
+// threshold unlimited): a session whose D_I changes every frame, with a
+// synchronisation per frame, would otherwise map fresh memory for most
+// frames.  Created on first use and kept until the process ends.
+hipError_t scratch_pool(int device, hipMemPool_t *out)
+{
+    static std::mutex mu;
+    static std::vector<hipMemPool_t> pools;
+    std::lock_guard<std::mutex> lock(mu);
+    if (device < 0) return hipErrorInvalidDevice;
+    if ((int)pools.size() <= device) pools.resize(device + 1, nullptr);
+    if (!pools[device]) {
+        hipMemPoolProps props = {};
+        props.allocType = hipMemAllocationTypePinned;
+        props.handleTypes = hipMemHandleTypeNone;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = device;
+        hipMemPool_t p = nullptr;
+        hipError_t e = hipMemPoolCreate(&p, &props);
+        if (e != hipSuccess) return e;
+        uint64_t keep = UINT64_MAX;
+        e = hipMemPoolSetAttribute(p, hipMemPoolAttrReleaseThreshold, &keep);
+        if (e != hipSuccess) {
+            (void)hipMemPoolDestroy(p);
+            return e;
+        }
+        pools[device] = p;
+    }
+    *out = pools[device];
+    return hipSuccess;
+}
+
 // Renders into `out` (W x H); uses stream-ordered scratch for D_I > 1.
 int render_impl(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, float D_I, float D_R,
                 const vdi_render_opts *opts, float *out, hipStream_t s)
@@ -169,7 +203,15 @@ int render_impl(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, float D_I,
     HIP_OR_FAIL(hipSetDevice(v->device), "hipSetDevice");
     const bool down = (w != W || h != H);
     float4 *lo = nullptr;
-    if (down) HIP_OR_FAIL(hipMallocAsync((void **)&lo, (size_t)w * h * sizeof(float4), s), "preview scratch");
+    if (down) {
+        hipMemPool_t pool = nullptr;
+        HIP_OR_FAIL(scratch_pool(v->device, &pool), "scratch pool");
+        // Sizes rounded up to a power of two (at least 1 MiB): a D_I that
+        // changes every frame then reuses a few pooled blocks.
+        size_t bytes = (size_t)1 << 20;
+        while (bytes < (size_t)w * h * sizeof(float4)) bytes <<= 1;
+        HIP_OR_FAIL(hipMallocFromPoolAsync((void **)&lo, bytes, pool, s), "preview scratch");
+    }
     f.out = down ? lo : reinterpret_cast<float4 *>(out);
     f.DR = D_R;
     hipError_t e = D_R > 0.0f ? vdi::launch_render_preview(S.dev, f, s) : vdi::launch_render_exact(S.dev, f, false, s);
@@ -413,6 +455,55 @@ uint64_t vdi_plane_bytes(int32_t width, int32_t height, int32_t n_s, int32_t fmt
     const uint64_t plane = (uint64_t)width * height;
     const uint64_t colour = fmt == VDI_F32 ? 16 : 8;
     return plane + vdi::plane_elems(plane, n_s) * (8 + colour);
+}
+
+struct vdi_pace_s {
+    double target, kp, ki, xmin, xmax, x, e_prev;
+    bool first;
+};
+
+int vdi_pace_create(float target_ms, float kp, float ki, float D_I_min, float D_I_max, float D_I_start,
+                    vdi_pace_t *out)
+{
+    g_err.clear();
+    if (!out) return fail(VDI_ERR_ARG, "null output");
+    if (!isfinite(target_ms) || !(target_ms > 0.0f)) return fail(VDI_ERR_ARG, "target_ms must be > 0");
+    if (!isfinite(kp) || !isfinite(ki) || kp < 0.0f || ki < 0.0f) return fail(VDI_ERR_ARG, "gains must be >= 0");
+    if (!isfinite(D_I_min) || !isfinite(D_I_max) || !isfinite(D_I_start) || !(D_I_min >= 1.0f) ||
+        !(D_I_min <= D_I_start) || !(D_I_start <= D_I_max))
+        return fail(VDI_ERR_ARG, "need 1 <= D_I_min <= D_I_start <= D_I_max");
+    vdi_pace_s *p = new (std::nothrow) vdi_pace_s();
+    if (!p) return fail(VDI_ERR_OOM, "host allocation");
+    p->target = target_ms;
+    p->kp = kp;
+    p->ki = ki;
+    p->xmin = log((double)D_I_min);
+    p->xmax = log((double)D_I_max);
+    p->x = log((double)D_I_start);
+    p->e_prev = 0.0;
+    p->first = true;
+    *out = p;
+    return VDI_OK;
+}
+
+int vdi_pace_update(vdi_pace_t p, float frame_ms, float *next_D_I)
+{
+    g_err.clear();
+    if (!p || !next_D_I) return fail(VDI_ERR_ARG, "null argument");
+    if (!isfinite(frame_ms) || !(frame_ms > 0.0f)) return fail(VDI_ERR_ARG, "frame_ms must be > 0");
+    const double e = log((double)frame_ms / p->target);
+    const double de = p->first ? 0.0 : e - p->e_prev;
+    p->x = std::min(p->xmax, std::max(p->xmin, p->x + p->kp * de + p->ki * e));
+    p->e_prev = e;
+    p->first = false;
+    *next_D_I = (float)exp(p->x);
+    return VDI_OK;
+}
+
+int vdi_pace_destroy(vdi_pace_t p)
+{
+    delete p;
+    return VDI_OK;
 }
 
 int vdi_lowres_size(int32_t width, int32_t height, float D_I, int32_t *w, int32_t *h)

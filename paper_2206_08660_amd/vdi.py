@@ -29,7 +29,8 @@ SEARCH = {"seeded": 0, "binary": 1, "linear": 2, "window": 3}
 EXPORTS = ("vdi_create", "vdi_render", "vdi_render_ex", "vdi_render_counters", "vdi_get_grid", "vdi_get_info",
            "vdi_destroy", "vdi_lowres_size", "vdi_plane_bytes", "vdi_last_error", "vdi_server_create",
            "vdi_server_submit", "vdi_server_poll", "vdi_server_drain", "vdi_server_get_stats",
-           "vdi_server_reset_stats", "vdi_server_destroy", "vdi_replace_begin", "vdi_replace_poll")
+           "vdi_server_reset_stats", "vdi_server_destroy", "vdi_replace_begin", "vdi_replace_poll",
+           "vdi_pace_create", "vdi_pace_update", "vdi_pace_destroy")
 
 
 class VdiError(RuntimeError):
@@ -91,6 +92,9 @@ def lib() -> ctypes.CDLL:
         L.vdi_destroy.argtypes = [P]
         L.vdi_replace_begin.argtypes = [P, ctypes.POINTER(Desc), P]
         L.vdi_replace_poll.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
+        L.vdi_pace_create.argtypes = [F, F, F, F, F, F, ctypes.POINTER(P)]
+        L.vdi_pace_update.argtypes = [P, F, ctypes.POINTER(F)]
+        L.vdi_pace_destroy.argtypes = [P]
         L.vdi_lowres_size.argtypes = [I32, I32, F, ctypes.POINTER(I32), ctypes.POINTER(I32)]
         L.vdi_plane_bytes.argtypes = [I32, I32, I32, I32]
         L.vdi_plane_bytes.restype = ctypes.c_uint64
