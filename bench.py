@@ -49,6 +49,7 @@ def parse():
     p.add_argument("--skip-precision", action="store_true")
     p.add_argument("--skip-replace", action="store_true")
     p.add_argument("--skip-paced", action="store_true")
+    p.add_argument("--skip-generation", action="store_true")
     p.add_argument("--profile-pass", action="store_true",
                    help="short run for rocprofv3: one 1 GiB copy (counter calibration) and one exact render per angle")
     return p.parse_args()
@@ -244,6 +245,8 @@ def main():
         result["paced"] = paced_leg(h, out, stream, np)
     if not args.skip_replace:
         result["replacement"] = replace_leg(h, cams[20.0], out, stream, torch, V)
+    if not args.skip_generation:
+        result["generation"] = generation_leg(src, torch, V)
     h.close()
     if not args.skip_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline_leg(src, cams, per, result.get("precision"), np, torch, V)
@@ -360,6 +363,56 @@ def replace_leg(h, cam, out, stream, torch, V):
            "frame_ms_after_swap": round(float(np.median(after)), 4)}
     log(f"replacement: swapped after {swap_ms:.0f} ms; {len(during)} frames meanwhile at "
         f"{res['frame_ms_during_upload']} ms (idle {res['frame_ms_idle']} ms)")
+    return res
+
+
+def generation_leg(src, torch, V):
+    """GPU VDI generation (Section 3 with Alg. S1; the paper's Table 2 layout):
+    mean time per VDI over 12 generating views 30 degrees apart, N_S = 15 / 20
+    / 30, for the 720p and 1080p workloads' volumes, plus the N_S = 50 VDI the
+    renderer is timed on, checked bit for bit against the CPU generator's."""
+    import numpy as np
+
+    import inputs
+    res = {}
+    for name in ("720p", "1080p"):
+        spec = inputs.WORKLOADS[name]
+        vol = inputs.make_volume(spec)
+        nz, ny, nx = vol.shape
+        bmin, bmax = inputs.aabb_for((nx, ny, nz))
+        dvol = torch.from_numpy(vol.view(np.int16) if vol.dtype == np.uint16 else vol).cuda()
+        del vol
+        tf = {inputs.TF_RAMP: "ramp", inputs.TF_KNOTS4: "knots4"}[spec["tf"]]
+        W0, H0 = spec["width"], spec["height"]
+        row = {}
+        for ns in (15, 20, 30):
+            bufs = (torch.empty((H0, W0), dtype=torch.uint8, device="cuda"),
+                    torch.empty((ns, H0, W0, 2), dtype=torch.float32, device="cuda"),
+                    torch.empty((ns, H0, W0, 4), dtype=torch.float32, device="cuda"), None)
+            V.generate(dvol, bmin, bmax, inputs.orbit_camera(0.0), W0, H0, ns, tf=tf, out=bufs)
+            ms, segs = [], 0
+            for k in range(12):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                V.generate(dvol, bmin, bmax, inputs.orbit_camera(30.0 * k), W0, H0, ns, tf=tf, out=bufs)
+                e1.record()
+                torch.cuda.synchronize()
+                ms.append(e0.elapsed_time(e1))
+                segs += int(bufs[0].sum())
+            row[f"N_S={ns}"] = {"mean_ms": round(float(np.mean(ms)), 2), "max_ms": round(float(np.max(ms)), 2),
+                                "supersegments_mean": segs // 12}
+            del bufs
+        if name == "1080p":
+            count, depth, rgba, _ = V.generate(dvol, bmin, bmax, src.camera, W0, H0, src.ns, tf=tf, gamma_out=False)
+            torch.cuda.synchronize()
+            same = (np.array_equal(count.cpu().numpy(), src.count) and np.array_equal(depth.cpu().numpy(), src.depth)
+                    and np.array_equal(rgba.cpu().numpy(), src.rgba))
+            row["N_S=50_bit_identical_to_cpu_generator"] = bool(same)
+            del count, depth, rgba
+        del dvol
+        torch.cuda.empty_cache()
+        res[f"{name} ({nx}x{ny}x{nz} {'u16' if spec['volume'] == 'slab_u16' else 'f32'}, {W0}x{H0})"] = row
+        log(f"generation {name}: " + ", ".join(f"{k} {v['mean_ms']} ms" for k, v in row.items() if isinstance(v, dict)))
     return res
 
 

@@ -252,6 +252,72 @@ uint64_t vdi_plane_bytes(int32_t width, int32_t height, int32_t n_s, int32_t rgb
 const char *vdi_last_error(void);
 
 /* ------------------------------------------------------------------------
+ * VDI generation (Section 3: the server raycasts the volume from V_O and
+ * splits each ray into supersegments with the homogeneity criterion of Eq. 1;
+ * supplement Alg. S1: per ray, a bisection on the sensitivity gamma so that
+ * the ray yields at most N_S supersegments and not many fewer).
+ * ------------------------------------------------------------------------ */
+#define VDI_VOXEL_F32 0 /* float32 voxels */
+#define VDI_VOXEL_U16 1 /* uint16 voxels, value / 65535 */
+
+#define VDI_TF_RAMP 0   /* colour (v, 0.25 + 0.5 v, 1 - v), opacity 0.2 clamp((v - 0.05)/0.95, 0, 1) */
+#define VDI_TF_KNOTS4 1 /* piecewise linear through 4 knots at v = 0, 0.25, 0.55, 1:
+                           colours (0.1,0.2,0.8) (0.1,0.7,0.9) (0.95,0.9,0.3) (0.9,0.15,0.1),
+                           opacities 0, 0, 0.04, 0.12 (v clamped to [0, 1]) */
+
+/* A scalar volume in DEVICE memory, [nz][ny][nx] with x fastest, spanning the
+ * AABB with cell-centred voxels (voxel (i,j,k) sits at the centre of the
+ * (i,j,k)-th of nx x ny x nz equal cells). 1 <= nx, ny, nz <= 16384. */
+typedef struct {
+    int32_t nx, ny, nz;
+    int32_t voxel_fmt; /* VDI_VOXEL_* */
+    const void *data;
+    double aabb_min[3], aabb_max[3];
+} vdi_volume;
+
+typedef struct {
+    vdi_camera camera_VO;       /* the generating view; one ray per pixel centre */
+    int32_t width, height;      /* V_O viewport = number of lists, 1..32768 each */
+    int32_t max_supersegments;  /* N_S, 1..255 */
+    int32_t tf;                 /* VDI_TF_* */
+    double gamma;               /* > 0: fixed sensitivity; 0: per-ray bisection (Alg. S1) */
+} vdi_gen_params;
+
+/*
+ * Generate a VDI on the device.  Per ray (all arithmetic FP64, no fused
+ * multiply-adds; the per-call constants below are computed on the host):
+ *   - clip to the AABB and to V_O's near plane (view depth >= near) -> [t0, t1];
+ *   - N = ceil((t1 - t0)/ds - 1e-9) equal samples, clamped to
+ *     [1, 2 max(nx,ny,nz) + 8], ds = longest AABB side / max(nx,ny,nz); each
+ *     sample at its midpoint, trilinear with clamp to edge, transfer function
+ *     tf, opacity a' = 1 - (1 - a)^(len/ds) for the sample length len;
+ *   - front-to-back emission-absorption until the transmittance is <= 1e-5
+ *     (early ray termination): the samples taken are the ones split;
+ *   - gamma = params->gamma, or Alg. S1: start at 1e-5 in [0, sqrt 3],
+ *     accept the first trial if it gives fewer than N_S supersegments,
+ *     otherwise bisect until the count is in [N_S - floor(0.15 N_S), N_S]
+ *     (or the interval is under 1e-6 wide, or after 25 trials: take its upper
+ *     end, or its lower end if that gives none);
+ *   - split with Eq. 1: a non-transparent sample joins the open supersegment
+ *     unless the distance between the supersegment's premultiplied colour,
+ *     with its opacity rescaled to one sample's length, and the sample's is
+ *     >= gamma; a transparent sample closes it; once N_S - 1 are closed the
+ *     last one takes every remaining non-transparent sample.
+ * Outputs (DEVICE pointers, caller-owned, the vdi_desc host layout, so that
+ * they can be copied to host arrays for vdi_create): count [height][width]
+ * uint8; depth [N_S][height][width][2] float32 (f, b) as linear V_O depth
+ * (b raised to the next float above f if they round equal); rgba
+ * [N_S][height][width][4] float32 straight colour and accumulated opacity;
+ * slots at index >= count are zero.  gamma_out [height][width] float64 (may be
+ * NULL): the gamma each ray used (0 for rays that miss the volume).
+ * Asynchronous on `stream` (NULL: the null stream).
+ * Errors: VDI_ERR_ARG (null pointers, sizes or formats out of range,
+ * non-finite or degenerate camera, empty AABB, gamma < 0), VDI_ERR_HIP.
+ */
+int vdi_generate(const vdi_volume *volume, const vdi_gen_params *params, uint8_t *count, float *depth, float *rgba,
+                 double *gamma_out, void *stream);
+
+/* ------------------------------------------------------------------------
  * Serving (continuous batching; a build addition, the paper's client renders
  * one request at a time, Section 5).  A server renders requests for any
  * number of resident VDIs.  Requests are admitted while request slots and the

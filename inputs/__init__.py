@@ -275,13 +275,13 @@ def load_workload(name: str, base_deg: float = 0.0, verbose: bool = False, keep_
     t = time.time()
     vol = make_volume(spec)
     if verbose:
-        print(f"[inputs] {name}: volume {vol.shape} {vol.dtype} in {time.time() - t:.1f}s", flush=True)
+        print(f"[inputs] {name}: volume {vol.shape} {vol.dtype} in {time.time() - t:.1f}s", file=sys.stderr, flush=True)
     t = time.time()
     vdi = generate_vdi(vol, cam, spec["width"], spec["height"], spec["ns"], spec["tf"], spec["gamma"], name=name)
     del vol
     if verbose:
         print(f"[inputs] {name}: VDI {spec['width']}x{spec['height']}x{spec['ns']} in {time.time() - t:.1f}s, "
-              f"{int(vdi.count.sum())} supersegments", flush=True)
+              f"{int(vdi.count.sum())} supersegments", file=sys.stderr, flush=True)
     tmp = d + ".tmp%d" % os.getpid()
     os.makedirs(tmp, exist_ok=True)
     for f in files:

@@ -11,7 +11,7 @@ REPO = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(REPO, "include")
 LIB = os.path.join(PKG, "libvdi.so")
-SOURCES = ["vdi_api.hip", "vdi_kernels.hip", "vdi_serve.hip"]
+SOURCES = ["vdi_api.hip", "vdi_kernels.hip", "vdi_serve.hip", "vdi_generate.hip"]
 ARCH = os.environ.get("VDI_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

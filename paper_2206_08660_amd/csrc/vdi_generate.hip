@@ -1,0 +1,391 @@
+// VDI generation on the GPU (paper Section 3: supersegments by Eq. 1 along
+// each generating ray of V_O; supplement Alg. S1: per-ray bisection of the
+// sensitivity gamma so that a ray yields at most N_S supersegments).
+//
+// One thread per generating ray, FP64 throughout, every expression in the
+// order written and without contraction into fused multiply-adds, so that the
+// comparisons deciding supersegment boundaries come out as the same arithmetic
+// does on a CPU.  A thread cannot keep a ray's samples, so each pass over the
+// ray (direct volume rendering to find where early termination ends it, each
+// counting pass of the bisection, the final capped split) samples the volume
+// again: trilinear interpolation of cell-centred voxels, transfer function,
+// opacity corrected to the sample length.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "vdi_internal.h"
+
+namespace vdi {
+namespace {
+
+constexpr double kGenTTerm = 1e-5;  // early ray termination of the generating rays
+
+struct GenCam {
+    double eye[3], F[3], R[3], U[3], tanh_, aspect, near_;
+    int W, H;
+};
+
+struct GenVol {
+    int nx, ny, nz, is_u16;
+    const void *data;
+    double bmin[3], bmax[3];
+};
+
+struct GenParams {
+    GenCam cam;
+    GenVol vol;
+    int NS, tf, maxs, delta;
+    double ds, gamma;  // gamma > 0: fixed
+};
+
+struct Sample {
+    double c[3], a;  // straight colour, opacity corrected to the sample length
+};
+
+struct Seg {
+    double ts, te, C[3], A;  // t-range, premultiplied colour, opacity
+};
+
+__host__ __device__ inline double clamp01(double v)
+{
+#pragma clang fp contract(off)
+    return v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
+}
+
+__host__ __device__ inline double voxel(const GenVol &v, int i, int j, int k)
+{
+#pragma clang fp contract(off)
+    const size_t o = ((size_t)k * v.ny + j) * v.nx + i;
+    return v.is_u16 ? (double)static_cast<const uint16_t *>(v.data)[o] * (1.0 / 65535.0)
+                    : (double)static_cast<const float *>(v.data)[o];
+}
+
+__host__ __device__ inline int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
+
+// Trilinear interpolation of cell-centred voxels, clamped to the edge.
+__host__ __device__ inline double sample_tri(const GenVol &v, const double *P)
+{
+#pragma clang fp contract(off)
+    const int n[3] = {v.nx, v.ny, v.nz};
+    double w[3];
+    int i0[3], i1[3];
+    for (int a = 0; a < 3; ++a) {
+        const double u = (P[a] - v.bmin[a]) / (v.bmax[a] - v.bmin[a]) * n[a] - 0.5;
+        const double f = floor(u);
+        w[a] = u - f;
+        i0[a] = clampi((int)f, 0, n[a] - 1);
+        i1[a] = clampi((int)f + 1, 0, n[a] - 1);
+    }
+    const double c00 = voxel(v, i0[0], i0[1], i0[2]) * (1 - w[0]) + voxel(v, i1[0], i0[1], i0[2]) * w[0];
+    const double c10 = voxel(v, i0[0], i1[1], i0[2]) * (1 - w[0]) + voxel(v, i1[0], i1[1], i0[2]) * w[0];
+    const double c01 = voxel(v, i0[0], i0[1], i1[2]) * (1 - w[0]) + voxel(v, i1[0], i0[1], i1[2]) * w[0];
+    const double c11 = voxel(v, i0[0], i1[1], i1[2]) * (1 - w[0]) + voxel(v, i1[0], i1[1], i1[2]) * w[0];
+    const double c0 = c00 * (1 - w[1]) + c10 * w[1], c1 = c01 * (1 - w[1]) + c11 * w[1];
+    return c0 * (1 - w[2]) + c1 * w[2];
+}
+
+// The two transfer functions of the synthetic workloads (VDI_TF_*).
+__host__ __device__ inline void tf_eval(int tf, double v, double *c, double &a)
+{
+#pragma clang fp contract(off)
+    if (tf == VDI_TF_RAMP) {
+        c[0] = v;
+        c[1] = 0.25 + 0.5 * v;
+        c[2] = 1.0 - v;
+        a = 0.2 * clamp01((v - 0.05) / 0.95);
+        return;
+    }
+    const double kv[4] = {0.0, 0.25, 0.55, 1.0};
+    const double ka[4] = {0.0, 0.0, 0.04, 0.12};
+    const double kc[4][3] = {{0.1, 0.2, 0.8}, {0.1, 0.7, 0.9}, {0.95, 0.9, 0.3}, {0.9, 0.15, 0.1}};
+    v = clamp01(v);
+    const int s = v < kv[1] ? 0 : (v < kv[2] ? 1 : 2);
+    const double u = (v - kv[s]) / (kv[s + 1] - kv[s]);
+    for (int m = 0; m < 3; ++m) c[m] = kc[s][m] + u * (kc[s + 1][m] - kc[s][m]);
+    a = ka[s] + u * (ka[s + 1] - ka[s]);
+}
+
+// Sample q of a ray (midpoint of [t0 + q len, t0 + (q + 1) len]).
+__host__ __device__ inline Sample take_sample(const GenParams &G, const double *d, double t0, double len, int q)
+{
+#pragma clang fp contract(off)
+    const double tm = t0 + (q + 0.5) * len;
+    double P[3];
+    for (int a = 0; a < 3; ++a) P[a] = G.cam.eye[a] + tm * d[a];
+    const double v = sample_tri(G.vol, P);
+    Sample s;
+    double atf;
+    tf_eval(G.tf, v, s.c, atf);
+    s.a = atf > 0.0 ? 1.0 - pow(1.0 - atf, len / G.ds) : 0.0;
+    return s;
+}
+
+// Split the first ns samples of a ray into supersegments with sensitivity
+// gamma (Eq. 1).  cap == 0: count only.  cap > 0: at most cap supersegments;
+// once cap - 1 are closed the last one takes every remaining non-transparent
+// sample, across gaps.  Eq. 1 compares the open supersegment's straight colour
+// times its opacity normalised to one sample length with the next sample's
+// colour times its opacity.  With WRITE, supersegment j goes to slot j of
+// list li (depths as V_O view depth f = t cos(theta), b likewise).
+template <bool WRITE>
+__host__ __device__ inline int split_ray(const GenParams &G, const double *d, double cth, double t0, double len, int ns,
+                         double gamma, int cap, size_t li, size_t plane, float2 *depth, float4 *rgba)
+{
+#pragma clang fp contract(off)
+    int nclosed = 0;
+    bool open = false;
+    Seg cur = {0.0, 0.0, {0.0, 0.0, 0.0}, 0.0};
+    auto close = [&]() {
+        if constexpr (WRITE) {
+            float f = (float)(cur.ts * cth), b = (float)(cur.te * cth);
+            if (!(b > f)) b = nextafterf(f, INFINITY);
+            const size_t o = (size_t)nclosed * plane + li;
+            depth[o] = make_float2(f, b);
+            const double A = cur.A;
+            rgba[o] = make_float4((float)(cur.C[0] / A), (float)(cur.C[1] / A), (float)(cur.C[2] / A), (float)A);
+        }
+        ++nclosed;
+        open = false;
+    };
+    for (int q = 0; q < ns; ++q) {
+        const Sample s = take_sample(G, d, t0, len, q);
+        const bool last = cap > 0 && nclosed == cap - 1;
+        if (s.a == 0.0) {
+            if (open && !last) close();
+            continue;
+        }
+        const double qs = t0 + q * len, qe = t0 + (q + 1) * len;
+        if (open && !last) {
+            const double lenS = cur.te - cur.ts;
+            const double abar = 1.0 - pow(1.0 - cur.A, len / lenS);
+            double d2 = 0.0;
+            for (int m = 0; m < 3; ++m) {
+                const double e = cur.C[m] / cur.A * abar - s.c[m] * s.a;
+                d2 += e * e;
+            }
+            if (sqrt(d2) >= gamma) close();
+        }
+        if (!open) {
+            cur.ts = qs;
+            cur.te = qe;
+            cur.A = s.a;
+            for (int m = 0; m < 3; ++m) cur.C[m] = s.a * s.c[m];
+            open = true;
+            continue;
+        }
+        for (int m = 0; m < 3; ++m) cur.C[m] += (1.0 - cur.A) * s.a * s.c[m];
+        cur.A += (1.0 - cur.A) * s.a;
+        cur.te = qe;
+    }
+    if (open) close();
+    return nclosed;
+}
+
+// The whole generation of list (px, py): ray, samples, gamma, supersegments.
+__host__ __device__ inline void gen_ray(const GenParams &G, int px, int py, uint8_t *count, float2 *depth, float4 *rgba,
+                                        double *gamma_out)
+{
+#pragma clang fp contract(off)
+    const int W = G.cam.W, H = G.cam.H;
+    const size_t li = (size_t)py * W + px, plane = (size_t)W * H;
+    // Generating ray through the pixel centre, clipped to the AABB and V_O's near plane.
+    const double xc = -1.0 + (2.0 * px + 1.0) / W, yc = -1.0 + (2.0 * py + 1.0) / H;
+    double d[3];
+    for (int a = 0; a < 3; ++a)
+        d[a] = G.cam.F[a] + xc * G.cam.tanh_ * G.cam.aspect * G.cam.R[a] + yc * G.cam.tanh_ * G.cam.U[a];
+    const double nrm = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    for (int a = 0; a < 3; ++a) d[a] /= nrm;
+    const double cth = G.cam.F[0] * d[0] + G.cam.F[1] * d[1] + G.cam.F[2] * d[2];
+    double lo = G.cam.near_ / cth, hi = INFINITY;
+    bool hit = true;
+    for (int a = 0; a < 3 && hit; ++a) {
+        if (fabs(d[a]) < 1e-300) {
+            if (G.cam.eye[a] < G.vol.bmin[a] || G.cam.eye[a] > G.vol.bmax[a]) hit = false;
+            continue;
+        }
+        double ta = (G.vol.bmin[a] - G.cam.eye[a]) / d[a], tb = (G.vol.bmax[a] - G.cam.eye[a]) / d[a];
+        if (ta > tb) {
+            const double t = ta;
+            ta = tb;
+            tb = t;
+        }
+        if (ta > lo) lo = ta;
+        if (tb < hi) hi = tb;
+    }
+    int n = 0;
+    double gamma = 0.0;
+    if (hit && hi > lo) {
+        const double t0 = lo, t1 = hi;
+        int N = (int)ceil((t1 - t0) / G.ds - 1e-9);
+        if (N < 1) N = 1;
+        if (N > G.maxs) N = G.maxs;
+        const double len = (t1 - t0) / N;
+        // Direct volume rendering front to back: where early termination ends the ray.
+        double T = 1.0;
+        int ns = 0;
+        for (int q = 0; q < N; ++q) {
+            const Sample s = take_sample(G, d, t0, len, q);
+            ++ns;
+            T *= 1.0 - s.a;
+            if (T <= kGenTTerm) break;
+        }
+        if (G.gamma > 0.0) {
+            gamma = G.gamma;
+        } else {
+            // Supplement Alg. S1: bisection on gamma until the ray yields between
+            // N_S - delta and N_S supersegments (the first trial, gamma = 1e-5,
+            // is accepted whenever it already yields fewer than N_S).
+            double lo_g = 0.0, hi_g = sqrt(3.0);
+            gamma = 1e-5;
+            bool first = true;
+            for (int it = 0;; ++it) {
+                const int c = split_ray<false>(G, d, cth, t0, len, ns, gamma, 0, li, plane, nullptr, nullptr);
+                bool found = false;
+                if (fabs(hi_g - lo_g) < 1e-6) {
+                    found = true;
+                    gamma = (c == 0) ? lo_g : hi_g;
+                } else if (c > G.NS) {
+                    lo_g = gamma;
+                } else if (c < G.NS - G.delta) {
+                    hi_g = gamma;
+                } else {
+                    found = true;
+                }
+                if (first) {
+                    first = false;
+                    if (c < G.NS) found = true;
+                }
+                if (found) break;
+                if (it + 1 >= 25) {
+                    gamma = hi_g;
+                    break;
+                }
+                gamma = 0.5 * (lo_g + hi_g);
+            }
+        }
+        n = split_ray<true>(G, d, cth, t0, len, ns, gamma, G.NS, li, plane, depth, rgba);
+    }
+    count[li] = (uint8_t)n;
+    if (gamma_out) gamma_out[li] = gamma;
+    for (int j = n; j < G.NS; ++j) {
+        depth[(size_t)j * plane + li] = make_float2(0.0f, 0.0f);
+        rgba[(size_t)j * plane + li] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+}
+
+__global__ __launch_bounds__(64) void k_generate(GenParams G, uint8_t *__restrict__ count, float2 *__restrict__ depth,
+                                                 float4 *__restrict__ rgba, double *__restrict__ gamma_out)
+{
+    const int px = blockIdx.x * 64 + threadIdx.x, py = blockIdx.y;
+    if (px >= G.cam.W || py >= G.cam.H) return;
+    gen_ray(G, px, py, count, depth, rgba, gamma_out);
+}
+
+void gnorm(double *v)
+{
+    const double n = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    v[0] /= n;
+    v[1] /= n;
+    v[2] /= n;
+}
+
+void gcross(const double *a, const double *b, double *o)
+{
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+}  // namespace
+}  // namespace vdi
+
+namespace vdi {
+namespace {
+
+// Check the arguments and fill the per-call constants of the kernel.
+int make_gen_params(const vdi_volume *vol, const vdi_gen_params *p, GenParams &G)
+{
+    if (!vol || !p || !vol->data) return set_error(VDI_ERR_ARG, "null argument");
+    if (vol->nx < 1 || vol->ny < 1 || vol->nz < 1 || vol->nx > 16384 || vol->ny > 16384 || vol->nz > 16384)
+        return set_error(VDI_ERR_ARG, "volume size out of range");
+    if (vol->voxel_fmt != VDI_VOXEL_F32 && vol->voxel_fmt != VDI_VOXEL_U16)
+        return set_error(VDI_ERR_ARG, "unknown voxel format");
+    for (int a = 0; a < 3; ++a)
+        if (!isfinite(vol->aabb_min[a]) || !isfinite(vol->aabb_max[a]) || !(vol->aabb_max[a] > vol->aabb_min[a]))
+            return set_error(VDI_ERR_ARG, "the AABB must be finite and non-empty");
+    if (p->width < 1 || p->height < 1 || p->width > 32768 || p->height > 32768)
+        return set_error(VDI_ERR_ARG, "VDI size out of range");
+    if (p->max_supersegments < 1 || p->max_supersegments > VDI_MAX_SUPERSEGMENTS)
+        return set_error(VDI_ERR_ARG, "max_supersegments must be in [1, 255]");
+    if (p->tf != VDI_TF_RAMP && p->tf != VDI_TF_KNOTS4) return set_error(VDI_ERR_ARG, "unknown transfer function");
+    if (!isfinite(p->gamma) || p->gamma < 0.0) return set_error(VDI_ERR_ARG, "gamma must be finite and >= 0");
+    const vdi_camera &c = p->camera_VO;
+    const float cv[11] = {c.eye[0], c.eye[1], c.eye[2], c.target[0], c.target[1], c.target[2],
+                          c.up[0],  c.up[1],  c.up[2],  c.fov_y_deg, c.near_plane};
+    for (float x : cv)
+        if (!isfinite(x)) return set_error(VDI_ERR_ARG, "camera has a non-finite value");
+    if (!(c.fov_y_deg > 0.0f && c.fov_y_deg < 180.0f) || !(c.near_plane > 0.0f))
+        return set_error(VDI_ERR_ARG, "camera fov or near plane out of range");
+
+    memset(&G, 0, sizeof G);
+    // V_O basis: F = normalize(target - eye), R = normalize(F x up), U = R x F.
+    double up[3];
+    for (int a = 0; a < 3; ++a) {
+        G.cam.eye[a] = c.eye[a];
+        G.cam.F[a] = (double)c.target[a] - (double)c.eye[a];
+        up[a] = c.up[a];
+    }
+    gnorm(G.cam.F);
+    gcross(G.cam.F, up, G.cam.R);
+    gnorm(G.cam.R);
+    gcross(G.cam.R, G.cam.F, G.cam.U);
+    for (int a = 0; a < 3; ++a)
+        if (!isfinite(G.cam.F[a]) || !isfinite(G.cam.R[a]))
+            return set_error(VDI_ERR_ARG, "degenerate camera (target equals eye, or up parallel to the view)");
+    G.cam.tanh_ = tan((double)c.fov_y_deg * M_PI / 360.0);
+    G.cam.aspect = (double)p->width / (double)p->height;
+    G.cam.near_ = c.near_plane;
+    G.cam.W = p->width;
+    G.cam.H = p->height;
+    G.vol.nx = vol->nx;
+    G.vol.ny = vol->ny;
+    G.vol.nz = vol->nz;
+    G.vol.is_u16 = vol->voxel_fmt == VDI_VOXEL_U16;
+    G.vol.data = vol->data;
+    double ext = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        G.vol.bmin[a] = vol->aabb_min[a];
+        G.vol.bmax[a] = vol->aabb_max[a];
+        ext = std::max(ext, vol->aabb_max[a] - vol->aabb_min[a]);
+    }
+    const int nmax = std::max(vol->nx, std::max(vol->ny, vol->nz));
+    G.ds = ext / nmax;  // one voxel of the longest axis
+    G.maxs = 2 * nmax + 8;
+    G.NS = p->max_supersegments;
+    G.delta = (int)floor(0.15 * G.NS);
+    G.tf = p->tf;
+    G.gamma = p->gamma;
+    return VDI_OK;
+}
+
+}  // namespace
+}  // namespace vdi
+
+extern "C" int vdi_generate(const vdi_volume *vol, const vdi_gen_params *p, uint8_t *count, float *depth, float *rgba,
+                            double *gamma_out, void *stream)
+{
+    if (!count || !depth || !rgba) return vdi::set_error(VDI_ERR_ARG, "null output");
+    vdi::GenParams G;
+    const int rc = vdi::make_gen_params(vol, p, G);
+    if (rc) return rc;
+    const dim3 grid((unsigned)((p->width + 63) / 64), (unsigned)p->height);
+    vdi::k_generate<<<grid, 64, 0, static_cast<hipStream_t>(stream)>>>(
+        G, count, reinterpret_cast<float2 *>(depth), reinterpret_cast<float4 *>(rgba), gamma_out);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return vdi::hip_error(e, "generation launch");
+    return VDI_OK;
+}

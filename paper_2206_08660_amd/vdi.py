@@ -30,7 +30,10 @@ EXPORTS = ("vdi_create", "vdi_render", "vdi_render_ex", "vdi_render_counters", "
            "vdi_destroy", "vdi_lowres_size", "vdi_plane_bytes", "vdi_last_error", "vdi_server_create",
            "vdi_server_submit", "vdi_server_poll", "vdi_server_drain", "vdi_server_get_stats",
            "vdi_server_reset_stats", "vdi_server_destroy", "vdi_replace_begin", "vdi_replace_poll",
-           "vdi_pace_create", "vdi_pace_update", "vdi_pace_destroy")
+           "vdi_pace_create", "vdi_pace_update", "vdi_pace_destroy", "vdi_generate")
+
+VOXEL = {"f32": 0, "u16": 1}
+TF = {"ramp": 0, "knots4": 1}
 
 
 class VdiError(RuntimeError):
@@ -72,6 +75,17 @@ class ServerStats(ctypes.Structure):
                 ("queued", ctypes.c_int32), ("peak_batch", ctypes.c_int32)]
 
 
+class Volume(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("voxel_fmt", ctypes.c_int32), ("data", ctypes.c_void_p),
+                ("aabb_min", ctypes.c_double * 3), ("aabb_max", ctypes.c_double * 3)]
+
+
+class GenParams(ctypes.Structure):
+    _fields_ = [("camera_VO", Camera), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("max_supersegments", ctypes.c_int32), ("tf", ctypes.c_int32), ("gamma", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -107,6 +121,7 @@ def lib() -> ctypes.CDLL:
         L.vdi_server_get_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
         L.vdi_server_reset_stats.argtypes = [P]
         L.vdi_server_destroy.argtypes = [P]
+        L.vdi_generate.argtypes = [ctypes.POINTER(Volume), ctypes.POINTER(GenParams), P, P, P, P, P]
         _lib = L
     return _lib
 
@@ -268,3 +283,45 @@ class Vdi:
             self.close()
         except Exception:
             pass
+
+
+def generate(volume, aabb_min, aabb_max, cam, width: int, height: int, ns: int, tf: str = "knots4",
+             gamma: float = 0.0, out=None, gamma_out: bool = True, stream=None):
+    """vdi_generate: a VDI from a device volume ([nz, ny, nx] float32, or
+    uint16 / int16 holding uint16 bits), as device tensors in the vdi_desc
+    layout: (count [H, W] uint8, depth [NS, H, W, 2] f32, rgba [NS, H, W, 4]
+    f32, gamma [H, W] f64 or None).  `out` may give those tensors to fill."""
+    import torch
+    if volume.dim() != 3 or not volume.is_cuda or not volume.is_contiguous():
+        raise ValueError("volume must be a contiguous 3-d device tensor [nz, ny, nx]")
+    if volume.dtype == torch.float32:
+        fmt = VOXEL["f32"]
+    elif volume.dtype in (torch.int16, getattr(torch, "uint16", torch.int16)):
+        fmt = VOXEL["u16"]
+    else:
+        raise TypeError("volume must be float32 or 16-bit")
+    nz, ny, nx = volume.shape
+    v = Volume(nx, ny, nz, fmt, ctypes.c_void_p(volume.data_ptr()))
+    v.aabb_min[:] = [float(x) for x in aabb_min]
+    v.aabb_max[:] = [float(x) for x in aabb_max]
+    p = GenParams()
+    p.camera_VO = camera(cam)
+    p.width, p.height, p.max_supersegments, p.tf, p.gamma = width, height, ns, TF[tf], float(gamma)
+    dev = volume.device
+    if out is None:
+        count = torch.empty((height, width), dtype=torch.uint8, device=dev)
+        depth = torch.empty((ns, height, width, 2), dtype=torch.float32, device=dev)
+        rgba = torch.empty((ns, height, width, 4), dtype=torch.float32, device=dev)
+        gam = torch.empty((height, width), dtype=torch.float64, device=dev) if gamma_out else None
+    else:
+        count, depth, rgba, gam = out
+        if (tuple(count.shape) != (height, width) or count.dtype != torch.uint8
+                or tuple(depth.shape) != (ns, height, width, 2) or depth.dtype != torch.float32
+                or tuple(rgba.shape) != (ns, height, width, 4) or rgba.dtype != torch.float32
+                or (gam is not None and (tuple(gam.shape) != (height, width) or gam.dtype != torch.float64))
+                or not all(t.is_contiguous() and t.is_cuda for t in (count, depth, rgba))):
+            raise ValueError("output tensors do not match the VDI shape")
+    _check(lib().vdi_generate(ctypes.byref(v), ctypes.byref(p), ctypes.c_void_p(count.data_ptr()),
+                              ctypes.c_void_p(depth.data_ptr()), ctypes.c_void_p(rgba.data_ptr()),
+                              None if gam is None else ctypes.c_void_p(gam.data_ptr()), _stream_handle(stream)))
+    return count, depth, rgba, gam

@@ -110,3 +110,54 @@ def test_replace_rejects_null_arguments_before_any_device_work():
     sw = ctypes.c_int32(7)
     assert lib.vdi_replace_poll(None, ctypes.byref(sw)) == V.VDI_ERR_ARG
     assert lib.vdi_replace_poll(ctypes.c_void_p(1), None) == V.VDI_ERR_ARG
+
+
+def test_generate_rejects_bad_arguments_before_any_device_work():
+    lib = V.lib()
+    buf = ctypes.c_void_p(16)  # never dereferenced: every case fails its checks first
+
+    def good():
+        v = V.Volume(8, 8, 8, V.VOXEL["f32"], buf)
+        v.aabb_min[:] = [-0.5] * 3
+        v.aabb_max[:] = [0.5] * 3
+        p = V.GenParams()
+        c = V.Camera()
+        c.eye[:] = [0.0, 0.0, 1.5]
+        c.target[:] = [0.0, 0.0, 0.0]
+        c.up[:] = [0.0, 1.0, 0.0]
+        c.fov_y_deg, c.near_plane = 50.0, 0.1
+        p.camera_VO = c
+        p.width, p.height, p.max_supersegments, p.tf, p.gamma = 16, 16, 4, V.TF["ramp"], 0.0
+        return v, p
+
+    def call(v, p, outs=(buf, buf, buf)):
+        return lib.vdi_generate(None if v is None else ctypes.byref(v), None if p is None else ctypes.byref(p),
+                                *outs, None, None)
+
+    v, p = good()
+    assert call(None, p) == V.VDI_ERR_ARG
+    assert call(v, None) == V.VDI_ERR_ARG
+    assert call(v, p, (buf, None, buf)) == V.VDI_ERR_ARG
+    cases = [
+        ("nx", lambda v, p: setattr(v, "nx", 0), "volume size"),
+        ("fmt", lambda v, p: setattr(v, "voxel_fmt", 5), "voxel format"),
+        ("aabb", lambda v, p: v.aabb_max.__setitem__(1, -0.5), "AABB"),
+        ("nan aabb", lambda v, p: v.aabb_min.__setitem__(0, float("nan")), "AABB"),
+        ("width", lambda v, p: setattr(p, "width", 0), "VDI size"),
+        ("ns", lambda v, p: setattr(p, "max_supersegments", 256), "max_supersegments"),
+        ("tf", lambda v, p: setattr(p, "tf", 9), "transfer function"),
+        ("gamma", lambda v, p: setattr(p, "gamma", -1.0), "gamma"),
+        ("gamma nan", lambda v, p: setattr(p, "gamma", float("nan")), "gamma"),
+        ("fov", lambda v, p: setattr(p.camera_VO, "fov_y_deg", 180.0), "fov"),
+        ("eye=target", lambda v, p: p.camera_VO.eye.__setitem__(2, 0.0), "degenerate"),
+        ("up parallel", lambda v, p: p.camera_VO.up.__setitem__(1, 0.0) or p.camera_VO.up.__setitem__(2, 1.0),
+         "degenerate"),
+    ]
+    for name, mutate, msg in cases:
+        v, p = good()
+        mutate(v, p)
+        assert call(v, p) == V.VDI_ERR_ARG, name
+        assert msg in V.last_error(), (name, V.last_error())
+    v, p = good()
+    v.data = None
+    assert call(v, p) == V.VDI_ERR_ARG

@@ -1,0 +1,130 @@
+"""GPU VDI generation (vdi_generate, needs an MI355X) against the CPU FP64
+generator of `inputs` (Section 3, Eq. 1; supplement Alg. S1).
+
+Both sides run the same FP64 steps in the same order without fused
+multiply-adds, so supersegment counts, gammas, depths and colours are
+compared bit for bit, on the full-size workloads and on edge cases: ragged
+sizes, N_S = 1 (everything in one smeared supersegment), an eye inside the
+volume (near-plane clipping), an empty volume and rays that miss it.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def to_device(vol):
+    if vol.dtype == np.uint16:
+        return torch.from_numpy(vol.view(np.int16)).cuda()
+    return torch.from_numpy(vol).cuda()
+
+
+def gpu_generate(dvol, cam, W, H, ns, tf, gamma, bmin=None, bmax=None):
+    from paper_2206_08660_amd import vdi as V
+    nz, ny, nx = dvol.shape
+    if bmin is None:
+        bmin, bmax = inputs.aabb_for((nx, ny, nz))
+    count, depth, rgba, gam = V.generate(dvol, bmin, bmax, cam, W, H, ns, tf={0: "ramp", 1: "knots4"}[tf],
+                                         gamma=gamma)
+    torch.cuda.synchronize()
+    return count.cpu().numpy(), depth.cpu().numpy(), rgba.cpu().numpy(), gam.cpu().numpy()
+
+
+def check_same(tag, ref, got):
+    count, depth, rgba, gam = got
+    bad = {
+        "count": int((count != ref.count).sum()),
+        "gamma": int((gam != ref.gamma).sum()),
+        "depth": int((depth.view(np.uint32) != ref.depth.view(np.uint32)).any(axis=-1).sum()),
+        "rgba": int((rgba.view(np.uint32) != ref.rgba.view(np.uint32)).any(axis=-1).sum()),
+    }
+    say(f"[gpu] {tag}: {int(ref.count.sum())} supersegments in {ref.count.size} lists, mismatches {bad}")
+    assert all(v == 0 for v in bad.values()), (tag, bad)
+
+
+@pytest.fixture(scope="module")
+def tiny_vol():
+    return inputs.make_volume(inputs.WORKLOADS["tiny"])
+
+
+@pytest.mark.parametrize("yaw", [0.0, 37.0])
+def test_tiny_fixed_gamma(tiny_vol, yaw):
+    spec = inputs.WORKLOADS["tiny"]
+    cam = inputs.orbit_camera(yaw)
+    say(f"[gpu] generate tiny yaw {yaw}")
+    ref = inputs.generate_vdi(tiny_vol, cam, spec["width"], spec["height"], spec["ns"], spec["tf"], spec["gamma"])
+    check_same(f"tiny yaw {yaw}", ref, gpu_generate(to_device(tiny_vol), cam, spec["width"], spec["height"],
+                                                       spec["ns"], spec["tf"], spec["gamma"]))
+
+
+@pytest.mark.parametrize("W,H,ns,tf,gamma", [(100, 70, 3, inputs.TF_RAMP, 0.0), (65, 1, 1, inputs.TF_KNOTS4, 0.0),
+                                             (1, 33, 7, inputs.TF_RAMP, 0.02), (130, 96, 255, inputs.TF_RAMP, 0.0)])
+def test_ragged_and_extreme_ns(tiny_vol, W, H, ns, tf, gamma):
+    cam = inputs.orbit_camera(12.0)
+    say(f"[gpu] generate tiny {W}x{H} ns {ns} tf {tf} gamma {gamma}")
+    ref = inputs.generate_vdi(tiny_vol, cam, W, H, ns, tf, gamma)
+    check_same(f"{W}x{H} ns {ns}", ref, gpu_generate(to_device(tiny_vol), cam, W, H, ns, tf, gamma))
+
+
+def test_eye_inside_volume_and_empty_volume(tiny_vol):
+    cam = inputs.orbit_camera(20.0, radius=0.2)  # inside the AABB: the near plane clips
+    say("[gpu] generate with the eye inside the volume")
+    ref = inputs.generate_vdi(tiny_vol, cam, 96, 64, 12, inputs.TF_RAMP, 0.0)
+    check_same("eye inside", ref, gpu_generate(to_device(tiny_vol), cam, 96, 64, 12, inputs.TF_RAMP, 0.0))
+    empty = np.zeros((20, 24, 16), dtype=np.float32)
+    cam = inputs.orbit_camera(45.0)
+    say("[gpu] generate from an empty volume")
+    ref = inputs.generate_vdi(empty, cam, 80, 40, 5, inputs.TF_KNOTS4, 0.0)
+    got = gpu_generate(to_device(empty), cam, 80, 40, 5, inputs.TF_KNOTS4, 0.0)
+    check_same("empty", ref, got)
+    assert got[0].sum() == 0 and not got[1].any() and not got[2].any()
+    # Wide field of view: the outer rays miss the volume (count 0, gamma 0).
+    cam = inputs.Camera(eye=(0.0, 0.0, 1.5), target=(0.0, 0.0, 0.0), up=(0.0, 1.0, 0.0), fov_y_deg=120.0)
+    ref = inputs.generate_vdi(tiny_vol, cam, 64, 64, 8, inputs.TF_RAMP, 0.0)
+    got = gpu_generate(to_device(tiny_vol), cam, 64, 64, 8, inputs.TF_RAMP, 0.0)
+    check_same("wide fov", ref, got)
+    assert (got[3] == 0.0).any() and (got[0] == 0).any()
+
+
+def test_720p_workload_full_size():
+    spec = inputs.WORKLOADS["720p"]
+    vol = inputs.make_volume(spec)
+    dvol = to_device(vol)
+    for yaw in (0.0, 30.0):
+        cam = inputs.orbit_camera(yaw)
+        say(f"[gpu] generate 720p yaw {yaw}")
+        ref = inputs.generate_vdi(vol, cam, spec["width"], spec["height"], spec["ns"], spec["tf"], spec["gamma"])
+        check_same(f"720p yaw {yaw}", ref, gpu_generate(dvol, cam, spec["width"], spec["height"], spec["ns"],
+                                                           spec["tf"], spec["gamma"]))
+
+
+def test_1080p_workload_full_size():
+    """The 1080p workload's VDI (the renderer's benchmark input) regenerated on the GPU."""
+    spec = inputs.WORKLOADS["1080p"]
+    say("[gpu] loading the 1080p workload")
+    ref = inputs.load_workload("1080p", verbose=True)
+    vol = inputs.make_volume(spec)
+    dvol = to_device(vol)
+    del vol
+    say("[gpu] generate 1080p")
+    got = gpu_generate(dvol, ref.camera, spec["width"], spec["height"], spec["ns"], spec["tf"], spec["gamma"])
+    check_same("1080p", ref, got)
