@@ -50,6 +50,7 @@ def parse():
     p.add_argument("--skip-replace", action="store_true")
     p.add_argument("--skip-paced", action="store_true")
     p.add_argument("--skip-generation", action="store_true")
+    p.add_argument("--skip-quality", action="store_true")
     p.add_argument("--profile-pass", action="store_true",
                    help="short run for rocprofv3: one 1 GiB copy (counter calibration) and one exact render per angle")
     return p.parse_args()
@@ -245,6 +246,8 @@ def main():
         result["paced"] = paced_leg(h, out, stream, np)
     if not args.skip_replace:
         result["replacement"] = replace_leg(h, cams[20.0], out, stream, torch, V)
+    if not args.skip_quality:
+        result["quality"] = quality_leg(src, h, cams, out, stream, torch, V)
     if not args.skip_generation:
         result["generation"] = generation_leg(src, torch, V)
     h.close()
@@ -363,6 +366,99 @@ def replace_leg(h, cam, out, stream, torch, V):
            "frame_ms_after_swap": round(float(np.median(after)), 4)}
     log(f"replacement: swapped after {swap_ms:.0f} ms; {len(during)} frames meanwhile at "
         f"{res['frame_ms_during_upload']} ms (idle {res['frame_ms_idle']} ms)")
+    return res
+
+
+def _event_ms(fn, stream, torch, reps=5, warm=2):
+    """Mean GPU time of fn() over reps launches, HIP events on the launch stream."""
+    import numpy as np
+    for _ in range(warm):
+        fn()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    return float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev]))
+
+
+def quality_leg(src, h, cams, out, stream, torch, V):
+    """VDI renderings against DVR of the volume from the same viewpoint
+    (Section 6, Figs. 7-9): SSIM / PSNR against the FP64 DVR at every
+    viewpoint of the step (exact mode), the D_I x D_R grid at 30 degrees with
+    frame times (the fps / quality trade-off), and frame times of DVR (FP64
+    reference and FP32 shading) against exact VDI rendering with and without
+    empty-space skipping, for the 1080p and the 720p workloads."""
+    import numpy as np
+
+    import inputs
+    res = {}
+    spec = inputs.WORKLOADS["1080p"]
+    vol = inputs.make_volume(spec)
+    dvol = torch.from_numpy(vol).cuda()
+    del vol
+    tf = "knots4"
+    ref = torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
+    dvr_out = torch.empty_like(ref)
+    per_angle = {}
+    for th in ANGLES:
+        V.dvr(dvol, src.bmin, src.bmax, cams[th], W, H, tf=tf, precision="f64", out=ref)
+        h.render(cams[th], W, H, out=out)
+        s, p = V.image_quality(out, ref)
+        ms64 = _event_ms(lambda: V.dvr(dvol, src.bmin, src.bmax, cams[th], W, H, tf=tf, precision="f64",
+                                       out=dvr_out), stream, torch, reps=2, warm=0)
+        ms32 = _event_ms(lambda: V.dvr(dvol, src.bmin, src.bmax, cams[th], W, H, tf=tf, precision="f32",
+                                       out=dvr_out), stream, torch)
+        s32, p32 = V.image_quality(dvr_out, ref)
+        vdi_ms = _event_ms(lambda: h.render(cams[th], W, H, out=out), stream, torch)
+        vdi_noess = _event_ms(lambda: h.render(cams[th], W, H, out=out, ess=False), stream, torch)
+        per_angle[f"{th:g}"] = {"ssim": round(s, 5), "psnr_db": round(p, 2), "vdi_ms": round(vdi_ms, 4),
+                                "vdi_no_ess_ms": round(vdi_noess, 4), "dvr_f32_ms": round(ms32, 3),
+                                "dvr_f64_ms": round(ms64, 2), "dvr_f32_psnr_vs_f64_db": round(p32, 1),
+                                "speedup_vs_dvr_f32": round(ms32 / vdi_ms, 1)}
+    res["1080p_exact_vs_dvr"] = per_angle
+    log("quality 1080p exact: " + ", ".join(f"{k} deg SSIM {v['ssim']} PSNR {v['psnr_db']}" for k, v in per_angle.items()))
+    th = 30.0
+    V.dvr(dvol, src.bmin, src.bmax, cams[th], W, H, tf=tf, precision="f64", out=ref)
+    grid = {}
+    for di in (1.0, 2.0, 4.0):
+        for dr in (0.0, 0.5, 1.0, 2.0, 4.0):
+            h.render(cams[th], W, H, di, dr, out=out)
+            s, p = V.image_quality(out, ref)
+            ms = _event_ms(lambda: h.render(cams[th], W, H, di, dr, out=out), stream, torch)
+            grid[f"D_I={di:g},D_R={dr:g}"] = {"ssim": round(s, 5), "psnr_db": round(p, 2), "ms": round(ms, 4),
+                                              "fps": round(1e3 / ms, 1)}
+    res["1080p_30deg_DI_x_DR"] = grid
+    del dvol
+    torch.cuda.empty_cache()
+    # 720p workload: frame rates of exact VDI rendering (ESS on / off) against DVR.
+    spec = inputs.WORKLOADS["720p"]
+    s720 = inputs.load_workload("720p", keep_dvr=False)
+    vol = inputs.make_volume(spec)
+    dvol = torch.from_numpy(vol.view(np.int16)).cuda()
+    del vol
+    w7, h7 = spec["width"], spec["height"]
+    o7 = torch.empty((h7, w7, 4), dtype=torch.float32, device="cuda")
+    r7 = torch.empty_like(o7)
+    row = {}
+    with V.Vdi(s720) as h720:
+        for th7 in (5.0, 15.0, 30.0, 45.0):
+            cam = inputs.orbit_camera(th7)
+            V.dvr(dvol, s720.bmin, s720.bmax, cam, w7, h7, tf=tf, precision="f64", out=r7)
+            h720.render(cam, w7, h7, out=o7)
+            s, p = V.image_quality(o7, r7)
+            vdi_ms = _event_ms(lambda: h720.render(cam, w7, h7, out=o7), stream, torch)
+            noess = _event_ms(lambda: h720.render(cam, w7, h7, out=o7, ess=False), stream, torch)
+            d32 = _event_ms(lambda: V.dvr(dvol, s720.bmin, s720.bmax, cam, w7, h7, tf=tf, precision="f32", out=r7),
+                            stream, torch)
+            row[f"{th7:g}"] = {"ssim": round(s, 5), "psnr_db": round(p, 2), "vdi_ms": round(vdi_ms, 4),
+                               "vdi_no_ess_ms": round(noess, 4), "dvr_f32_ms": round(d32, 3),
+                               "speedup_vs_dvr_f32": round(d32 / vdi_ms, 1)}
+    res["720p_exact_vs_dvr"] = row
+    del dvol
+    torch.cuda.empty_cache()
+    log("quality 720p: " + ", ".join(f"{k} deg x{v['speedup_vs_dvr_f32']} vs DVR, SSIM {v['ssim']}" for k, v in row.items()))
     return res
 
 

@@ -318,6 +318,47 @@ int vdi_generate(const vdi_volume *volume, const vdi_gen_params *params, uint8_t
                  double *gamma_out, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Direct volume rendering and image quality (Section 6: VDI renderings are
+ * compared with DVR of the volume from the same viewpoint by SSIM and PSNR,
+ * and their frame rates with DVR's).
+ * ------------------------------------------------------------------------ */
+#define VDI_DVR_F64 0 /* every step in FP64, the generator's arithmetic (the quality reference) */
+#define VDI_DVR_F32 1 /* FP64 ray set-up and sample positions; FP32 interpolation, transfer
+                         function, opacity and compositing (the frame-rate baseline) */
+
+typedef struct {
+    vdi_camera camera;     /* the view rendered (V_N) */
+    int32_t width, height; /* 1..16384 each */
+    int32_t tf;            /* VDI_TF_* */
+    int32_t precision;     /* VDI_DVR_* */
+} vdi_dvr_params;
+
+/*
+ * Raycast the volume into out_rgba (DEVICE, caller-owned, width*height*16
+ * bytes, the vdi_render layout: premultiplied RGB and opacity over
+ * transparent black, row 0 at the bottom).  One ray per pixel centre, with
+ * the clipping, samples, transfer function, opacity correction and early
+ * termination (transmittance <= 1e-5) of vdi_generate's DVR pass, composited
+ * front to back.  Asynchronous on `stream`.
+ * Errors: VDI_ERR_ARG (as vdi_generate, and an unknown precision), VDI_ERR_HIP.
+ */
+int vdi_dvr(const vdi_volume *volume, const vdi_dvr_params *params, float *out_rgba, void *stream);
+
+/*
+ * SSIM and PSNR of `image` against `reference` (DEVICE RGBA float32 images of
+ * width x height, the vdi_render layout; RGB compared, opacity ignored, data
+ * range 1).  SSIM as Wang et al. (2004): 11 x 11 Gaussian window with
+ * sigma 1.5, K1 = 0.01, K2 = 0.03, population moments, averaged over the
+ * pixels whose window lies inside the image and over R, G and B.  PSNR =
+ * 10 log10(1 / MSE) over all pixels and channels (+inf for equal images).
+ * Sums run in FP64 in a fixed order (deterministic).  Allocates stream-ordered
+ * scratch; waits for `stream` and returns the values in host memory.
+ * Errors: VDI_ERR_ARG (null, images under 11 x 11 or over 16384), VDI_ERR_HIP.
+ */
+int vdi_image_quality(const float *image, const float *reference, int32_t width, int32_t height, double *ssim,
+                      double *psnr, void *stream);
+
+/* ------------------------------------------------------------------------
  * Serving (continuous batching; a build addition, the paper's client renders
  * one request at a time, Section 5).  A server renders requests for any
  * number of resident VDIs.  Requests are admitted while request slots and the

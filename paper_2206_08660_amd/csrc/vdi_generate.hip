@@ -185,26 +185,24 @@ __host__ __device__ inline int split_ray(const GenParams &G, const double *d, do
     return nclosed;
 }
 
-// The whole generation of list (px, py): ray, samples, gamma, supersegments.
-__host__ __device__ inline void gen_ray(const GenParams &G, int px, int py, uint8_t *count, float2 *depth, float4 *rgba,
-                                        double *gamma_out)
+// Ray through the centre of pixel (px, py) of the camera, clipped to the
+// AABB and the camera's near plane: unit direction d, cos(theta) = F.d and
+// the parameter range [t0, t1] along d (false when empty).
+__host__ __device__ inline bool ray_clip(const GenParams &G, int px, int py, double *d, double &cth, double &t0,
+                                         double &t1)
 {
 #pragma clang fp contract(off)
     const int W = G.cam.W, H = G.cam.H;
-    const size_t li = (size_t)py * W + px, plane = (size_t)W * H;
-    // Generating ray through the pixel centre, clipped to the AABB and V_O's near plane.
     const double xc = -1.0 + (2.0 * px + 1.0) / W, yc = -1.0 + (2.0 * py + 1.0) / H;
-    double d[3];
     for (int a = 0; a < 3; ++a)
         d[a] = G.cam.F[a] + xc * G.cam.tanh_ * G.cam.aspect * G.cam.R[a] + yc * G.cam.tanh_ * G.cam.U[a];
     const double nrm = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     for (int a = 0; a < 3; ++a) d[a] /= nrm;
-    const double cth = G.cam.F[0] * d[0] + G.cam.F[1] * d[1] + G.cam.F[2] * d[2];
+    cth = G.cam.F[0] * d[0] + G.cam.F[1] * d[1] + G.cam.F[2] * d[2];
     double lo = G.cam.near_ / cth, hi = INFINITY;
-    bool hit = true;
-    for (int a = 0; a < 3 && hit; ++a) {
+    for (int a = 0; a < 3; ++a) {
         if (fabs(d[a]) < 1e-300) {
-            if (G.cam.eye[a] < G.vol.bmin[a] || G.cam.eye[a] > G.vol.bmax[a]) hit = false;
+            if (G.cam.eye[a] < G.vol.bmin[a] || G.cam.eye[a] > G.vol.bmax[a]) return false;
             continue;
         }
         double ta = (G.vol.bmin[a] - G.cam.eye[a]) / d[a], tb = (G.vol.bmax[a] - G.cam.eye[a]) / d[a];
@@ -216,13 +214,34 @@ __host__ __device__ inline void gen_ray(const GenParams &G, int px, int py, uint
         if (ta > lo) lo = ta;
         if (tb < hi) hi = tb;
     }
+    t0 = lo;
+    t1 = hi;
+    return hi > lo;
+}
+
+// Number of equal samples over [t0, t1]: about one per ds, at least 1.
+__host__ __device__ inline int sample_count(const GenParams &G, double t0, double t1)
+{
+#pragma clang fp contract(off)
+    int N = (int)ceil((t1 - t0) / G.ds - 1e-9);
+    if (N < 1) N = 1;
+    if (N > G.maxs) N = G.maxs;
+    return N;
+}
+
+// The whole generation of list (px, py): ray, samples, gamma, supersegments.
+__host__ __device__ inline void gen_ray(const GenParams &G, int px, int py, uint8_t *count, float2 *depth, float4 *rgba,
+                                        double *gamma_out)
+{
+#pragma clang fp contract(off)
+    const int W = G.cam.W, H = G.cam.H;
+    const size_t li = (size_t)py * W + px, plane = (size_t)W * H;
+    double d[3], cth, t0, t1;
+    const bool hit = ray_clip(G, px, py, d, cth, t0, t1);
     int n = 0;
     double gamma = 0.0;
-    if (hit && hi > lo) {
-        const double t0 = lo, t1 = hi;
-        int N = (int)ceil((t1 - t0) / G.ds - 1e-9);
-        if (N < 1) N = 1;
-        if (N > G.maxs) N = G.maxs;
+    if (hit) {
+        const int N = sample_count(G, t0, t1);
         const double len = (t1 - t0) / N;
         // Direct volume rendering front to back: where early termination ends the ray.
         double T = 1.0;
@@ -283,6 +302,187 @@ __global__ __launch_bounds__(64) void k_generate(GenParams G, uint8_t *__restric
     const int px = blockIdx.x * 64 + threadIdx.x, py = blockIdx.y;
     if (px >= G.cam.W || py >= G.cam.H) return;
     gen_ray(G, px, py, count, depth, rgba, gamma_out);
+}
+
+// ---------------------------------------------------------------------------
+// Direct volume rendering (the image a VDI approximates; Section 6 compares
+// VDI renderings against it): one lane per pixel of the camera, the samples
+// and transfer function of generation, front-to-back emission-absorption with
+// early termination at transmittance <= 1e-5.
+// ---------------------------------------------------------------------------
+
+// FP32 shading: the sample position and trilinear cell/weights come from the
+// FP64 expressions above; interpolation, transfer function, opacity and
+// compositing run in FP32.
+__device__ inline float sample_tri_f32(const GenVol &v, const double *P)
+{
+    const int n[3] = {v.nx, v.ny, v.nz};
+    float w[3];
+    int i0[3], i1[3];
+    for (int a = 0; a < 3; ++a) {
+        const double u = (P[a] - v.bmin[a]) / (v.bmax[a] - v.bmin[a]) * n[a] - 0.5;
+        const double f = floor(u);
+        w[a] = (float)(u - f);
+        i0[a] = clampi((int)f, 0, n[a] - 1);
+        i1[a] = clampi((int)f + 1, 0, n[a] - 1);
+    }
+    auto vx = [&](int i, int j, int k) { return (float)voxel(v, i, j, k); };
+    const float c00 = vx(i0[0], i0[1], i0[2]) * (1 - w[0]) + vx(i1[0], i0[1], i0[2]) * w[0];
+    const float c10 = vx(i0[0], i1[1], i0[2]) * (1 - w[0]) + vx(i1[0], i1[1], i0[2]) * w[0];
+    const float c01 = vx(i0[0], i0[1], i1[2]) * (1 - w[0]) + vx(i1[0], i0[1], i1[2]) * w[0];
+    const float c11 = vx(i0[0], i1[1], i1[2]) * (1 - w[0]) + vx(i1[0], i1[1], i1[2]) * w[0];
+    const float c0 = c00 * (1 - w[1]) + c10 * w[1], c1 = c01 * (1 - w[1]) + c11 * w[1];
+    return c0 * (1 - w[2]) + c1 * w[2];
+}
+
+__device__ inline void tf_eval_f32(int tf, float v, float *c, float &a)
+{
+    if (tf == VDI_TF_RAMP) {
+        c[0] = v;
+        c[1] = 0.25f + 0.5f * v;
+        c[2] = 1.0f - v;
+        a = 0.2f * fminf(fmaxf((v - 0.05f) / 0.95f, 0.0f), 1.0f);
+        return;
+    }
+    const float kv[4] = {0.0f, 0.25f, 0.55f, 1.0f};
+    const float ka[4] = {0.0f, 0.0f, 0.04f, 0.12f};
+    const float kc[4][3] = {{0.1f, 0.2f, 0.8f}, {0.1f, 0.7f, 0.9f}, {0.95f, 0.9f, 0.3f}, {0.9f, 0.15f, 0.1f}};
+    v = fminf(fmaxf(v, 0.0f), 1.0f);
+    const int s = v < kv[1] ? 0 : (v < kv[2] ? 1 : 2);
+    const float u = (v - kv[s]) / (kv[s + 1] - kv[s]);
+    for (int m = 0; m < 3; ++m) c[m] = kc[s][m] + u * (kc[s + 1][m] - kc[s][m]);
+    a = ka[s] + u * (ka[s + 1] - ka[s]);
+}
+
+template <bool F64>
+__global__ __launch_bounds__(64) void k_dvr(GenParams G, float4 *__restrict__ out)
+{
+#pragma clang fp contract(off)
+    const int px = blockIdx.x * 64 + threadIdx.x, py = blockIdx.y;
+    if (px >= G.cam.W || py >= G.cam.H) return;
+    double d[3], cth, t0, t1;
+    float4 o = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (ray_clip(G, px, py, d, cth, t0, t1)) {
+        const int N = sample_count(G, t0, t1);
+        const double len = (t1 - t0) / N;
+        if constexpr (F64) {
+            double T = 1.0, acc[3] = {0.0, 0.0, 0.0};
+            for (int q = 0; q < N; ++q) {
+                const Sample s = take_sample(G, d, t0, len, q);
+                for (int m = 0; m < 3; ++m) acc[m] += T * s.a * s.c[m];
+                T *= 1.0 - s.a;
+                if (T <= kGenTTerm) break;
+            }
+            o = make_float4((float)acc[0], (float)acc[1], (float)acc[2], (float)(1.0 - T));
+        } else {
+            const float r = (float)(len / G.ds);
+            float T = 1.0f, acc[3] = {0.0f, 0.0f, 0.0f};
+            for (int q = 0; q < N; ++q) {
+                const double tm = t0 + (q + 0.5) * len;
+                double P[3];
+                for (int a = 0; a < 3; ++a) P[a] = G.cam.eye[a] + tm * d[a];
+                float c[3], atf;
+                tf_eval_f32(G.tf, sample_tri_f32(G.vol, P), c, atf);
+                const float ap = atf > 0.0f ? 1.0f - powf(1.0f - atf, r) : 0.0f;
+                for (int m = 0; m < 3; ++m) acc[m] += T * ap * c[m];
+                T *= 1.0f - ap;
+                if (T <= (float)kGenTTerm) break;
+            }
+            o = make_float4(acc[0], acc[1], acc[2], 1.0f - T);
+        }
+    }
+    out[(size_t)py * G.cam.W + px] = o;
+}
+
+// ---------------------------------------------------------------------------
+// Image quality of a rendering against a reference (Section 6: SSIM and
+// PSNR of VDI renderings against DVR).  RGB of RGBA float32 images, data
+// range 1.  SSIM (Wang et al. 2004): 11 x 11 Gaussian window, sigma 1.5,
+// K1 = 0.01, K2 = 0.03, population moments, averaged over the pixels whose
+// window lies inside the image and over the three channels.  PSNR from the
+// mean squared error over all pixels and channels.
+// ---------------------------------------------------------------------------
+constexpr int kSsimR = 5;                 // window radius
+constexpr int kQualityBlock = 256;        // threads per block of the partial-sum kernel
+
+struct SsimWeights {
+    double w[2 * kSsimR + 1];             // 1-d Gaussian, normalised to sum 1
+};
+
+// Per block: the sum of the SSIM (3 channels summed) of its valid pixels and
+// the sum of squared RGB differences of all its pixels, in a fixed order.
+__global__ __launch_bounds__(kQualityBlock) void k_quality_partials(const float4 *__restrict__ a,
+                                                                    const float4 *__restrict__ b, int W, int H,
+                                                                    SsimWeights g, double2 *__restrict__ part)
+{
+    __shared__ double sh[2][kQualityBlock];
+    const size_t n = (size_t)W * H;
+    const size_t i = (size_t)blockIdx.x * kQualityBlock + threadIdx.x;
+    double ssim = 0.0, se = 0.0;
+    if (i < n) {
+        const int x = (int)(i % W), y = (int)(i / W);
+        const float4 pa = a[i], pb = b[i];
+        const double d0 = (double)pa.x - pb.x, d1 = (double)pa.y - pb.y, d2 = (double)pa.z - pb.z;
+        se = d0 * d0 + d1 * d1 + d2 * d2;
+        if (x >= kSsimR && x < W - kSsimR && y >= kSsimR && y < H - kSsimR) {
+            double mx[3] = {0, 0, 0}, my[3] = {0, 0, 0}, sxx[3] = {0, 0, 0}, syy[3] = {0, 0, 0}, sxy[3] = {0, 0, 0};
+            for (int dy = -kSsimR; dy <= kSsimR; ++dy)
+                for (int dx = -kSsimR; dx <= kSsimR; ++dx) {
+                    const double w = g.w[dy + kSsimR] * g.w[dx + kSsimR];
+                    const size_t j = (size_t)(y + dy) * W + (x + dx);
+                    const float4 qa = a[j], qb = b[j];
+                    const double va[3] = {qa.x, qa.y, qa.z}, vb[3] = {qb.x, qb.y, qb.z};
+                    for (int c = 0; c < 3; ++c) {
+                        mx[c] += w * va[c];
+                        my[c] += w * vb[c];
+                        sxx[c] += w * va[c] * va[c];
+                        syy[c] += w * vb[c] * vb[c];
+                        sxy[c] += w * va[c] * vb[c];
+                    }
+                }
+            const double C1 = 0.01 * 0.01, C2 = 0.03 * 0.03;
+            for (int c = 0; c < 3; ++c) {
+                const double vx = sxx[c] - mx[c] * mx[c], vy = syy[c] - my[c] * my[c];
+                const double cxy = sxy[c] - mx[c] * my[c];
+                ssim += ((2 * mx[c] * my[c] + C1) * (2 * cxy + C2)) /
+                        ((mx[c] * mx[c] + my[c] * my[c] + C1) * (vx + vy + C2));
+            }
+        }
+    }
+    sh[0][threadIdx.x] = ssim;
+    sh[1][threadIdx.x] = se;
+    __syncthreads();
+    for (int s = kQualityBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + s];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = make_double2(sh[0][0], sh[1][0]);
+}
+
+// One block sums the partials in a fixed order.
+__global__ __launch_bounds__(kQualityBlock) void k_quality_sum(const double2 *__restrict__ part, int nparts,
+                                                               double2 *__restrict__ total)
+{
+    __shared__ double sh[2][kQualityBlock];
+    double s0 = 0.0, s1 = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += kQualityBlock) {
+        s0 += part[k].x;
+        s1 += part[k].y;
+    }
+    sh[0][threadIdx.x] = s0;
+    sh[1][threadIdx.x] = s1;
+    __syncthreads();
+    for (int s = kQualityBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + s];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = make_double2(sh[0][0], sh[1][0]);
 }
 
 void gnorm(double *v)
@@ -387,5 +587,66 @@ extern "C" int vdi_generate(const vdi_volume *vol, const vdi_gen_params *p, uint
         G, count, reinterpret_cast<float2 *>(depth), reinterpret_cast<float4 *>(rgba), gamma_out);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return vdi::hip_error(e, "generation launch");
+    return VDI_OK;
+}
+
+extern "C" int vdi_dvr(const vdi_volume *vol, const vdi_dvr_params *p, float *out_rgba, void *stream)
+{
+    if (!p || !out_rgba) return vdi::set_error(VDI_ERR_ARG, "null argument");
+    if (p->precision != VDI_DVR_F64 && p->precision != VDI_DVR_F32)
+        return vdi::set_error(VDI_ERR_ARG, "unknown DVR precision");
+    if (p->width > 16384 || p->height > 16384) return vdi::set_error(VDI_ERR_ARG, "image size out of range");
+    vdi_gen_params gp;
+    memset(&gp, 0, sizeof gp);
+    gp.camera_VO = p->camera;
+    gp.width = p->width;
+    gp.height = p->height;
+    gp.max_supersegments = 1;
+    gp.tf = p->tf;
+    vdi::GenParams G;
+    const int rc = vdi::make_gen_params(vol, &gp, G);
+    if (rc) return rc;
+    const dim3 grid((unsigned)((p->width + 63) / 64), (unsigned)p->height);
+    auto *out = reinterpret_cast<float4 *>(out_rgba);
+    if (p->precision == VDI_DVR_F64)
+        vdi::k_dvr<true><<<grid, 64, 0, static_cast<hipStream_t>(stream)>>>(G, out);
+    else
+        vdi::k_dvr<false><<<grid, 64, 0, static_cast<hipStream_t>(stream)>>>(G, out);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return vdi::hip_error(e, "DVR launch");
+    return VDI_OK;
+}
+
+extern "C" int vdi_image_quality(const float *image, const float *reference, int32_t width, int32_t height,
+                                 double *ssim, double *psnr, void *stream)
+{
+    if (!image || !reference || !ssim || !psnr) return vdi::set_error(VDI_ERR_ARG, "null argument");
+    if (width < 2 * vdi::kSsimR + 1 || height < 2 * vdi::kSsimR + 1 || width > 16384 || height > 16384)
+        return vdi::set_error(VDI_ERR_ARG, "images must be 11x11 to 16384x16384 (the SSIM window is 11x11)");
+    vdi::SsimWeights g;
+    double sum = 0.0;
+    for (int k = -vdi::kSsimR; k <= vdi::kSsimR; ++k) sum += (g.w[k + vdi::kSsimR] = exp(-(k * k) / (2.0 * 1.5 * 1.5)));
+    for (double &w : g.w) w /= sum;
+    const size_t n = (size_t)width * height;
+    const int nparts = (int)((n + vdi::kQualityBlock - 1) / vdi::kQualityBlock);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double2 *d_part = nullptr;
+    hipError_t e = hipMallocAsync((void **)&d_part, (nparts + 1) * sizeof(double2), st);
+    if (e != hipSuccess) return vdi::hip_error(e, "quality scratch");
+    vdi::k_quality_partials<<<nparts, vdi::kQualityBlock, 0, st>>>(reinterpret_cast<const float4 *>(image),
+                                                                   reinterpret_cast<const float4 *>(reference), width,
+                                                                   height, g, d_part);
+    vdi::k_quality_sum<<<1, vdi::kQualityBlock, 0, st>>>(d_part, nparts, d_part + nparts);
+    double2 tot = make_double2(0.0, 0.0);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&tot, d_part + nparts, sizeof tot, hipMemcpyDeviceToHost, st);
+    const hipError_t e2 = hipFreeAsync(d_part, st);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return vdi::hip_error(e, "quality");
+    const double valid = (double)(width - 2 * vdi::kSsimR) * (height - 2 * vdi::kSsimR) * 3.0;
+    *ssim = tot.x / valid;
+    const double mse = tot.y / (3.0 * (double)n);
+    *psnr = mse > 0.0 ? 10.0 * log10(1.0 / mse) : INFINITY;
     return VDI_OK;
 }

@@ -30,10 +30,12 @@ EXPORTS = ("vdi_create", "vdi_render", "vdi_render_ex", "vdi_render_counters", "
            "vdi_destroy", "vdi_lowres_size", "vdi_plane_bytes", "vdi_last_error", "vdi_server_create",
            "vdi_server_submit", "vdi_server_poll", "vdi_server_drain", "vdi_server_get_stats",
            "vdi_server_reset_stats", "vdi_server_destroy", "vdi_replace_begin", "vdi_replace_poll",
-           "vdi_pace_create", "vdi_pace_update", "vdi_pace_destroy", "vdi_generate")
+           "vdi_pace_create", "vdi_pace_update", "vdi_pace_destroy", "vdi_generate", "vdi_dvr",
+           "vdi_image_quality")
 
 VOXEL = {"f32": 0, "u16": 1}
 TF = {"ramp": 0, "knots4": 1}
+DVR_PRECISION = {"f64": 0, "f32": 1}
 
 
 class VdiError(RuntimeError):
@@ -86,6 +88,11 @@ class GenParams(ctypes.Structure):
                 ("max_supersegments", ctypes.c_int32), ("tf", ctypes.c_int32), ("gamma", ctypes.c_double)]
 
 
+class DvrParams(ctypes.Structure):
+    _fields_ = [("camera", Camera), ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("tf", ctypes.c_int32),
+                ("precision", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -122,6 +129,9 @@ def lib() -> ctypes.CDLL:
         L.vdi_server_reset_stats.argtypes = [P]
         L.vdi_server_destroy.argtypes = [P]
         L.vdi_generate.argtypes = [ctypes.POINTER(Volume), ctypes.POINTER(GenParams), P, P, P, P, P]
+        L.vdi_dvr.argtypes = [ctypes.POINTER(Volume), ctypes.POINTER(DvrParams), P, P]
+        L.vdi_image_quality.argtypes = [P, P, I32, I32, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double), P]
         _lib = L
     return _lib
 
@@ -285,12 +295,7 @@ class Vdi:
             pass
 
 
-def generate(volume, aabb_min, aabb_max, cam, width: int, height: int, ns: int, tf: str = "knots4",
-             gamma: float = 0.0, out=None, gamma_out: bool = True, stream=None):
-    """vdi_generate: a VDI from a device volume ([nz, ny, nx] float32, or
-    uint16 / int16 holding uint16 bits), as device tensors in the vdi_desc
-    layout: (count [H, W] uint8, depth [NS, H, W, 2] f32, rgba [NS, H, W, 4]
-    f32, gamma [H, W] f64 or None).  `out` may give those tensors to fill."""
+def _volume(volume, aabb_min, aabb_max) -> Volume:
     import torch
     if volume.dim() != 3 or not volume.is_cuda or not volume.is_contiguous():
         raise ValueError("volume must be a contiguous 3-d device tensor [nz, ny, nx]")
@@ -304,6 +309,49 @@ def generate(volume, aabb_min, aabb_max, cam, width: int, height: int, ns: int, 
     v = Volume(nx, ny, nz, fmt, ctypes.c_void_p(volume.data_ptr()))
     v.aabb_min[:] = [float(x) for x in aabb_min]
     v.aabb_max[:] = [float(x) for x in aabb_max]
+    return v
+
+
+def dvr(volume, aabb_min, aabb_max, cam, width: int, height: int, tf: str = "knots4", precision: str = "f64",
+        out=None, stream=None):
+    """vdi_dvr: direct volume rendering of a device volume; returns the
+    [height, width, 4] float32 device image (the vdi_render layout)."""
+    import torch
+    v = _volume(volume, aabb_min, aabb_max)
+    p = DvrParams()
+    p.camera = camera(cam)
+    p.width, p.height, p.tf, p.precision = width, height, TF[tf], DVR_PRECISION[precision]
+    if out is None:
+        out = torch.empty((height, width, 4), dtype=torch.float32, device=volume.device)
+    elif tuple(out.shape) != (height, width, 4) or out.dtype != torch.float32 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 [height, width, 4] tensor")
+    _check(lib().vdi_dvr(ctypes.byref(v), ctypes.byref(p), ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return out
+
+
+def image_quality(image, reference, stream=None):
+    """vdi_image_quality: (SSIM, PSNR) of a device RGBA float32 image against a reference."""
+    import torch
+    for t in (image, reference):
+        if t.dim() != 3 or t.shape[2] != 4 or t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("images must be contiguous float32 [height, width, 4] device tensors")
+    if image.shape != reference.shape:
+        raise ValueError("images differ in shape")
+    s, p = ctypes.c_double(), ctypes.c_double()
+    _check(lib().vdi_image_quality(ctypes.c_void_p(image.data_ptr()), ctypes.c_void_p(reference.data_ptr()),
+                                   image.shape[1], image.shape[0], ctypes.byref(s), ctypes.byref(p),
+                                   _stream_handle(stream)))
+    return s.value, p.value
+
+
+def generate(volume, aabb_min, aabb_max, cam, width: int, height: int, ns: int, tf: str = "knots4",
+             gamma: float = 0.0, out=None, gamma_out: bool = True, stream=None):
+    """vdi_generate: a VDI from a device volume ([nz, ny, nx] float32, or
+    uint16 / int16 holding uint16 bits), as device tensors in the vdi_desc
+    layout: (count [H, W] uint8, depth [NS, H, W, 2] f32, rgba [NS, H, W, 4]
+    f32, gamma [H, W] f64 or None).  `out` may give those tensors to fill."""
+    import torch
+    v = _volume(volume, aabb_min, aabb_max)
     p = GenParams()
     p.camera_VO = camera(cam)
     p.width, p.height, p.max_supersegments, p.tf, p.gamma = width, height, ns, TF[tf], float(gamma)
