@@ -434,6 +434,7 @@ int check_render_args(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, floa
     return ::check_args(v, cam, W, H, D_I, D_R, out);
 }
 void lowres_size(int32_t W, int32_t H, float D_I, int32_t *w, int32_t *h) { ::lowres_dims(W, H, D_I, w, h); }
+hipError_t library_pool(int device, hipMemPool_t *out) { return ::scratch_pool(device, out); }
 int make_frame(const VdiSet &S, const vdi_camera &cam, int w, int h, double aspect, Frame &f)
 {
     return ::build_frame(S, cam, w, h, aspect, f);

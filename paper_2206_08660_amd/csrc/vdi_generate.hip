@@ -33,6 +33,7 @@ struct GenVol {
     int nx, ny, nz, is_u16;
     const void *data;
     double bmin[3], bmax[3];
+    __host__ __device__ int n(int a) const { return a == 0 ? nx : (a == 1 ? ny : nz); }
 };
 
 struct GenParams {
@@ -44,6 +45,15 @@ struct GenParams {
 
 struct Sample {
     double c[3], a;  // straight colour, opacity corrected to the sample length
+    double v;        // interpolated scalar
+};
+
+// A lane's cache of its ray's first K samples, (v, a) of sample q at
+// p[q * stride]: the passes after the first read them back instead of
+// sampling the volume again.  K = 0: no cache.
+struct SampleCache {
+    double2 *p;
+    int K, stride;
 };
 
 struct Seg {
@@ -121,7 +131,25 @@ __host__ __device__ inline Sample take_sample(const GenParams &G, const double *
     double atf;
     tf_eval(G.tf, v, s.c, atf);
     s.a = atf > 0.0 ? 1.0 - pow(1.0 - atf, len / G.ds) : 0.0;
+    s.v = v;
     return s;
+}
+
+// Sample q from the cache when it holds it (the same doubles: the colour is
+// the transfer function of the same v), else from the volume.
+__host__ __device__ inline Sample cached_sample(const GenParams &G, const SampleCache &C, const double *d, double t0,
+                                                double len, int q)
+{
+    if (q < C.K) {
+        const double2 e = C.p[(size_t)q * C.stride];
+        Sample s;
+        double atf;
+        tf_eval(G.tf, e.x, s.c, atf);
+        s.a = e.y;
+        s.v = e.x;
+        return s;
+    }
+    return take_sample(G, d, t0, len, q);
 }
 
 // Split the first ns samples of a ray into supersegments with sensitivity
@@ -132,8 +160,9 @@ __host__ __device__ inline Sample take_sample(const GenParams &G, const double *
 // colour times its opacity.  With WRITE, supersegment j goes to slot j of
 // list li (depths as V_O view depth f = t cos(theta), b likewise).
 template <bool WRITE>
-__host__ __device__ inline int split_ray(const GenParams &G, const double *d, double cth, double t0, double len, int ns,
-                         double gamma, int cap, size_t li, size_t plane, float2 *depth, float4 *rgba)
+__host__ __device__ inline int split_ray(const GenParams &G, const SampleCache &C, const double *d, double cth, double t0,
+                                         double len, int ns, double gamma, int cap, size_t li, size_t plane,
+                                         float2 *depth, float4 *rgba)
 {
 #pragma clang fp contract(off)
     int nclosed = 0;
@@ -152,7 +181,7 @@ __host__ __device__ inline int split_ray(const GenParams &G, const double *d, do
         open = false;
     };
     for (int q = 0; q < ns; ++q) {
-        const Sample s = take_sample(G, d, t0, len, q);
+        const Sample s = cached_sample(G, C, d, t0, len, q);
         const bool last = cap > 0 && nclosed == cap - 1;
         if (s.a == 0.0) {
             if (open && !last) close();
@@ -230,8 +259,8 @@ __host__ __device__ inline int sample_count(const GenParams &G, double t0, doubl
 }
 
 // The whole generation of list (px, py): ray, samples, gamma, supersegments.
-__host__ __device__ inline void gen_ray(const GenParams &G, int px, int py, uint8_t *count, float2 *depth, float4 *rgba,
-                                        double *gamma_out)
+__host__ __device__ inline void gen_ray(const GenParams &G, const SampleCache &C, int px, int py, uint8_t *count,
+                                        float2 *depth, float4 *rgba, double *gamma_out)
 {
 #pragma clang fp contract(off)
     const int W = G.cam.W, H = G.cam.H;
@@ -248,6 +277,7 @@ __host__ __device__ inline void gen_ray(const GenParams &G, int px, int py, uint
         int ns = 0;
         for (int q = 0; q < N; ++q) {
             const Sample s = take_sample(G, d, t0, len, q);
+            if (q < C.K) C.p[(size_t)q * C.stride] = make_double2(s.v, s.a);
             ++ns;
             T *= 1.0 - s.a;
             if (T <= kGenTTerm) break;
@@ -262,7 +292,7 @@ __host__ __device__ inline void gen_ray(const GenParams &G, int px, int py, uint
             gamma = 1e-5;
             bool first = true;
             for (int it = 0;; ++it) {
-                const int c = split_ray<false>(G, d, cth, t0, len, ns, gamma, 0, li, plane, nullptr, nullptr);
+                const int c = split_ray<false>(G, C, d, cth, t0, len, ns, gamma, 0, li, plane, nullptr, nullptr);
                 bool found = false;
                 if (fabs(hi_g - lo_g) < 1e-6) {
                     found = true;
@@ -286,7 +316,7 @@ __host__ __device__ inline void gen_ray(const GenParams &G, int px, int py, uint
                 gamma = 0.5 * (lo_g + hi_g);
             }
         }
-        n = split_ray<true>(G, d, cth, t0, len, ns, gamma, G.NS, li, plane, depth, rgba);
+        n = split_ray<true>(G, C, d, cth, t0, len, ns, gamma, G.NS, li, plane, depth, rgba);
     }
     count[li] = (uint8_t)n;
     if (gamma_out) gamma_out[li] = gamma;
@@ -296,12 +326,31 @@ __host__ __device__ inline void gen_ray(const GenParams &G, int px, int py, uint
     }
 }
 
-__global__ __launch_bounds__(64) void k_generate(GenParams G, uint8_t *__restrict__ count, float2 *__restrict__ depth,
-                                                 float4 *__restrict__ rgba, double *__restrict__ gamma_out)
+// Persistent wavefronts: each takes the next 64-ray row segment from
+// `counter` (zero at launch) until none is left, and keeps the samples of
+// its rays in its own cache region: [K][64 lanes] of (v, a), so that the 64
+// lanes, which step through a pass in lockstep, touch 1 KiB of consecutive
+// memory per sample.  Samples beyond K are taken from the volume again.
+constexpr size_t kGenCacheBytes = (size_t)4 << 30;  // at most this much cache in all
+#ifndef VDI_GEN_WAVES
+#define VDI_GEN_WAVES 3  // wavefronts per SIMD the kernel is compiled for
+#endif
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(VDI_GEN_WAVES))) void k_generate(GenParams G, unsigned *__restrict__ counter, int ntiles,
+                                                 double2 *__restrict__ cache, int K, uint8_t *__restrict__ count,
+                                                 float2 *__restrict__ depth, float4 *__restrict__ rgba,
+                                                 double *__restrict__ gamma_out)
 {
-    const int px = blockIdx.x * 64 + threadIdx.x, py = blockIdx.y;
-    if (px >= G.cam.W || py >= G.cam.H) return;
-    gen_ray(G, px, py, count, depth, rgba, gamma_out);
+    const int tiles_x = (G.cam.W + 63) / 64;
+    const SampleCache C = {cache + (size_t)blockIdx.x * K * 64 + threadIdx.x, K, 64};
+    for (;;) {
+        int tile = 0;
+        if (threadIdx.x == 0) tile = (int)atomicAdd(counter, 1u);
+        tile = __shfl(tile, 0);
+        if (tile >= ntiles) break;
+        const int py = tile / tiles_x, px = (tile % tiles_x) * 64 + threadIdx.x;
+        if (px < G.cam.W) gen_ray(G, C, px, py, count, depth, rgba, gamma_out);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -311,18 +360,17 @@ __global__ __launch_bounds__(64) void k_generate(GenParams G, uint8_t *__restric
 // early termination at transmittance <= 1e-5.
 // ---------------------------------------------------------------------------
 
-// FP32 shading: the sample position and trilinear cell/weights come from the
-// FP64 expressions above; interpolation, transfer function, opacity and
-// compositing run in FP32.
-__device__ inline float sample_tri_f32(const GenVol &v, const double *P)
+// FP32 shading: the voxel coordinates u (FP64, cell-centred: voxel i at
+// u = i) give the trilinear cell and weights; interpolation, transfer
+// function, opacity and compositing run in FP32.
+__device__ inline float sample_tri_f32(const GenVol &v, const double *u)
 {
     const int n[3] = {v.nx, v.ny, v.nz};
     float w[3];
     int i0[3], i1[3];
     for (int a = 0; a < 3; ++a) {
-        const double u = (P[a] - v.bmin[a]) / (v.bmax[a] - v.bmin[a]) * n[a] - 0.5;
-        const double f = floor(u);
-        w[a] = (float)(u - f);
+        const double f = floor(u[a]);
+        w[a] = (float)(u[a] - f);
         i0[a] = clampi((int)f, 0, n[a] - 1);
         i1[a] = clampi((int)f + 1, 0, n[a] - 1);
     }
@@ -375,15 +423,23 @@ __global__ __launch_bounds__(64) void k_dvr(GenParams G, float4 *__restrict__ ou
             }
             o = make_float4((float)acc[0], (float)acc[1], (float)acc[2], (float)(1.0 - T));
         } else {
+            // Opacity 1 - (1 - a)^r as 1 - 2^(r log2(1 - a)) with the hardware
+            // base-2 exponential and logarithm.
             const float r = (float)(len / G.ds);
+            // Voxel coordinate of sample q along each axis: u0 + q du (FP64).
+            double u0[3], du[3];
+            for (int a = 0; a < 3; ++a) {
+                const double sc = G.vol.n(a) / (G.vol.bmax[a] - G.vol.bmin[a]);
+                u0[a] = (G.cam.eye[a] + (t0 + 0.5 * len) * d[a] - G.vol.bmin[a]) * sc - 0.5;
+                du[a] = len * d[a] * sc;
+            }
             float T = 1.0f, acc[3] = {0.0f, 0.0f, 0.0f};
             for (int q = 0; q < N; ++q) {
-                const double tm = t0 + (q + 0.5) * len;
-                double P[3];
-                for (int a = 0; a < 3; ++a) P[a] = G.cam.eye[a] + tm * d[a];
+                double u[3];
+                for (int a = 0; a < 3; ++a) u[a] = u0[a] + q * du[a];
                 float c[3], atf;
-                tf_eval_f32(G.tf, sample_tri_f32(G.vol, P), c, atf);
-                const float ap = atf > 0.0f ? 1.0f - powf(1.0f - atf, r) : 0.0f;
+                tf_eval_f32(G.tf, sample_tri_f32(G.vol, u), c, atf);
+                const float ap = atf > 0.0f ? 1.0f - __builtin_amdgcn_exp2f(r * __builtin_amdgcn_logf(1.0f - atf)) : 0.0f;
                 for (int m = 0; m < 3; ++m) acc[m] += T * ap * c[m];
                 T *= 1.0f - ap;
                 if (T <= (float)kGenTTerm) break;
@@ -582,10 +638,37 @@ extern "C" int vdi_generate(const vdi_volume *vol, const vdi_gen_params *p, uint
     vdi::GenParams G;
     const int rc = vdi::make_gen_params(vol, p, G);
     if (rc) return rc;
-    const dim3 grid((unsigned)((p->width + 63) / 64), (unsigned)p->height);
-    vdi::k_generate<<<grid, 64, 0, static_cast<hipStream_t>(stream)>>>(
-        G, count, reinterpret_cast<float2 *>(depth), reinterpret_cast<float4 *>(rgba), gamma_out);
-    const hipError_t e = hipGetLastError();
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // Persistent grid: as many single-wavefront workgroups as fit on the device at once.
+    int device = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, vdi::k_generate, 64, 0);
+    if (e != hipSuccess) return vdi::hip_error(e, "device query");
+    const int tiles_x = (p->width + 63) / 64;
+    const long long ntiles = (long long)tiles_x * p->height;
+    const int blocks = (int)std::max<long long>(1, std::min<long long>(ntiles, (long long)std::max(1, cus * per_cu)));
+    // Each lane caches up to K samples: all of them (2 max(n) + 8) while the cache fits the budget.
+    const int K = (int)std::min<size_t>((size_t)G.maxs, vdi::kGenCacheBytes / ((size_t)blocks * 64 * sizeof(double2)));
+    const size_t cache_bytes = (size_t)blocks * K * 64 * sizeof(double2);
+    size_t bytes = (size_t)1 << 20;
+    while (bytes < 256 + cache_bytes) bytes <<= 1;
+    hipMemPool_t pool = nullptr;
+    e = vdi::library_pool(device, &pool);
+    if (e != hipSuccess) return vdi::hip_error(e, "scratch pool");
+    char *scratch = nullptr;
+    e = hipMallocFromPoolAsync((void **)&scratch, bytes, pool, st);
+    if (e != hipSuccess) return vdi::set_error(VDI_ERR_OOM, "generation scratch (%zu bytes)", bytes);
+    e = hipMemsetAsync(scratch, 0, sizeof(unsigned), st);
+    if (e == hipSuccess) {
+        vdi::k_generate<<<blocks, 64, 0, st>>>(G, reinterpret_cast<unsigned *>(scratch), (int)ntiles,
+                                               reinterpret_cast<double2 *>(scratch + 256), K, count,
+                                               reinterpret_cast<float2 *>(depth), reinterpret_cast<float4 *>(rgba),
+                                               gamma_out);
+        e = hipGetLastError();
+    }
+    const hipError_t e2 = hipFreeAsync(scratch, st);
+    if (e == hipSuccess) e = e2;
     if (e != hipSuccess) return vdi::hip_error(e, "generation launch");
     return VDI_OK;
 }

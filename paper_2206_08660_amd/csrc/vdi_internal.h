@@ -148,6 +148,9 @@ int hip_error(hipError_t e, const char *what);
 int check_render_args(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, float D_I, float D_R, const float *out);
 // Ray-grid size for downsampling factor D_I.
 void lowres_size(int32_t W, int32_t H, float D_I, int32_t *w, int32_t *h);
+// The library's stream-ordered memory pool on `device` (freed blocks are kept
+// for reuse until the process ends).
+hipError_t library_pool(int device, hipMemPool_t *out);
 // Frame constants for rays on a w x h grid of camera `cam` with aspect `aspect`.
 int make_frame(const VdiSet &s, const vdi_camera &cam, int w, int h, double aspect, Frame &f);
 // Copy of v's current set, taken under its lock.
