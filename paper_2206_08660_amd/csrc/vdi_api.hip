@@ -120,6 +120,7 @@ int build_frame(const vdi::VdiSet &S, const vdi_camera &cam, int w, int h, doubl
     f.H = h;
     f.ess = 1;
     f.search = VDI_SEARCH_WINDOW;
+    f.parts = vdi::preview_parts(w, h);
     return VDI_OK;
 }
 

@@ -24,6 +24,28 @@ constexpr int kTileW = 64;
 constexpr int kTileH = VDI_TILE_H;
 constexpr int kXcds = 8;
 
+// Preview rays are split over `parts` adjacent lanes when there are few of
+// them: a preview frame lasts about as long as its longest ray's chain of
+// dependent loads, and with fewer rays than about two wavefronts per SIMD
+// nothing else hides it.  Each lane composites a contiguous block of the
+// ray's grid cells; the partial results are combined in ray order.
+#ifndef VDI_PREVIEW_LANES
+#define VDI_PREVIEW_LANES 1000000  // lanes a preview launch should reach
+#endif
+__host__ __device__ inline int preview_parts(int w, int h)
+{
+    const long long rays = (long long)w * h;
+    int p = 1;
+    while (p < 8 && rays * p < VDI_PREVIEW_LANES) p <<= 1;
+    return p;
+}
+// Workgroups (one wavefront each) of a preview launch over a w x h ray grid.
+__host__ __device__ inline uint32_t preview_tiles(int w, int h)
+{
+    const int tw = kTileW / preview_parts(w, h);
+    return (uint32_t)(((w + tw - 1) / tw) * ((h + kTileH - 1) / kTileH));
+}
+
 // Storage order of the depth and colour planes on the device.  Lists, taken
 // in row-major order, are grouped in bricks of kBrick; a brick stores slot 0
 // of its lists, then slot 1, and so on.  Slot j of list li is element
@@ -80,6 +102,7 @@ struct Frame {
     int32_t W, H;              // rays cast
     int32_t ess, search;
     double DR;                 // > 0: along-ray subsampling
+    int32_t parts;             // preview: lanes per ray (preview_parts)
     float4 *out;               // [H][W]
     // counters (instrumented kernel only)
     uint8_t *touched_lists, *touched_slots;

@@ -60,18 +60,31 @@ __global__ __launch_bounds__(kBlock) VDI_EXACT_OCC void k_render_exact(DevVDI V,
     }
 }
 
+// One preview tile: kTileW / F.parts rays by kTileH, F.parts lanes per ray.
+// Lanes outside the image take part in the combination with an empty result.
+template <int FMT>
+__device__ __forceinline__ void preview_tile(const DevVDI &V, const Frame &F, const float *s_gz, int tile_index)
+{
+    const int parts = F.parts, tw = kTileW / parts;
+    const int tiles_x = (F.W + tw - 1) / tw, tiles_y = (F.H + kTileH - 1) / kTileH;
+    const int tile = xcd_tile(tile_index, tiles_x, tiles_y);
+    const int lane = threadIdx.x;
+    const int px = (tile % tiles_x) * tw + (lane % kTileW) / parts;
+    const int py = (tile / tiles_x) * kTileH + lane / kTileW;
+    const bool in = px < F.W && py < F.H;
+    Accum a = {0.0f, 0.0f, 0.0f, 1.0f};
+    if (in) a = trace_preview<FMT>(V, F, s_gz, px, py, lane % parts, parts);
+    a = combine_parts(a, parts, lane);
+    if (in && lane % parts == 0) F.out[(uint64_t)py * F.W + px] = to_rgba(a);
+}
+
 template <int FMT>
 __global__ __launch_bounds__(kBlock) void k_render_preview(DevVDI V, Frame F)
 {
     __shared__ float s_gz[VDI_MAX_GRID_NZ + 1];
     for (int i = threadIdx.x; i <= V.gnz; i += kBlock) s_gz[i] = V.gz[i];
     __syncthreads();
-    const int tiles_x = (F.W + kTileW - 1) / kTileW, tiles_y = (F.H + kTileH - 1) / kTileH;
-    const int tile = xcd_tile(blockIdx.x, tiles_x, tiles_y);
-    const int px = (tile % tiles_x) * kTileW + (threadIdx.x % kTileW);
-    const int py = (tile / tiles_x) * kTileH + (threadIdx.x / kTileW);
-    if (px >= F.W || py >= F.H) return;
-    F.out[(uint64_t)py * F.W + px] = trace_preview<FMT>(V, F, s_gz, px, py);
+    preview_tile<FMT>(V, F, s_gz, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -101,19 +114,17 @@ __global__ __launch_bounds__(kBlock) VDI_EXACT_OCC void k_render_batch(const Bat
     if (local >= J.ntiles) return;  // padding block: the whole workgroup leaves
     for (int i = threadIdx.x; i <= J.V.gnz; i += kBlock) s_gz[i] = J.V.gz[i];
     __syncthreads();
-    const int tiles_x = (J.F.W + kTileW - 1) / kTileW, tiles_y = (J.F.H + kTileH - 1) / kTileH;
-    const int tile = xcd_tile((int)local, tiles_x, tiles_y);
-    const int px = (tile % tiles_x) * kTileW + (threadIdx.x % kTileW);
-    const int py = (tile / tiles_x) * kTileH + (threadIdx.x / kTileW);
-    if (px >= J.F.W || py >= J.F.H) return;
-    float4 o;
     if constexpr (PREVIEW) {
-        o = trace_preview<FMT>(J.V, J.F, s_gz, px, py);
+        preview_tile<FMT>(J.V, J.F, s_gz, (int)local);
     } else {
+        const int tiles_x = (J.F.W + kTileW - 1) / kTileW, tiles_y = (J.F.H + kTileH - 1) / kTileH;
+        const int tile = xcd_tile((int)local, tiles_x, tiles_y);
+        const int px = (tile % tiles_x) * kTileW + (threadIdx.x % kTileW);
+        const int py = (tile / tiles_x) * kTileH + (threadIdx.x / kTileW);
+        if (px >= J.F.W || py >= J.F.H) return;
         Counters cnt = {0, 0};
-        o = trace_exact<FMT, VDI_SEARCH_WINDOW, true, false>(J.V, J.F, s_gz, px, py, cnt);
+        J.F.out[(uint64_t)py * J.F.W + px] = trace_exact<FMT, VDI_SEARCH_WINDOW, true, false>(J.V, J.F, s_gz, px, py, cnt);
     }
-    J.F.out[(uint64_t)py * J.F.W + px] = o;
 }
 
 __global__ __launch_bounds__(256) void k_upsample_batch(const UpsampleJob *__restrict__ jobs, int njobs)
@@ -253,7 +264,8 @@ hipError_t launch_render_exact(const DevVDI &v, const Frame &f, bool counters, h
 
 hipError_t launch_render_preview(const DevVDI &v, const Frame &f, hipStream_t s)
 {
-    const dim3 g = tile_grid(f.W, f.H);
+    if (f.parts != preview_parts(f.W, f.H)) return hipErrorInvalidValue;
+    const dim3 g(preview_tiles(f.W, f.H));
     switch (v.fmt) {
     case VDI_F16: k_render_preview<VDI_F16><<<g, kBlock, 0, s>>>(v, f); break;
     case VDI_BF16: k_render_preview<VDI_BF16><<<g, kBlock, 0, s>>>(v, f); break;

@@ -351,7 +351,7 @@ int vdi_server_submit(vdi_server_t s, vdi_t v, const vdi_camera *cam, int32_t W,
     r.job.F.ess = 1;
     r.job.F.search = VDI_SEARCH_WINDOW;
     r.job.tile0 = 0;
-    r.job.ntiles = vdi::tiles_of(w, h);
+    r.job.ntiles = D_R > 0.0f ? vdi::preview_tiles(w, h) : vdi::tiles_of(w, h);
     r.fmt = S.dev.fmt;
     r.preview = D_R > 0.0f;
     r.down = down;

@@ -722,9 +722,15 @@ VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, in
 // ---------------------------------------------------------------------------
 // Preview: adaptive along-ray subsampling (Section 4.4)
 // ---------------------------------------------------------------------------
-// One preview ray through V_N pixel (px, py) of the (low-res) grid.
+// Part `part` of `parts` of the preview ray through V_N pixel (px, py) of
+// the (low-res) grid: the samples of a contiguous block of the grid cells the
+// ray crosses, composited front to back from full transmittance.  The blocks
+// split the walk's cell sequence evenly by an estimate of its length (cells
+// between entry and exit); every part walks the same sequence, so together
+// the parts take exactly the samples of the whole ray (parts = 1).
 template <int FMT>
-VDI_HD float4 trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, int px, int py)
+VDI_HD Accum trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, int px, int py, int part = 0,
+                           int parts = 1)
 {
     Accum A = {0.0f, 0.0f, 0.0f, 1.0f};
     Ray r;
@@ -759,13 +765,23 @@ VDI_HD float4 trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, 
             else
                 tz = cz > 0 ? ((double)s_gz[cz] - F.Z0) * invZp : inf;
         };
-        locate(t);
+        int c_lo = 0, c_hi = 0x7fffffff;
+        if (parts > 1) {
+            locate(r.t1);
+            const int ex = cx, ey = cy, ez = cz;
+            locate(t);
+            const long long cells = (long long)abs(ex - cx) + abs(ey - cy) + abs(ez - cz) + 1;
+            c_lo = (int)(cells * part / parts);
+            if (part + 1 < parts) c_hi = (int)(cells * (part + 1) / parts);
+        } else {
+            locate(t);
+        }
         int p = -1;
         const int max_iter = 4 * (WO + HO) / k + 4 * V.gnz + 64;
         bool done = false;
-        for (int it = 0; it < max_iter && !done; ++it) {
+        for (int it = 0; it < max_iter && it < c_hi && !done; ++it) {
             const double tn = fmin(fmin(fmin(tx, ty), tz), r.t1);
-            if (tn > t) {
+            if (it >= c_lo && tn > t) {
                 const uint32_t G = V.grid[((uint64_t)cz * V.GH + cy) * V.GW + cx];
                 if (G != 0u) {
                     const double dz = (double)s_gz[cz + 1] - (double)s_gz[cz];
@@ -835,8 +851,28 @@ VDI_HD float4 trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, 
                 break;
         }
     }
-    return make_float4(A.r, A.g, A.b, 1.0f - A.T);
+    return A;
 }
+
+// "over" of a front and a back partial result of one ray.
+VDI_HD inline Accum over(const Accum &f, const Accum &b)
+{
+    return {fmaf(f.T, b.r, f.r), fmaf(f.T, b.g, f.g), fmaf(f.T, b.b, f.b), f.T * b.T};
+}
+
+// Combine the partial results of the `parts` lanes of each ray (adjacent
+// lanes, part = lane % parts, parts a power of two) in ray order: pairs, then
+// pairs of pairs.  Every lane of the group ends with the same result.
+__device__ inline Accum combine_parts(Accum a, int parts, int lane)
+{
+    for (int m = 1; m < parts; m <<= 1) {
+        const Accum o = {__shfl_xor(a.r, m), __shfl_xor(a.g, m), __shfl_xor(a.b, m), __shfl_xor(a.T, m)};
+        a = (lane & m) ? over(o, a) : over(a, o);
+    }
+    return a;
+}
+
+VDI_HD inline float4 to_rgba(const Accum &A) { return make_float4(A.r, A.g, A.b, 1.0f - A.T); }
 
 
 // ---------------------------------------------------------------------------

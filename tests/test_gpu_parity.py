@@ -154,6 +154,21 @@ def test_tiny_preview(tiny, tiny_h, d_i, d_r):
     assert np.abs(img - ref)[ok].max() <= TOL
 
 
+@pytest.mark.parametrize("W,H", [(200, 150), (600, 500), (800, 700), (1200, 900)])
+def test_tiny_preview_lane_splits(tiny, tiny_h, W, H):
+    """Preview ray grids of 30k, 300k, 560k and 1.08M rays: each preview ray
+    is split over 8, 4, 2 and 1 lanes (blocks of its grid cells combined in
+    ray order); sampled pixels against the oracle's serial rays."""
+    say(f"[gpu] tiny preview {W}x{H} ({W * H} rays)")
+    cam = inputs.orbit_camera(-14.0)
+    pix = sample_pixels(W, H, 20000, seed=W)
+    ref, flags = oracle.render_preview(tiny, cam, W, H, 1.5, pixels=pix)
+    img = gpu_render(tiny_h, cam, W, H, d_r=1.5).reshape(-1, 4)[pix]
+    ok = flags == 0
+    assert ok.mean() > 0.95
+    assert np.abs(img - ref)[ok].max() <= TOL
+
+
 def test_random_preview_backward():
     V = _v()
     v = synth.random_vdi(32, 24, 6, seed=9)
