@@ -326,12 +326,18 @@ __host__ __device__ inline void gen_ray(const GenParams &G, const SampleCache &C
     }
 }
 
-// Persistent wavefronts: each takes the next 64-ray row segment from
-// `counter` (zero at launch) until none is left, and keeps the samples of
-// its rays in its own cache region: [K][64 lanes] of (v, a), so that the 64
-// lanes, which step through a pass in lockstep, touch 1 KiB of consecutive
-// memory per sample.  Samples beyond K are taken from the volume again.
+// Persistent wavefronts: each takes the next tile of 64 rays from `counter`
+// (zero at launch) until none is left, and keeps the samples of its rays in
+// its own cache region: [K][64 lanes] of (v, a), so that the 64 lanes, which
+// step through a pass in lockstep, touch 1 KiB of consecutive memory per
+// sample.  Samples beyond K are taken from the volume again.
 constexpr size_t kGenCacheBytes = (size_t)4 << 30;  // at most this much cache in all
+// A wavefront generates a tile of kGenTileW x kGenTileH rays: neighbouring
+// rays in both directions see similar data, so their work differs less.
+#ifndef VDI_GEN_TILE_W
+#define VDI_GEN_TILE_W 8
+#endif
+constexpr int kGenTileW = VDI_GEN_TILE_W, kGenTileH = 64 / VDI_GEN_TILE_W;
 #ifndef VDI_GEN_WAVES
 #define VDI_GEN_WAVES 3  // wavefronts per SIMD the kernel is compiled for
 #endif
@@ -341,15 +347,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(VDI_GEN_WAVE
                                                  float2 *__restrict__ depth, float4 *__restrict__ rgba,
                                                  double *__restrict__ gamma_out)
 {
-    const int tiles_x = (G.cam.W + 63) / 64;
+    const int tiles_x = (G.cam.W + kGenTileW - 1) / kGenTileW;
     const SampleCache C = {cache + (size_t)blockIdx.x * K * 64 + threadIdx.x, K, 64};
     for (;;) {
         int tile = 0;
         if (threadIdx.x == 0) tile = (int)atomicAdd(counter, 1u);
         tile = __shfl(tile, 0);
         if (tile >= ntiles) break;
-        const int py = tile / tiles_x, px = (tile % tiles_x) * 64 + threadIdx.x;
-        if (px < G.cam.W) gen_ray(G, C, px, py, count, depth, rgba, gamma_out);
+        const int px = (tile % tiles_x) * kGenTileW + (int)threadIdx.x % kGenTileW;
+        const int py = (tile / tiles_x) * kGenTileH + (int)threadIdx.x / kGenTileW;
+        if (px < G.cam.W && py < G.cam.H) gen_ray(G, C, px, py, count, depth, rgba, gamma_out);
     }
 }
 
@@ -645,8 +652,8 @@ extern "C" int vdi_generate(const vdi_volume *vol, const vdi_gen_params *p, uint
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, vdi::k_generate, 64, 0);
     if (e != hipSuccess) return vdi::hip_error(e, "device query");
-    const int tiles_x = (p->width + 63) / 64;
-    const long long ntiles = (long long)tiles_x * p->height;
+    const long long ntiles = (long long)((p->width + vdi::kGenTileW - 1) / vdi::kGenTileW) *
+                             ((p->height + vdi::kGenTileH - 1) / vdi::kGenTileH);
     const int blocks = (int)std::max<long long>(1, std::min<long long>(ntiles, (long long)std::max(1, cus * per_cu)));
     // Each lane caches up to K samples: all of them (2 max(n) + 8) while the cache fits the budget.
     const int K = (int)std::min<size_t>((size_t)G.maxs, vdi::kGenCacheBytes / ((size_t)blocks * 64 * sizeof(double2)));
