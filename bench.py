@@ -53,6 +53,9 @@ def parse():
     p.add_argument("--skip-quality", action="store_true")
     p.add_argument("--profile-pass", action="store_true",
                    help="short run for rocprofv3: one 1 GiB copy (counter calibration) and one exact render per angle")
+    p.add_argument("--profile-generation", action="store_true",
+                   help="short run for rocprofv3: one 1 GiB copy, then two GPU generations of the 720p VDI "
+                        "(1280x720, N_S=20, generating view 0 deg), the second the one to read")
     return p.parse_args()
 
 
@@ -79,6 +82,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.profile_generation:
+        profile_generation(torch, V)
+        return
 
     t = time.time()
     src = inputs.load_workload("1080p", verbose=True)
@@ -244,10 +250,11 @@ def main():
         result["served"] = served_leg(torch, V)
     if not args.skip_paced:
         result["paced"] = paced_leg(h, out, stream, np)
-    if not args.skip_replace:
-        result["replacement"] = replace_leg(h, cams[20.0], out, stream, torch, V)
+    # The quality leg renders the resident VDI of the step; the replacement leg swaps another one in.
     if not args.skip_quality:
         result["quality"] = quality_leg(src, h, cams, out, stream, torch, V)
+    if not args.skip_replace:
+        result["replacement"] = replace_leg(h, cams[20.0], out, stream, torch, V)
     if not args.skip_generation:
         result["generation"] = generation_leg(src, torch, V)
     h.close()
@@ -460,6 +467,25 @@ def quality_leg(src, h, cams, out, stream, torch, V):
     torch.cuda.empty_cache()
     log("quality 720p: " + ", ".join(f"{k} deg x{v['speedup_vs_dvr_f32']} vs DVR, SSIM {v['ssim']}" for k, v in row.items()))
     return res
+
+
+def profile_generation(torch, V):
+    import numpy as np
+
+    import inputs
+    a = torch.empty(2 ** 28, dtype=torch.float32, device="cuda").fill_(1.0)   # 1 GiB
+    b = torch.empty_like(a)
+    b.copy_(a)
+    del a, b
+    spec = inputs.WORKLOADS["720p"]
+    vol = inputs.make_volume(spec)
+    nz, ny, nx = vol.shape
+    bmin, bmax = inputs.aabb_for((nx, ny, nz))
+    dvol = torch.from_numpy(vol.view(np.int16)).cuda()
+    for _ in range(2):
+        V.generate(dvol, bmin, bmax, inputs.orbit_camera(0.0), spec["width"], spec["height"], spec["ns"], tf="knots4")
+    torch.cuda.synchronize()
+    log("generation profile pass done")
 
 
 def generation_leg(src, torch, V):
