@@ -530,7 +530,14 @@ def generation_leg(src, torch, V):
             same = (np.array_equal(count.cpu().numpy(), src.count) and np.array_equal(depth.cpu().numpy(), src.depth)
                     and np.array_equal(rgba.cpu().numpy(), src.rgba))
             row["N_S=50_bit_identical_to_cpu_generator"] = bool(same)
-            del count, depth, rgba
+            # The generated planes straight into vdi_create (device to device, brick scatter, count grid).
+            dv = V.DeviceVDI(count, depth, rgba, src.camera, src.bmin, src.bmax, grid_z=src.grid_z)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            hd = V.Vdi(dv)
+            row["N_S=50_vdi_create_from_device_planes_ms"] = round(1e3 * (time.perf_counter() - t), 1)
+            hd.close()
+            del count, depth, rgba, dv
         del dvol
         torch.cuda.empty_cache()
         res[f"{name} ({nx}x{ny}x{nz} {'u16' if spec['volume'] == 'slab_u16' else 'f32'}, {W0}x{H0})"] = row

@@ -69,7 +69,7 @@ typedef struct {
 } vdi_camera;
 
 /*
- * Description of a VDI held in host memory (Section 2.3; Section 5 gives the
+ * Description of a VDI in host or device memory (Section 2.3; Section 5 gives the
  * paper's texture layout, re-laid out here as slot-major planes).
  *   width, height       V_O viewport resolution = number of lists (N_L = w h).
  *   max_supersegments   N_S, 1..255.
@@ -89,6 +89,10 @@ typedef struct {
  *           or NULL to use grid_nz equal slices over the AABB corners' depth range.
  *   validate  non-zero: check every list (f < b, sorted, non-overlapping,
  *           count <= N_S, opacity in [0, 1], finite values) before upload.
+ *   planes_on_device  0: count, depth and rgba are host arrays.  1: they are
+ *           device arrays in the same layout (vdi_generate's output), copied
+ *           device to device; only the count plane is read back to the host
+ *           for the checks; validate must be 0.  grid_z stays a host array.
  * Slots at index >= count of their list are ignored.
  */
 typedef struct {
@@ -102,6 +106,7 @@ typedef struct {
     int32_t grid_k, grid_nz;
     const float *grid_z;
     int32_t validate;
+    int32_t planes_on_device; /* 1: count, depth and rgba are DEVICE pointers (e.g. from vdi_generate) */
 } vdi_desc;
 
 /* Per-call options of vdi_render_ex.  Neither option changes the image. */
@@ -121,8 +126,9 @@ typedef struct {
 /*
  * Upload a VDI and build its count grid (Section 4.3: per grid cell, the
  * number of supersegments of its lists whose [f, b] overlaps the cell's depth
- * slice with positive length).  Copies every host array: the caller may free
- * them on return.  Synchronous.  Writes *out only on success.
+ * slice with positive length).  Copies every array: the caller may free them
+ * on return.  Synchronous.  Device planes must be complete (their writers
+ * finished) when it is called.  Writes *out only on success.
  * Errors: VDI_ERR_ARG (null pointers, sizes, N_S or grid shape out of range,
  * non-finite camera or AABB, formats, and with validate != 0 an invalid list),
  * VDI_ERR_OOM, VDI_ERR_HIP.
@@ -199,6 +205,9 @@ int vdi_destroy(vdi_t v);
  * stream), and the back buffers are allocated by the first call.  Renders of
  * v keep using the current VDI until vdi_replace_poll swaps the new one in.
  * Returns when the host arrays have been read: the caller may free them.
+ * With device planes the call first waits for `stream` (the planes may be
+ * written there, e.g. by vdi_generate) and the caller keeps them alive until
+ * vdi_replace_poll reports the swap.
  * Renders of v on other streams and requests of a server that use v must be
  * complete before the call (their work may still read the back buffers, which
  * held the VDI before the last swap).

@@ -278,7 +278,22 @@ void free_vdi(vdi_s *v)
 
 // Checks of a descriptor common to vdi_create and vdi_replace_begin; on
 // success fills the V_O basis and the grid slice boundaries.
-int check_desc(const vdi_desc *d, Basis &ob, std::vector<float> &gz)
+// The count plane in host memory: d->count itself, or a copy of it in
+// `copy` when the planes are in device memory (they must be complete).
+int host_counts(const vdi_desc *d, std::vector<uint8_t> &copy, const uint8_t **out)
+{
+    if (!d->planes_on_device) {
+        *out = d->count;
+        return VDI_OK;
+    }
+    copy.resize((size_t)d->width * d->height);
+    const hipError_t e = hipMemcpy(copy.data(), d->count, copy.size(), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "count plane download");
+    *out = copy.data();
+    return VDI_OK;
+}
+
+int check_desc(const vdi_desc *d, Basis &ob, std::vector<float> &gz, const uint8_t **counts, std::vector<uint8_t> &count_copy)
 {
     if (d->width < 1 || d->height < 1 || d->width > 32768 || d->height > 32768)
         return fail(VDI_ERR_ARG, "VDI size %dx%d out of range", d->width, d->height);
@@ -301,9 +316,14 @@ int check_desc(const vdi_desc *d, Basis &ob, std::vector<float> &gz)
         if (!(d->aabb_max[a] > d->aabb_min[a])) return fail(VDI_ERR_ARG, "empty AABB");
     int rc = make_basis(d->camera_VO, ob);
     if (rc) return rc;
+    if (d->planes_on_device != 0 && d->planes_on_device != 1) return fail(VDI_ERR_ARG, "planes_on_device must be 0 or 1");
+    if (d->planes_on_device && d->validate)
+        return fail(VDI_ERR_ARG, "list validation reads the planes on the host: not available for device planes");
+    rc = host_counts(d, count_copy, counts);
+    if (rc) return rc;
     const uint64_t plane = (uint64_t)d->width * d->height;
     for (uint64_t li = 0; li < plane; ++li)
-        if (d->count[li] > d->max_supersegments) return fail(VDI_ERR_ARG, "a list count exceeds max_supersegments");
+        if ((*counts)[li] > d->max_supersegments) return fail(VDI_ERR_ARG, "a list count exceeds max_supersegments");
     if (d->validate) {
         rc = validate_lists(d);
         if (rc) return rc;
@@ -347,8 +367,8 @@ uint64_t set_bytes_of(const vdi_desc *d)
 // `stage` (stage_bytes) and scatter them into storage order (colour
 // converted on the way), then build the count grid.  Enqueues only; the
 // caller synchronises.  `gz` must stay valid until the work has run.
-hipError_t upload_set(vdi::VdiSet &S, const vdi_desc *d, const Basis &ob, const std::vector<float> &gz, hipStream_t st,
-                      void *stage, uint64_t stage_bytes, const char **what)
+hipError_t upload_set(vdi::VdiSet &S, const vdi_desc *d, const uint8_t *counts, const Basis &ob,
+                      const std::vector<float> &gz, hipStream_t st, void *stage, uint64_t stage_bytes, const char **what)
 {
     const uint64_t plane = (uint64_t)d->width * d->height;
     const uint64_t ns = (uint64_t)d->max_supersegments;
@@ -390,7 +410,8 @@ hipError_t upload_set(vdi::VdiSet &S, const vdi_desc *d, const Basis &ob, const 
     D.grid = S.d_grid;
     D.gz = S.d_gz;
     *what = "upload";
-    e = hipMemcpyAsync(S.d_count, d->count, plane, hipMemcpyHostToDevice, st);
+    const hipMemcpyKind kind = d->planes_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    e = hipMemcpyAsync(S.d_count, d->count, plane, kind, st);
     if (e == hipSuccess) e = hipMemcpyAsync(S.d_gz, gz.data(), gz.size() * sizeof(float), hipMemcpyHostToDevice, st);
     const size_t colour_in = d->rgba_fmt_in == VDI_F32 ? 16 : 8;
     const uint64_t slots = std::max<uint64_t>(1, std::min<uint64_t>(ns, stage_bytes / (plane * 16)));
@@ -401,7 +422,7 @@ hipError_t upload_set(vdi::VdiSet &S, const vdi_desc *d, const Basis &ob, const 
         for (uint64_t j0 = 0; j0 < ns && e == hipSuccess; j0 += slots) {
             const uint64_t nj = std::min(slots, ns - j0);
             // Stream order keeps the staging buffer from being refilled before it is scattered.
-            e = hipMemcpyAsync(stage, src + j0 * plane * esz, nj * plane * esz, hipMemcpyHostToDevice, st);
+            e = hipMemcpyAsync(stage, src + j0 * plane * esz, nj * plane * esz, kind, st);
             if (e == hipSuccess)
                 e = vdi::launch_scatter_slots(stage, d->rgba_fmt_in, dep ? (void *)S.d_depth : S.d_rgba, d->rgba_fmt_store,
                                               dep, nj * plane, D, (int32_t)j0, st);
@@ -411,7 +432,7 @@ hipError_t upload_set(vdi::VdiSet &S, const vdi_desc *d, const Basis &ob, const 
     *what = "grid build";
     e = vdi::launch_grid_build(D, S.d_grid, st);
     uint64_t total = 0;
-    for (uint64_t li = 0; li < plane; ++li) total += d->count[li];
+    for (uint64_t li = 0; li < plane; ++li) total += counts[li];
     S.supersegments = total;
     return e;
 }
@@ -521,7 +542,9 @@ int vdi_create(const vdi_desc *d, vdi_t *out)
     if (!d || !out) return fail(VDI_ERR_ARG, "null argument");
     Basis ob;
     std::vector<float> gz;
-    int rc = check_desc(d, ob, gz);
+    std::vector<uint8_t> count_copy;
+    const uint8_t *counts = nullptr;
+    int rc = check_desc(d, ob, gz, &counts, count_copy);
     if (rc) return rc;
     vdi_s *v = new (std::nothrow) vdi_s();
     if (!v) return fail(VDI_ERR_OOM, "host allocation");
@@ -535,7 +558,7 @@ int vdi_create(const vdi_desc *d, vdi_t *out)
     void *stage = nullptr;
     const char *what = "staging";
     e = hipMalloc(&stage, stage_bytes);
-    if (e == hipSuccess) e = upload_set(v->cur, d, ob, gz, 0, stage, stage_bytes, &what);
+    if (e == hipSuccess) e = upload_set(v->cur, d, counts, ob, gz, 0, stage, stage_bytes, &what);
     if (e == hipSuccess) what = "upload", e = hipDeviceSynchronize();
     if (stage) {
         const hipError_t ef = hipFree(stage);
@@ -555,9 +578,16 @@ int vdi_replace_begin(vdi_t v, const vdi_desc *d, void *stream)
 {
     g_err.clear();
     if (!v || !d) return fail(VDI_ERR_ARG, "null argument");
+    // Device planes may still be being written on the caller's stream.
+    if (d->planes_on_device) {
+        const hipError_t es = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+        if (es != hipSuccess) return hip_fail(es, "waiting for the caller's stream");
+    }
     Basis ob;
     std::vector<float> gz;
-    int rc = check_desc(d, ob, gz);
+    std::vector<uint8_t> count_copy;
+    const uint8_t *counts = nullptr;
+    int rc = check_desc(d, ob, gz, &counts, count_copy);
     if (rc) return rc;
     {
         std::lock_guard<std::mutex> lock(v->mu);
@@ -587,7 +617,7 @@ int vdi_replace_begin(vdi_t v, const vdi_desc *d, void *stream)
     // upload waits for the work already enqueued on the caller's stream.
     if (e == hipSuccess) e = hipEventRecord(v->start, static_cast<hipStream_t>(stream));
     if (e == hipSuccess) e = hipStreamWaitEvent(v->copy, v->start, 0);
-    if (e == hipSuccess) e = upload_set(v->back, d, ob, v->gz_host, v->copy, v->stage, v->stage_bytes, &what);
+    if (e == hipSuccess) e = upload_set(v->back, d, counts, ob, v->gz_host, v->copy, v->stage, v->stage_bytes, &what);
     if (e == hipSuccess) what = "replacement", e = hipEventRecord(v->ready, v->copy);
     std::lock_guard<std::mutex> lock(v->mu);
     if (e != hipSuccess) {

@@ -55,7 +55,7 @@ class Desc(ctypes.Structure):
                 ("count", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("rgba", ctypes.c_void_p),
                 ("rgba_fmt_in", ctypes.c_int32), ("rgba_fmt_store", ctypes.c_int32),
                 ("grid_k", ctypes.c_int32), ("grid_nz", ctypes.c_int32), ("grid_z", ctypes.c_void_p),
-                ("validate", ctypes.c_int32)]
+                ("validate", ctypes.c_int32), ("planes_on_device", ctypes.c_int32)]
 
 
 class Opts(ctypes.Structure):
@@ -177,28 +177,60 @@ def _opts(ess: bool, search: str) -> Opts:
     return Opts(1 if ess else 0, SEARCH[search])
 
 
+def _on_device(a) -> bool:
+    return bool(getattr(a, "is_cuda", False))
+
+
 def _desc(src, store: str, validate: bool, rgba_in, fmt_in: str):
-    """vdi_desc for src, and the arrays it points to (kept alive by the caller)."""
-    count = np.ascontiguousarray(src.count, dtype=np.uint8)
-    depth = np.ascontiguousarray(src.depth, dtype=np.float32)
-    rgba = np.ascontiguousarray(src.rgba if rgba_in is None else rgba_in)
-    if fmt_in == "f32":
-        rgba = rgba.astype(np.float32, copy=False)
+    """vdi_desc for src, and the arrays it points to (kept alive by the caller).
+    Planes given as CUDA tensors are passed as device planes."""
+    dev = _on_device(src.count)
+    if dev:
+        import torch
+        count, depth = src.count, src.depth
+        rgba = src.rgba if rgba_in is None else rgba_in
+        ok = (_on_device(depth) and _on_device(rgba) and count.dtype == torch.uint8 and depth.dtype == torch.float32
+              and rgba.dtype == (torch.float32 if fmt_in == "f32" else rgba.dtype)
+              and all(t.is_contiguous() for t in (count, depth, rgba)))
+        if not ok:
+            raise ValueError("device planes must be contiguous CUDA tensors: count uint8, depth float32, rgba float32 "
+                             "(or 16-bit with fmt_in)")
+        ptr = lambda t: t.data_ptr()
+    else:
+        count = np.ascontiguousarray(src.count, dtype=np.uint8)
+        depth = np.ascontiguousarray(src.depth, dtype=np.float32)
+        rgba = np.ascontiguousarray(src.rgba if rgba_in is None else rgba_in)
+        if fmt_in == "f32":
+            rgba = rgba.astype(np.float32, copy=False)
+        ptr = lambda a: a.ctypes.data
     gz = None if src.grid_z is None else np.ascontiguousarray(src.grid_z, dtype=np.float32)
     d = Desc()
     d.width, d.height, d.max_supersegments = src.width, src.height, src.ns
     d.camera_VO = camera(src.camera)
     d.aabb_min[:] = [float(x) for x in src.bmin]
     d.aabb_max[:] = [float(x) for x in src.bmax]
-    d.count = count.ctypes.data
-    d.depth = depth.ctypes.data
-    d.rgba = rgba.ctypes.data
+    d.count = ptr(count)
+    d.depth = ptr(depth)
+    d.rgba = ptr(rgba)
     d.rgba_fmt_in = FORMATS[fmt_in]
     d.rgba_fmt_store = FORMATS[store]
     d.grid_k, d.grid_nz = src.grid_k, src.grid_nz
     d.grid_z = None if gz is None else gz.ctypes.data
     d.validate = 1 if validate else 0
+    d.planes_on_device = 1 if dev else 0
     return d, (count, depth, rgba, gz)
+
+
+class DeviceVDI:
+    """A VDI whose planes are CUDA tensors in the vdi_desc layout (as
+    vdi_generate writes them); Vdi() and Vdi.replace_begin() take it without a
+    copy through host memory."""
+
+    def __init__(self, count, depth, rgba, camera, bmin, bmax, grid_k: int = 8, grid_nz: int = 20, grid_z=None):
+        self.count, self.depth, self.rgba = count, depth, rgba
+        self.ns, self.height, self.width = int(depth.shape[0]), int(depth.shape[1]), int(depth.shape[2])
+        self.camera, self.bmin, self.bmax = camera, tuple(bmin), tuple(bmax)
+        self.grid_k, self.grid_nz, self.grid_z = grid_k, grid_nz, grid_z
 
 
 class Vdi:
@@ -210,6 +242,9 @@ class Vdi:
         depth, rgba, grid_k, grid_nz, grid_z (e.g. inputs.VDI)."""
         self._h = None
         d, _keep = _desc(src, store, validate, rgba_in, fmt_in)
+        if d.planes_on_device:
+            import torch
+            torch.cuda.current_stream().synchronize()   # the planes may still be written there
         h = ctypes.c_void_p()
         _check(lib().vdi_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h

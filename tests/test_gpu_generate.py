@@ -128,3 +128,41 @@ def test_1080p_workload_full_size():
     say("[gpu] generate 1080p")
     got = gpu_generate(dvol, ref.camera, spec["width"], spec["height"], spec["ns"], spec["tf"], spec["gamma"])
     check_same("1080p", ref, got)
+
+
+def test_generated_vdi_is_rendered_without_a_host_copy(tiny_vol):
+    """vdi_generate's device planes go straight into vdi_create and
+    vdi_replace_begin (planes_on_device): renders are bit-identical to those
+    of the same VDI generated on the CPU and uploaded from host memory."""
+    from paper_2206_08660_amd import vdi as V
+    spec = inputs.WORKLOADS["tiny"]
+    W0, H0, ns = spec["width"], spec["height"], spec["ns"]
+    dvol = to_device(tiny_vol)
+    bmin, bmax = inputs.aabb_for(tiny_vol.shape[::-1])
+
+    def both(base):
+        cam_o = inputs.orbit_camera(0.0, base)
+        host = inputs.generate_vdi(tiny_vol, cam_o, W0, H0, ns, spec["tf"], 0.0)
+        c, d, r, _ = V.generate(dvol, bmin, bmax, cam_o, W0, H0, ns, tf="ramp", gamma=0.0, gamma_out=False)
+        return host, V.DeviceVDI(c, d, r, cam_o, host.bmin, host.bmax, grid_z=host.grid_z)
+
+    host0, dev0 = both(0.0)
+    host1, dev1 = both(25.0)
+    views = [(inputs.orbit_camera(12.0), 1.0, 0.0), (inputs.orbit_camera(-20.0), 2.0, 1.5)]
+    with V.Vdi(host0) as hh, V.Vdi(dev0) as hd:
+        for cam, di, dr in views:
+            a, b = hh.render(cam, 96, 80, di, dr), hd.render(cam, 96, 80, di, dr)
+            torch.cuda.synchronize()
+            assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+        assert hd.info().supersegments == int(host0.count.sum())
+        # Replacement from device planes written on the caller's stream.
+        hd.replace_begin(dev1)
+        while not hd.replace_poll():
+            pass
+        with V.Vdi(host1) as h1:
+            for cam, di, dr in views:
+                a, b = h1.render(cam, 96, 80, di, dr), hd.render(cam, 96, 80, di, dr)
+                torch.cuda.synchronize()
+                assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+    with pytest.raises(V.VdiError):
+        V.Vdi(dev0, validate=True)   # list validation needs host planes
