@@ -111,6 +111,33 @@ def test_random_vdi_exact(seed, theta):
                 assert np.abs(img - ref).max() <= TOL, (ess, search)
 
 
+def test_random_vdi_max_ns_inside_and_extreme_shapes():
+    """N_S = 255 (the maximum; most lists full), a V_N camera inside the
+    volume's box (rays start at V_N's near plane), a preview ray grid split
+    over 8 lanes, and output shapes at the size limit (16384 x 2, 3 x 16384);
+    sampled pixels of the large frames against the oracle."""
+    V = _v()
+    v = synth.random_vdi(24, 20, 255, seed=31, empty_frac=0.05, alpha_max=0.08)
+    say(f"[gpu] N_S=255 random VDI, {int(v.count.sum())} supersegments, max count {int(v.count.max())}")
+    inside = inputs.Camera(eye=(0.05, -0.02, 0.0), target=(0.3, 0.1, -1.5), up=(0.0, 1.0, 0.0), fov_y_deg=70.0)
+    with V.Vdi(v, validate=True) as h:
+        for cam in (inputs.orbit_camera(17.0), inside):
+            ref = oracle.render_exact(v, cam, 48, 36)
+            for search in ("window", "seeded"):
+                img = gpu_render(h, cam, 48, 36, search=search)
+                assert np.abs(img - ref).max() <= TOL, search
+            pref, flags = oracle.render_preview(v, cam, 48, 36, 0.7)
+            pimg = gpu_render(h, cam, 48, 36, d_r=0.7)
+            ok = flags == 0
+            assert ok.mean() > 0.9 and np.abs(pimg - pref)[ok].max() <= TOL
+        cam = inputs.orbit_camera(-23.0)
+        for W, H in ((16384, 2), (3, 16384)):
+            pix = sample_pixels(W, H, 3000, seed=W)
+            ref = oracle.render_exact(v, cam, W, H, pixels=pix)
+            img = gpu_render(h, cam, W, H).reshape(-1, 4)[pix]
+            assert np.abs(img - ref).max() <= TOL, (W, H)
+
+
 def test_slab_closed_form_on_gpu():
     V = _v()
     slabs = [(1.2, 1.4, 2.0, (0.9, 0.1, 0.1)), (1.5, 1.9, 5.0, (0.1, 0.8, 0.3))]
