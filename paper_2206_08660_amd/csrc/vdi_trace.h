@@ -47,7 +47,10 @@ VDI_HD inline double dot3(const double *a, const double *b) { return a[0] * b[0]
 // neighbours, whose rays cross the same V_O lists, share an L2) while the
 // bands of every XCD are spread over the image (the work is balanced).
 // The map is a bijection from [0, tiles_x * tiles_y) onto itself.
-constexpr int kBandRows = 8 / kTileH > 0 ? 8 / kTileH : 1;  // tile rows per band: 8 pixel rows
+#ifndef VDI_BAND_ROWS
+#define VDI_BAND_ROWS 8
+#endif
+constexpr int kBandRows = VDI_BAND_ROWS / kTileH > 0 ? VDI_BAND_ROWS / kTileH : 1;  // tile rows per band
 
 VDI_HD inline int xcd_tile(int bid, int tiles_x, int tiles_y)
 {
