@@ -51,6 +51,7 @@ def parse():
     p.add_argument("--skip-paced", action="store_true")
     p.add_argument("--skip-generation", action="store_true")
     p.add_argument("--skip-quality", action="store_true")
+    p.add_argument("--skip-search", action="store_true")
     p.add_argument("--profile-pass", action="store_true",
                    help="short run for rocprofv3: one 1 GiB copy (counter calibration) and one exact render per angle")
     p.add_argument("--profile-generation", action="store_true",
@@ -244,6 +245,8 @@ def main():
         "breakdown": breakdown,
     }
 
+    if not args.skip_search:
+        result["search"] = search_leg(h, cams, out, stream, torch)
     if not args.skip_precision:
         result["precision"] = precision_leg(src, cams, out, exact_ms, torch, V)
     if not args.skip_served:
@@ -261,6 +264,24 @@ def main():
     if not args.skip_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline_leg(src, cams, per, result.get("precision"), np, torch, V)
     print(json.dumps(result), flush=True)
+
+
+def search_leg(h, cams, out, stream, torch):
+    """First-supersegment search strategies (Section 4.2, supplement Alg. S2 /
+    Fig. 4): exact frames at the 10 viewpoints with each search, with and
+    without empty-space skipping (the image is the same for all)."""
+    res = {}
+    for ess in (True, False):
+        for search in ("window", "seeded", "binary", "linear"):
+            ms = {f"{th:g}": round(_event_ms(lambda: h.render(cams[th], W, H, out=out, ess=ess, search=search),
+                                             stream, torch, reps=3, warm=1), 4) for th in ANGLES}
+            res[f"{search}{'' if ess else '_no_ess'}"] = {"sum_ms": round(sum(ms.values()), 3), "per_angle_ms": ms}
+    w = res["window"]["sum_ms"]
+    log("search (exact sweep, ms): " + ", ".join(f"{k} {v['sum_ms']}" for k, v in res.items()))
+    res["speedup_window_vs_best_of_binary_linear"] = round(min(res["binary"]["sum_ms"], res["linear"]["sum_ms"]) / w, 2)
+    res["speedup_seeded_vs_best_of_binary_linear"] = round(
+        min(res["binary"]["sum_ms"], res["linear"]["sum_ms"]) / res["seeded"]["sum_ms"], 2)
+    return res
 
 
 def precision_leg(src, cams, out, exact_ms, torch, V):
