@@ -319,9 +319,13 @@ typedef struct {
  * [N_S][height][width][4] float32 straight colour and accumulated opacity;
  * slots at index >= count are zero.  gamma_out [height][width] float64 (may be
  * NULL): the gamma each ray used (0 for rays that miss the volume).
- * Asynchronous on `stream` (NULL: the null stream).
+ * Asynchronous on `stream` (NULL: the null stream).  Uses up to 4 GiB of
+ * device scratch (each resident wavefront's cache of its rays' samples) from
+ * the library's stream-ordered pool, which keeps freed blocks for reuse until
+ * the process ends.
  * Errors: VDI_ERR_ARG (null pointers, sizes or formats out of range,
- * non-finite or degenerate camera, empty AABB, gamma < 0), VDI_ERR_HIP.
+ * non-finite or degenerate camera, empty AABB, gamma < 0), VDI_ERR_OOM
+ * (scratch), VDI_ERR_HIP.
  */
 int vdi_generate(const vdi_volume *volume, const vdi_gen_params *params, uint8_t *count, float *depth, float *rgba,
                  double *gamma_out, void *stream);
