@@ -1,0 +1,87 @@
+"""The renderer's per-ray code compiled for the host (hipcc; nothing runs on
+a GPU): exact rays with every first-supersegment search, with and without
+empty-space skipping, and preview rays split into 1, 2, 4 or 8 blocks of grid
+cells combined in the kernel's order, against the FP64 oracle (the count
+grid comes from the oracle)."""
+import ctypes
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+from paper_2206_08660_amd import vdi as V
+from tests import synth
+from tests.gpu_util import TOL
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+
+
+@pytest.fixture(scope="module")
+def host(tmp_path_factory):
+    if shutil.which("hipcc") is None:
+        pytest.skip("hipcc not available")
+    out = str(tmp_path_factory.mktemp("renderhost") / "librender_host.so")
+    cmd = ["hipcc", "--offload-arch=gfx950", "-O2", "-std=c++17", "-fPIC", "-shared",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(ROOT, "paper_2206_08660_amd", "csrc"),
+           os.path.join(HERE, "host", "render_host.hip"), "-o", out]
+    subprocess.run(cmd, check=True, capture_output=True)
+    L = ctypes.CDLL(out)
+    L.host_render.argtypes = [ctypes.POINTER(V.Desc), ctypes.c_void_p, ctypes.POINTER(V.Camera), ctypes.c_int,
+                              ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_float, ctypes.c_int,
+                              ctypes.c_void_p]
+    return L
+
+
+def render(L, src, cam, W, H, preview=False, search="window", ess=True, d_r=0.0, parts=0):
+    d, keep = V._desc(src, "f32", False, None, "f32")
+    grid = np.ascontiguousarray(oracle.count_grid(src), dtype=np.uint32)
+    gz = np.ascontiguousarray(src.grid_z, dtype=np.float32)
+    d.grid_z = gz.ctypes.data
+    out = np.zeros((H, W, 4), np.float32)
+    c = V.camera(cam)
+    rc = L.host_render(ctypes.byref(d), grid.ctypes.data, ctypes.byref(c), W, H, int(preview), V.SEARCH[search],
+                       int(ess), d_r, parts, out.ctypes.data)
+    assert rc == 0
+    return out.astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return inputs.load_workload("tiny", keep_dvr=False)
+
+
+@pytest.mark.parametrize("theta", [7.0, -33.0, 120.0])
+def test_exact_every_search_and_skipping(host, tiny, theta):
+    cam = inputs.orbit_camera(theta)
+    ref = oracle.render_exact(tiny, cam, 64, 48)
+    for ess in (True, False):
+        for search in ("window", "seeded", "binary", "linear"):
+            img = render(host, tiny, cam, 64, 48, search=search, ess=ess)
+            assert np.abs(img - ref).max() <= TOL, (ess, search)
+
+
+def test_exact_random_vdi(host):
+    v = synth.random_vdi(30, 20, 9, seed=12)
+    for theta in (25.0, 135.0):
+        cam = inputs.orbit_camera(theta)
+        ref = oracle.render_exact(v, cam, 40, 26)
+        assert np.abs(render(host, v, cam, 40, 26) - ref).max() <= TOL
+
+
+@pytest.mark.parametrize("parts", [1, 2, 4, 8])
+def test_preview_split_rays(host, tiny, parts):
+    cam = inputs.orbit_camera(9.0)
+    ref, flags = oracle.render_preview(tiny, cam, 64, 48, 2.0)
+    ok = flags == 0
+    img = render(host, tiny, cam, 64, 48, preview=True, d_r=2.0, parts=parts)
+    whole = render(host, tiny, cam, 64, 48, preview=True, d_r=2.0, parts=1)
+    assert ok.mean() > 0.9
+    assert np.abs(img - ref)[ok].max() <= TOL
+    # The blocks take the whole ray's samples; only rounding and early termination differ.
+    assert np.abs(img - whole).max() <= 1e-5
