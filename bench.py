@@ -484,6 +484,32 @@ def quality_leg(src, h, cams, out, stream, torch, V):
                                "vdi_no_ess_ms": round(noess, 4), "dvr_f32_ms": round(d32, 3),
                                "speedup_vs_dvr_f32": round(d32 / vdi_ms, 1)}
     res["720p_exact_vs_dvr"] = row
+    # GPU against the CPU FP64 references (all host threads) on one 1280x720 frame at 30 deg:
+    # DVR (the generator's own DVR pass on the CPU) and SSIM / PSNR (numpy on the CPU).
+    from oracle import quality as Q
+    cam = inputs.orbit_camera(30.0)
+    gpu_dvr = _event_ms(lambda: V.dvr(dvol, s720.bmin, s720.bmax, cam, w7, h7, tf=tf, precision="f64", out=r7),
+                        stream, torch, reps=3, warm=1)
+    with V.Vdi(s720) as h720:
+        h720.render(cam, w7, h7, out=o7)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    V.image_quality(o7, r7)
+    gpu_q = time.perf_counter() - t
+    vol = inputs.make_volume(spec)
+    t = time.perf_counter()
+    cpu_dvr = inputs.generate_vdi(vol, cam, w7, h7, 1, spec["tf"], gamma=10.0).dvr
+    t_dvr = time.perf_counter() - t
+    del vol
+    img = o7.cpu().numpy()
+    t = time.perf_counter()
+    Q.ssim(img, cpu_dvr)
+    Q.psnr(img, cpu_dvr)
+    t_q = time.perf_counter() - t
+    res["gpu_vs_cpu_reference_720p_30deg"] = {
+        "gpu_dvr_f64_ms": round(gpu_dvr, 3), "cpu_fp64_dvr_ms": round(1e3 * t_dvr, 1),
+        "gpu_ssim_psnr_ms": round(1e3 * gpu_q, 3), "cpu_ssim_psnr_ms": round(1e3 * t_q, 1),
+        "cpu_threads": inputs.generator_threads()}
     del dvol
     torch.cuda.empty_cache()
     log("quality 720p: " + ", ".join(f"{k} deg x{v['speedup_vs_dvr_f32']} vs DVR, SSIM {v['ssim']}" for k, v in row.items()))
@@ -545,6 +571,14 @@ def generation_leg(src, torch, V):
             row[f"N_S={ns}"] = {"mean_ms": round(float(np.mean(ms)), 2), "max_ms": round(float(np.max(ms)), 2),
                                 "supersegments_mean": segs // 12}
             del bufs
+        if name == "720p":
+            # The CPU FP64 generator (the oracle of this kernel) on the same VDI, on all host threads.
+            vol = inputs.make_volume(spec)
+            t = time.perf_counter()
+            inputs.generate_vdi(vol, inputs.orbit_camera(0.0), W0, H0, 20, spec["tf"], 0.0)
+            row["cpu_generator_N_S=20_view0_ms"] = round(1e3 * (time.perf_counter() - t), 1)
+            row["cpu_generator_threads"] = inputs.generator_threads()
+            del vol
         if name == "1080p":
             count, depth, rgba, _ = V.generate(dvol, bmin, bmax, src.camera, W0, H0, src.ns, tf=tf, gamma_out=False)
             torch.cuda.synchronize()
