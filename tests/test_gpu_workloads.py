@@ -88,6 +88,21 @@ def test_720p_exact_sampled(w720, h720, theta):
             assert np.abs(other - img).max() <= 1e-6, (ess, search)
 
 
+@pytest.mark.parametrize("theta,d_i,d_r", [(12.0, 2.0, 2.0), (35.0, 4.0, 1.0), (20.0, 1.0, 3.0)])
+def test_720p_preview_sampled(w720, h720, theta, d_i, d_r):
+    """The dense slab, where rays terminate early: preview rays split over 2
+    and 8 lanes (D_I = 2 and 4) composite each block from full transmittance,
+    so a block behind the serial stop adds at most 1e-5."""
+    say(f"[gpu] 720p preview theta={theta} D_I={d_i} D_R={d_r}")
+    cam = inputs.orbit_camera(theta)
+    pix = sample_pixels(1280, 720, 5000, seed=300 + int(theta))
+    ref, flags = oracle.render_points(w720, cam, 1280, 720, d_i, d_r, pix)
+    img = frame(h720, cam, 1280, 720, d_i=d_i, d_r=d_r)
+    ok = flags == 0
+    assert ok.sum() >= 3000
+    assert np.abs(img[pix][ok] - ref[ok]).max() <= TOL
+
+
 def test_1080p_grid_bit_exact(w1080, h1080):
     assert np.array_equal(h1080.grid(), oracle.count_grid(w1080))
 
