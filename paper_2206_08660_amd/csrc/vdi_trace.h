@@ -781,59 +781,75 @@ VDI_HD Accum trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, i
         }
         int p = -1;
         const int max_iter = 4 * (WO + HO) / k + 4 * V.gnz + 64;
-        bool done = false;
-        for (int it = 0; it < max_iter && it < c_hi && !done; ++it) {
-            const double tn = fmin(fmin(fmin(tx, ty), tz), r.t1);
-            if (it >= c_lo && tn > t) {
-                const uint32_t G = V.grid[((uint64_t)cz * V.GH + cy) * V.GW + cx];
-                if (G != 0u) {
-                    const double dz = (double)s_gz[cz + 1] - (double)s_gz[cz];
-                    const double x = ((tn - t) / dz) * ((double)G * inv_k2) / F.DR;
-                    // D_R >= 1e-4 keeps x far below this bound; it only caps the loop.
-                    const int n = (int)fmin(fmax(ceil(x), 1.0), 16777216.0);
-                    const double h = (tn - t) / n;
-                    // List of sample q (its count is fetched one sample ahead).
-                    auto sample_list = [&](int q, double &u, double &z) -> uint64_t {
-                        u = t + (q + 0.5) * h;
-                        z = F.Z0 + u * r.Zp;
-                        const double iz = rcp64(z);
-                        const int lx = min(max((int)floor(((F.X0 + u * r.Xp) * iz + 1.0) * (0.5 * WO)), 0), WO - 1);
-                        const int ly = min(max((int)floor(((F.Y0 + u * r.Yp) * iz + 1.0) * (0.5 * HO)), 0), HO - 1);
-                        return (uint64_t)ly * WO + lx;
-                    };
-                    double u, z;
-                    uint64_t li = sample_list(0, u, z);
-                    int nl = V.count[li];
-                    for (int q = 0; q < n; ++q) {
-                        double un = 0.0, zn = 0.0;
-                        const uint64_t lin = q + 1 < n ? sample_list(q + 1, un, zn) : li;
-                        const int nln = q + 1 < n ? (int)V.count[lin] : 0;
-                        if (nl > 0) {
-                            // Point location: the supersegment with f <= z < b.
-                            const uint64_t lb = list_base(li, V.NS);
-                            const int j = first_back_above_win(dep, stride, lb, nl, z, fwd ? win_start_fwd(p) : win_start_bwd(p));
-                            if (j < nl) {
-                                const float2 fb = dep[(uint64_t)j * stride + lb];
-                                p = j;
-                                if ((double)fb.x <= z) {
-                                    const int lx = (int)(li % (uint64_t)WO), ly = (int)(li / (uint64_t)WO);
-                                    const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * stride + lb, V.fmt);
-                                    composite(A, c, (float)h * list_cos(V, lx, ly) * rcp32(fb.y - fb.x));
-                                    if (A.T <= kTTerm) {
-                                        done = true;
-                                        break;
-                                    }
-                                }
-                            }
-                        }
-                        li = lin;
-                        nl = nln;
-                        u = un;
-                        z = zn;
+        // List of sample q of the current cell (its count is fetched one sample ahead).
+        double h = 0.0;
+        auto sample_list = [&](int q, double &u, double &z) -> uint64_t {
+            u = t + (q + 0.5) * h;
+            z = F.Z0 + u * r.Zp;
+            const double iz = rcp64(z);
+            const int lx = min(max((int)floor(((F.X0 + u * r.Xp) * iz + 1.0) * (0.5 * WO)), 0), WO - 1);
+            const int ly = min(max((int)floor(((F.Y0 + u * r.Yp) * iz + 1.0) * (0.5 * HO)), 0), HO - 1);
+            return (uint64_t)ly * WO + lx;
+        };
+        // One flat loop: every step either enters the current grid cell (and,
+        // when the cell is non-empty and in this lane's block, sets up its
+        // samples) or takes one sample.  Lanes of a wavefront that are
+        // walking cells and lanes that are sampling thus advance together,
+        // instead of a cell step waiting for the wavefront's longest run of
+        // samples in a cell.
+        int it = 0;        // cells entered
+        int q = 0, n = 0;  // sample q of n in the current cell; n == 0 between cells
+        double tn = 0.0, u = 0.0, z = 0.0;
+        uint64_t li = 0;
+        int nl = 0;
+        for (;;) {
+            bool advance = true;
+            if (n == 0) {
+                if (it >= max_iter || it >= c_hi) break;
+                tn = fmin(fmin(fmin(tx, ty), tz), r.t1);
+                if (it >= c_lo && tn > t) {
+                    const uint32_t G = V.grid[((uint64_t)cz * V.GH + cy) * V.GW + cx];
+                    if (G != 0u) {
+                        const double dz = (double)s_gz[cz + 1] - (double)s_gz[cz];
+                        const double x = ((tn - t) / dz) * ((double)G * inv_k2) / F.DR;
+                        // D_R >= 1e-4 keeps x far below this bound; it only caps the loop.
+                        n = (int)fmin(fmax(ceil(x), 1.0), 16777216.0);
+                        h = (tn - t) / n;
+                        q = 0;
+                        li = sample_list(0, u, z);
+                        nl = V.count[li];
+                        advance = false;
                     }
                 }
+            } else {
+                double un = 0.0, zn = 0.0;
+                const uint64_t lin = q + 1 < n ? sample_list(q + 1, un, zn) : li;
+                const int nln = q + 1 < n ? (int)V.count[lin] : 0;
+                if (nl > 0) {
+                    // Point location: the supersegment with f <= z < b.
+                    const uint64_t lb = list_base(li, V.NS);
+                    const int j = first_back_above_win(dep, stride, lb, nl, z, fwd ? win_start_fwd(p) : win_start_bwd(p));
+                    if (j < nl) {
+                        const float2 fb = dep[(uint64_t)j * stride + lb];
+                        p = j;
+                        if ((double)fb.x <= z) {
+                            const int lx = (int)(li % (uint64_t)WO), ly = (int)(li / (uint64_t)WO);
+                            const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * stride + lb, V.fmt);
+                            composite(A, c, (float)h * list_cos(V, lx, ly) * rcp32(fb.y - fb.x));
+                            if (A.T <= kTTerm) break;
+                        }
+                    }
+                }
+                li = lin;
+                nl = nln;
+                u = un;
+                z = zn;
+                ++q;
+                advance = q == n;
+                if (advance) n = 0;
             }
-            if (done || tn >= r.t1) break;
+            if (!advance) continue;
+            if (tn >= r.t1) break;
             if (tx <= ty && tx <= tz) {
                 cx += sx;
                 mx = sx > 0 ? min((cx + 1) * k, WO) : cx * k;
@@ -850,6 +866,7 @@ VDI_HD Accum trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, i
                     tz = cz > 0 ? ((double)s_gz[cz] - F.Z0) * invZp : inf;
             }
             t = fmax(t, tn);
+            ++it;
             if ((unsigned)cx >= (unsigned)V.GW || (unsigned)cy >= (unsigned)V.GH || (unsigned)cz >= (unsigned)V.gnz)
                 break;
         }
