@@ -54,6 +54,8 @@ def parse():
     p.add_argument("--skip-search", action="store_true")
     p.add_argument("--profile-pass", action="store_true",
                    help="short run for rocprofv3: one 1 GiB copy (counter calibration) and one exact render per angle")
+    p.add_argument("--profile-preview", action="store_true",
+                   help="short run for rocprofv3: one D_I=2/D_R=2 and one D_I=4/D_R=2 render per angle")
     p.add_argument("--profile-generation", action="store_true",
                    help="short run for rocprofv3: one 1 GiB copy, then two GPU generations of the 720p VDI "
                         "(1280x720, N_S=20, generating view 0 deg), the second the one to read")
@@ -110,6 +112,14 @@ def main():
             h.render(cams[th], W, H, 1.0, 0.0, out=out)
         torch.cuda.synchronize()
         log("profile pass done")
+        return
+    if args.profile_preview:
+        for th in ANGLES:
+            for di, dr in MODES:
+                if dr > 0.0:
+                    h.render(cams[th], W, H, di, dr, out=out)
+        torch.cuda.synchronize()
+        log("preview profile pass done")
         return
 
     # Every render of the timed steps is bracketed by HIP events on the
