@@ -260,6 +260,7 @@ void free_set(vdi::VdiSet &S)
     (void)hipFree(S.d_depth);
     (void)hipFree(S.d_rgba);
     (void)hipFree(S.d_grid);
+    (void)hipFree(S.d_gbits);
     (void)hipFree(S.d_gz);
     S = vdi::VdiSet();
 }
@@ -394,6 +395,7 @@ hipError_t upload_set(vdi::VdiSet &S, const vdi_desc *d, const uint8_t *counts, 
     memcpy(S.bmax, d->aabb_max, sizeof S.bmax);
     const uint64_t elems = vdi::plane_elems(plane, (int)ns);
     const size_t grid_bytes = (size_t)D.gnz * D.GH * D.GW * sizeof(uint32_t);
+    const size_t gbits_bytes = ((size_t)D.gnz * D.GH * D.GW + 31) / 32 * sizeof(uint32_t);
     hipError_t e = hipSuccess;
     if (!S.d_count) {
         *what = "device allocation";
@@ -401,6 +403,7 @@ hipError_t upload_set(vdi::VdiSet &S, const vdi_desc *d, const uint8_t *counts, 
         if (e == hipSuccess) e = hipMalloc((void **)&S.d_depth, elems * sizeof(float2));
         if (e == hipSuccess) e = hipMalloc(&S.d_rgba, elems * colour);
         if (e == hipSuccess) e = hipMalloc((void **)&S.d_grid, grid_bytes);
+        if (e == hipSuccess) e = hipMalloc((void **)&S.d_gbits, gbits_bytes);
         if (e == hipSuccess) e = hipMalloc((void **)&S.d_gz, gz.size() * sizeof(float));
         if (e != hipSuccess) return e;
     }
@@ -408,6 +411,7 @@ hipError_t upload_set(vdi::VdiSet &S, const vdi_desc *d, const uint8_t *counts, 
     D.depth = S.d_depth;
     D.rgba = S.d_rgba;
     D.grid = S.d_grid;
+    D.gbits = S.d_gbits;
     D.gz = S.d_gz;
     *what = "upload";
     const hipMemcpyKind kind = d->planes_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
@@ -431,6 +435,7 @@ hipError_t upload_set(vdi::VdiSet &S, const vdi_desc *d, const uint8_t *counts, 
     if (e != hipSuccess) return e;
     *what = "grid build";
     e = vdi::launch_grid_build(D, S.d_grid, st);
+    if (e == hipSuccess) e = vdi::launch_grid_bits(D, S.d_gbits, st);
     uint64_t total = 0;
     for (uint64_t li = 0; li < plane; ++li) total += counts[li];
     S.supersegments = total;

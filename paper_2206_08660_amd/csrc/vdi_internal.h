@@ -81,6 +81,7 @@ struct DevVDI {
     const float2 *depth;       // (f, b), plane_elems(plane, NS) in brick order
     const void *rgba;          // same order; float4 or 4 x 16-bit
     const uint32_t *grid;      // [gnz][GH][GW]
+    const uint32_t *gbits;     // occupancy of the same cells, 32 per word: bit c % 32 of word c / 32 is (grid[c] != 0)
     int32_t gk, gnz, GW, GH;
     const float *gz;           // [gnz + 1] slice boundaries (device)
     float tx_o, ty_o;          // tan(fov/2) * aspect, tan(fov/2) of V_O
@@ -139,6 +140,7 @@ struct VdiSet {
     float2 *d_depth = nullptr;
     void *d_rgba = nullptr;
     uint32_t *d_grid = nullptr;
+    uint32_t *d_gbits = nullptr;
     float *d_gz = nullptr;
     uint64_t supersegments = 0;
 };
@@ -185,6 +187,8 @@ hipError_t launch_render_preview(const DevVDI &v, const Frame &f, hipStream_t st
 hipError_t launch_upsample(const float4 *lo, int32_t w, int32_t h, float4 *out, int32_t W, int32_t H,
                            hipStream_t stream);
 hipError_t launch_grid_build(const DevVDI &v, uint32_t *grid, hipStream_t stream);
+// Occupancy bits of the count grid (see DevVDI::gbits).
+hipError_t launch_grid_bits(const DevVDI &v, uint32_t *bits, hipStream_t stream);
 // n elements of slot-major input planes, starting at slot j0 (n a multiple of
 // v.plane), into v's storage order; colour converted from fmt_in to fmt_store.
 hipError_t launch_scatter_slots(const void *src, int32_t fmt_in, void *dst, int32_t fmt_store, bool depth, uint64_t n,

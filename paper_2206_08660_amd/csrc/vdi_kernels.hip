@@ -180,6 +180,22 @@ __global__ __launch_bounds__(256) void k_grid_build(DevVDI V, uint32_t *__restri
         grid[((uint64_t)c * V.GH + cy) * V.GW + cx] = s_cnt[c];
 }
 
+// Occupancy bits of the count grid, one 32-cell word per lane.  The exact
+// walker only asks whether a cell is empty; 81 KB of bits for the 1080p VDI's
+// 648,000 cells stay in L1 where the 2.6 MB of counts do not.
+__global__ __launch_bounds__(256) void k_grid_bits(const uint32_t *__restrict__ grid, uint32_t *__restrict__ bits,
+                                                   uint32_t ncells)
+{
+    const uint32_t w = blockIdx.x * 256u + threadIdx.x;
+    if (w >= (ncells + 31u) / 32u) return;
+    uint32_t b = 0u;
+    for (uint32_t i = 0; i < 32u; ++i) {
+        const uint32_t c = w * 32u + i;
+        if (c < ncells && grid[c] != 0u) b |= 1u << i;
+    }
+    bits[w] = b;
+}
+
 // ---------------------------------------------------------------------------
 // Upload: slots [j0, j0 + n / plane) of slot-major input planes are scattered
 // into the device's brick order, converting colour float32 -> binary16 /
@@ -311,6 +327,14 @@ hipError_t launch_grid_build(const DevVDI &v, uint32_t *grid, hipStream_t s)
 {
     const int threads = ((v.gk * v.gk + 63) / 64) * 64;
     k_grid_build<<<dim3((unsigned)(v.GW * v.GH)), threads, 0, s>>>(v, grid);
+    return hipGetLastError();
+}
+
+hipError_t launch_grid_bits(const DevVDI &v, uint32_t *bits, hipStream_t s)
+{
+    const uint32_t ncells = (uint32_t)v.gnz * (uint32_t)v.GH * (uint32_t)v.GW;
+    const uint32_t words = (ncells + 31u) / 32u;
+    k_grid_bits<<<dim3((words + 255u) / 256u), 256, 0, s>>>(v.grid, bits, ncells);
     return hipGetLastError();
 }
 

@@ -575,6 +575,13 @@ VDI_HD bool do_list(const DevVDI &V, const Frame &F, int ix, int iy, int n, doub
     return false;
 }
 
+// Whether grid cell `cell` holds any supersegment, from the occupancy bits
+// (the exact walker needs no more than that from the count grid).
+VDI_HD inline bool cell_occupied(const DevVDI &V, int cell)
+{
+    return (V.gbits[(uint32_t)cell >> 5] >> ((uint32_t)cell & 31u)) & 1u;
+}
+
 // ---------------------------------------------------------------------------
 // Exact render (Sections 4.1-4.3)
 // ---------------------------------------------------------------------------
@@ -601,8 +608,8 @@ VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, in
     // (ix, iy): current list; the next x (y) grid line crossed is ix + (sx > 0).
     int ix = 0, iy = 0, cz = 0;
     const int ox = sx > 0, oy = sy > 0;
-    int ccell = -1;  // grid cell whose count cg holds (fewer than 2^31 cells)
-    uint32_t cg = 0;
+    int ccell = -1;  // grid cell whose occupancy cg holds (fewer than 2^31 cells)
+    bool cg = false;  // whether grid cell ccell is occupied
     auto slice_t = [&](int c) -> double {
         if (flat) return inf;
         if (fwd) return c + 1 < V.gnz ? ((double)s_gz[c + 1] - F.Z0) * invZp : inf;
@@ -661,8 +668,7 @@ VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, in
                     break;
                 t = fmax(t, te);
                 const int cell = (cz * V.GH + iy) * V.GW + ix;
-                const uint32_t g = V.grid[cell];
-                if (g != 0u) {
+                if (cell_occupied(V, cell)) {
                     cellmode = false;
                     locate(t);
                     n = V.count[(uint64_t)iy * WO + ix];
@@ -680,10 +686,10 @@ VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, in
             const int cx = (int)((float)ix * V.inv_gk), cy = (int)((float)iy * V.inv_gk);
             const int cell = (cz * V.GH + cy) * V.GW + cx;
             if (cell != ccell) {
-                cg = V.grid[cell];
+                cg = cell_occupied(V, cell);
                 ccell = cell;
             }
-            if (cg == 0u) {
+            if (!cg) {
                 // Empty-space skipping: switch to walking cells (ix, iy become
                 // the cell indices, tx, ty the crossings of cell boundaries),
                 // unless the ray sits on the cell's exit (a located position

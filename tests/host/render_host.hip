@@ -36,6 +36,11 @@ extern "C" int host_render(const vdi_desc *d, const uint32_t *grid, const vdi_ca
     D.depth = dep.data();
     D.rgba = col.data();
     D.grid = grid;
+    const uint32_t ncells = (uint32_t)d->grid_nz * ((d->height + d->grid_k - 1) / d->grid_k) * ((d->width + d->grid_k - 1) / d->grid_k);
+    std::vector<uint32_t> bits((ncells + 31) / 32, 0u);
+    for (uint32_t c = 0; c < ncells; ++c)
+        if (grid[c] != 0u) bits[c / 32] |= 1u << (c % 32);
+    D.gbits = bits.data();
     D.gk = d->grid_k;
     D.gnz = d->grid_nz;
     D.GW = (d->width + d->grid_k - 1) / d->grid_k;
