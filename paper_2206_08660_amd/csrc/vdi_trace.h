@@ -691,12 +691,16 @@ VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, in
             }
             if (!cg) {
                 // Empty-space skipping: switch to walking cells (ix, iy become
-                // the cell indices, tx, ty the crossings of cell boundaries),
-                // unless the ray sits on the cell's exit (a located position
-                // rounded onto a cell boundary): then the list step below
-                // moves it across.
+                // the cell indices, tx, ty the crossings of cell boundaries)
+                // when that skips a list, i.e. the ray leaves its list before
+                // the cell: otherwise the list step below reaches the list's
+                // exit in one step where cells would take one per depth
+                // slice.  Not either when the ray sits on the cell's exit (a
+                // located position rounded onto a cell boundary): then the
+                // list step moves it across.
                 const double ctx = cell_tx(cx), cty = cell_ty(cy);
-                if (fmin(fmin(ctx, cty), fmin(tz, r.t1)) > t) {
+                const double te = fmin(fmin(ctx, cty), fmin(tz, r.t1));
+                if (te > t && tn < te) {
                     ix = cx;
                     iy = cy;
                     tx = ctx;

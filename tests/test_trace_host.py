@@ -66,6 +66,17 @@ def test_exact_every_search_and_skipping(host, tiny, theta):
             assert np.abs(img - ref).max() <= TOL, (ess, search)
 
 
+def test_exact_generating_view_with_skipping(host, tiny):
+    """From V_O itself at V_O's resolution every ray stays in its own list:
+    with skipping on, a ray in an empty grid cell takes the list step (one
+    step to the list's exit) rather than one cell step per depth slice."""
+    cam = tiny.camera
+    ref = oracle.render_exact(tiny, cam, tiny.width, tiny.height)
+    for ess in (True, False):
+        img = render(host, tiny, cam, tiny.width, tiny.height, ess=ess)
+        assert np.abs(img - ref).max() <= TOL, ess
+
+
 def test_exact_random_vdi(host):
     v = synth.random_vdi(30, 20, 9, seed=12)
     for theta in (25.0, 135.0):
