@@ -119,7 +119,7 @@ typedef struct {
 typedef struct {
     int32_t width, height, max_supersegments, rgba_fmt;
     int32_t grid_k, grid_nz, grid_w, grid_h;
-    uint64_t device_bytes; /* count + depth + colour planes + grid (twice, plus staging, once a replacement was made) */
+    uint64_t device_bytes; /* count + depth + colour planes + grid and its occupancy bits (twice, plus staging, once a replacement was made) */
     uint64_t supersegments; /* sum of count */
 } vdi_info_t;
 

@@ -359,8 +359,9 @@ uint64_t set_bytes_of(const vdi_desc *d)
     const uint64_t plane = (uint64_t)d->width * d->height;
     const uint64_t colour = d->rgba_fmt_store == VDI_F32 ? 16 : 8;
     const uint64_t gw = (d->width + d->grid_k - 1) / d->grid_k, gh = (d->height + d->grid_k - 1) / d->grid_k;
-    return plane + vdi::plane_elems(plane, d->max_supersegments) * (8 + colour) +
-           (uint64_t)d->grid_nz * gw * gh * sizeof(uint32_t) + (uint64_t)(d->grid_nz + 1) * sizeof(float);
+    const uint64_t cells = (uint64_t)d->grid_nz * gw * gh;
+    return plane + vdi::plane_elems(plane, d->max_supersegments) * (8 + colour) + cells * sizeof(uint32_t) +
+           (cells + 31) / 32 * sizeof(uint32_t) + (uint64_t)(d->grid_nz + 1) * sizeof(float);
 }
 
 // Upload d into the set S on stream st: allocate S's buffers if it has none,
