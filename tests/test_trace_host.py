@@ -85,9 +85,11 @@ def test_exact_random_vdi(host):
         assert np.abs(render(host, v, cam, 40, 26) - ref).max() <= TOL
 
 
+@pytest.mark.parametrize("theta", [9.0, 150.0])
 @pytest.mark.parametrize("parts", [1, 2, 4, 8])
-def test_preview_split_rays(host, tiny, parts):
-    cam = inputs.orbit_camera(9.0)
+def test_preview_split_rays(host, tiny, parts, theta):
+    """Rays moving away from V_O (9 deg) and towards it (150 deg)."""
+    cam = inputs.orbit_camera(theta)
     ref, flags = oracle.render_preview(tiny, cam, 64, 48, 2.0)
     ok = flags == 0
     img = render(host, tiny, cam, 64, 48, preview=True, d_r=2.0, parts=parts)
