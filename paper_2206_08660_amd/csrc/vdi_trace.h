@@ -738,9 +738,10 @@ VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, in
 // Part `part` of `parts` of the preview ray through V_N pixel (px, py) of
 // the (low-res) grid: the samples of a contiguous block of the grid cells the
 // ray crosses, composited front to back from full transmittance.  The blocks
-// split the walk's cell sequence evenly by an estimate of its length (cells
-// between entry and exit); every part walks the same sequence, so together
-// the parts take exactly the samples of the whole ray (parts = 1).
+// cut the ray's parameter range into equal parts, each cut moved back to the
+// entry of the cell it falls in; a part starts at its first cell and stops
+// where the next part starts, so together the parts take exactly the samples
+// of the whole ray (parts = 1).
 template <int FMT>
 VDI_HD Accum trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, int px, int py, int part = 0,
                            int parts = 1)
@@ -778,14 +779,46 @@ VDI_HD Accum trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, i
             else
                 tz = cz > 0 ? ((double)s_gz[cz] - F.Z0) * invZp : inf;
         };
-        int c_lo = 0, c_hi = 0x7fffffff;
+        // Parameter at which the walk enters the cell holding the ray at
+        // parameter u: the latest crossing of the cell's faces behind the ray
+        // (the walk computes the same crossings, in the same way, as it leaves
+        // the cells before).  A face counts if it is crossed before the cell's
+        // exit: one with no crossing on the ray's valid branch was not crossed
+        // to get there, and u itself may lie a rounding error before a face
+        // that the cell lookup already puts behind it.
+        auto entry_at = [&](double u) -> double {
+            locate(u);
+            const double exit_t = fmin(fmin(tx, ty), fmin(tz, r.t1));
+            double te = r.t0;
+            auto take = [&](double tf) {
+                if (tf < exit_t) te = fmax(te, tf);
+            };
+            if (sx != 0) {
+                const int m = sx > 0 ? cx * k : (cx + 1) * k;
+                if (m > 0 && m < WO) take(line_t(m, V.dcx, F.X0, r.Xp, F.Z0, r.Zp));
+            }
+            if (sy != 0) {
+                const int m = sy > 0 ? cy * k : (cy + 1) * k;
+                if (m > 0 && m < HO) take(line_t(m, V.dcy, F.Y0, r.Yp, F.Z0, r.Zp));
+            }
+            if (!flat) {
+                const int c = fwd ? cz : cz + 1;
+                if (c > 0 && c < V.gnz) take(((double)s_gz[c] - F.Z0) * invZp);
+            }
+            return te;
+        };
+        // Lane `part` takes the cells the walk enters in [its start, t_stop):
+        // the ray's parameter range cut into equal parts, each cut moved back
+        // to the entry of the cell it falls in, so the lanes need not walk the
+        // cells before their own.
+        double t_stop = inf;
         if (parts > 1) {
-            locate(r.t1);
-            const int ex = cx, ey = cy, ez = cz;
-            locate(t);
-            const long long cells = (long long)abs(ex - cx) + abs(ey - cy) + abs(ez - cz) + 1;
-            c_lo = (int)(cells * part / parts);
-            if (part + 1 < parts) c_hi = (int)(cells * (part + 1) / parts);
+            const double span = r.t1 - r.t0;
+            if (part + 1 < parts) t_stop = entry_at(r.t0 + span * (part + 1) / parts);
+            if (part > 0)
+                t = entry_at(r.t0 + span * part / parts);
+            else
+                locate(t);
         } else {
             locate(t);
         }
@@ -802,11 +835,10 @@ VDI_HD Accum trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, i
             return (uint64_t)ly * WO + lx;
         };
         // One flat loop: every step either enters the current grid cell (and,
-        // when the cell is non-empty and in this lane's block, sets up its
-        // samples) or takes one sample.  Lanes of a wavefront that are
-        // walking cells and lanes that are sampling thus advance together,
-        // instead of a cell step waiting for the wavefront's longest run of
-        // samples in a cell.
+        // when the cell is non-empty, sets up its samples) or takes one
+        // sample.  Lanes of a wavefront that are crossing empty cells and
+        // lanes that are sampling thus advance together, instead of a cell
+        // step waiting for the wavefront's longest run of samples in a cell.
         int it = 0;        // cells entered
         int q = 0, n = 0;  // sample q of n in the current cell; n == 0 between cells
         double tn = 0.0, u = 0.0, z = 0.0;
@@ -815,9 +847,9 @@ VDI_HD Accum trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, i
         for (;;) {
             bool advance = true;
             if (n == 0) {
-                if (it >= max_iter || it >= c_hi) break;
+                if (it >= max_iter || t >= t_stop) break;
                 tn = fmin(fmin(fmin(tx, ty), tz), r.t1);
-                if (it >= c_lo && tn > t) {
+                if (tn > t) {
                     const uint32_t G = V.grid[((uint64_t)cz * V.GH + cy) * V.GW + cx];
                     if (G != 0u) {
                         const double dz = (double)s_gz[cz + 1] - (double)s_gz[cz];
