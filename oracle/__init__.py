@@ -8,6 +8,7 @@ Functions (each follows a passage of the paper; see oracle.c for the plain
 definitions they implement):
   render_exact      exact raycast of a VDI from a new viewpoint (Sections 4.1-4.2, Eq. 2)
   render_preview    along-ray subsampled preview (Section 4.4) with tie flags
+  preview_tie_variants   the preview's valid results where samples rest on ties
   render            full entry point: D_I image downsampling + bilinear upsampling
   count_grid        per-cell supersegment counts (Section 4.3)
   march             brute-force fine-step marching of the same field (a check, not the method)
@@ -54,8 +55,8 @@ def _load():
         P = ctypes.c_void_p
         I = ctypes.c_int
         I64 = ctypes.c_int64
-        lib.or_render_exact.argtypes = [P, P, I, I, ctypes.c_double, I64, P, P, P, P, P, I]
-        lib.or_render_preview.argtypes = [P, P, I, I, ctypes.c_double, ctypes.c_double, I64, P, P, P, P, I]
+        lib.or_render_exact.argtypes = [P, P, I, I, ctypes.c_double, I64, P, P, P, P, P, P, I]
+        lib.or_render_preview.argtypes = [P, P, I, I, ctypes.c_double, ctypes.c_double, I64, P, P, P, P, P, I]
         lib.or_upsample.argtypes = [P, P, I, I, I, I, P, P]
         lib.or_upsample.restype = None
         lib.or_count_grid.argtypes = [P, P]
@@ -100,32 +101,42 @@ def threads() -> int:
 
 
 def render_exact(vdi, camera, width: int, height: int, pixels=None, rgba: Optional[np.ndarray] = None,
-                 stats: bool = False, touched: bool = False, nthreads: int = 0, aspect: float = 0.0):
+                 stats: bool = False, touched: bool = False, nthreads: int = 0, aspect: float = 0.0,
+                 ess: bool = False):
     """Exact FP64 render.  Returns out [H, W, 4] (or [npix, 4] for a pixel
     list of row-major indices py*W+px), premultiplied RGB + alpha.
     With stats=True also returns int64 [.., 2] = (lists entered, pieces
-    composited); with touched=True also (touched_lists [H,W] u8,
-    touched_S [NS,H,W] u8) of the VDI."""
+    composited), [.., 3] with ess=True (and lists entered over a part of
+    the ray inside a non-empty grid cell); with touched=True also
+    (touched_lists [H,W] u8, touched_S [NS,H,W] u8) of the VDI, and with
+    ess=True also touched_lists_ess [H,W] u8: the lists entered before
+    termination over a part of the ray inside a non-empty grid cell (the
+    lists empty-space skipping cannot skip, Section 4.3)."""
     lib = _load()
-    b = _Bound(vdi, rgba=rgba)
+    b = _Bound(vdi, rgba=rgba, grid=count_grid(vdi) if ess else None)
     cam = _cam(camera)
     pix = _pix(pixels)
     n = width * height if pix is None else len(pix)
     out = np.zeros((n, 4), dtype=np.float64)
-    st = np.zeros((n, 2), dtype=np.int64) if stats else None
+    st = np.zeros((n, 3), dtype=np.int64) if stats else None
     tl = np.zeros((vdi.height, vdi.width), dtype=np.uint8) if touched else None
     ts = np.zeros((vdi.ns, vdi.height, vdi.width), dtype=np.uint8) if touched else None
+    te = np.zeros((vdi.height, vdi.width), dtype=np.uint8) if (touched or stats) and ess else None
     lib.or_render_exact(ctypes.byref(b.c), _p(cam), width, height, float(aspect), n, _p(pix), _p(out), _p(st),
-                        _p(tl), _p(ts), nthreads)
+                        _p(tl), _p(ts), _p(te), nthreads)
+    if st is not None and not ess:
+        st = st[:, :2]
     if pix is None:
         out = out.reshape(height, width, 4)
         if st is not None:
-            st = st.reshape(height, width, 2)
+            st = st.reshape(height, width, st.shape[1])
     res = [out]
     if stats:
         res.append(st)
     if touched:
         res.extend([tl, ts])
+        if ess:
+            res.append(te)
     return res[0] if len(res) == 1 else tuple(res)
 
 
@@ -145,10 +156,13 @@ def lowres_size(width: int, height: int, d_i: float):
 
 
 def render_preview(vdi, camera, w: int, h: int, d_r: float, pixels=None, grid: Optional[np.ndarray] = None,
-                   rgba: Optional[np.ndarray] = None, nthreads: int = 0, samples: bool = False, aspect: float = 0.0):
+                   rgba: Optional[np.ndarray] = None, nthreads: int = 0, samples: bool = False, aspect: float = 0.0,
+                   bias=None):
     """Along-ray subsampled render of a w x h image (D_R > 0); aspect 0
     means w/h.  Returns (out [h, w, 4], flags [h, w] u8) or per-pixel arrays
-    for a pixel list."""
+    for a pixel list.  bias = (bx, by, bz, bn), each -1, 0 or +1, resolves
+    every tie of a ray one way (list edges in x and y, supersegment faces,
+    sample-count thresholds); None leaves ties to rounding."""
     lib = _load()
     if grid is None:
         grid = count_grid(vdi)
@@ -159,13 +173,31 @@ def render_preview(vdi, camera, w: int, h: int, d_r: float, pixels=None, grid: O
     out = np.zeros((n, 4), dtype=np.float64)
     flags = np.zeros(n, dtype=np.uint8)
     ns = np.zeros(n, dtype=np.int64)
+    bb = None if bias is None else np.ascontiguousarray(bias, dtype=np.float64)
+    assert bb is None or (bb.shape == (4,) and np.isin(bb, (-1.0, 0.0, 1.0)).all())
     rc = lib.or_render_preview(ctypes.byref(b.c), _p(cam), w, h, float(aspect), float(d_r), n, _p(pix), _p(out),
-                               _p(flags), _p(ns), nthreads)
+                               _p(flags), _p(ns), _p(bb), nthreads)
     if rc != 0:
         raise ValueError("render_preview needs D_R > 0")
     if pix is None:
         out, flags, ns = out.reshape(h, w, 4), flags.reshape(h, w), ns.reshape(h, w)
     return (out, flags, ns) if samples else (out, flags)
+
+
+TIE_BIASES = [(bx, by, bz, bn) for bx in (-1, 1) for by in (-1, 1) for bz in (-1, 1) for bn in (-1, 1)]
+
+
+def preview_tie_variants(vdi, camera, w: int, h: int, d_r: float, pixels, grid: Optional[np.ndarray] = None,
+                         rgba: Optional[np.ndarray] = None, nthreads: int = 0, aspect: float = 0.0) -> np.ndarray:
+    """The valid results of flagged preview pixels (Section 4.4 sampling
+    rule): the pixels rendered once per way of resolving their ties
+    consistently along the ray (TIE_BIASES, 16 ways).  Returns
+    [len(TIE_BIASES), npix, 4]; a result that rests on ties is correct when
+    it equals one of these."""
+    if grid is None:
+        grid = count_grid(vdi)
+    return np.stack([render_preview(vdi, camera, w, h, d_r, pixels=pixels, grid=grid, rgba=rgba, nthreads=nthreads,
+                                    aspect=aspect, bias=b)[0] for b in TIE_BIASES])
 
 
 def upsample(lo: np.ndarray, width: int, height: int, lo_flags: Optional[np.ndarray] = None):

@@ -222,6 +222,7 @@ static double corrected_alpha(double a, double l)
 
 typedef struct {
     int64_t lists, pieces; /* per pixel: list sub-intervals entered before termination; pieces composited */
+    int64_t lists_ess;     /* those of the sub-intervals that lie partly in a non-empty grid cell */
 } ostat_t;
 
 /*
@@ -229,12 +230,27 @@ typedef struct {
  * touched_lists [H*W] / touched_S [NS*H*W] (optional) receive 1 for every list
  * entered before termination and every supersegment composited.
  */
+/* Whether the depth range [zlo, zhi] of list li holds any part of a non-empty
+ * grid cell (Section 4.3): a slice overlapping it with positive length whose
+ * count for li's column is non-zero.  A list sub-interval that fails this
+ * holds no supersegment, so empty-space skipping need not read the list. */
+static int in_nonempty_cell(const or_vdi_t *v, int px, int py, double zlo, double zhi)
+{
+    const int k = v->grid_k, GW = (v->W + k - 1) / k, GH = (v->H + k - 1) / k;
+    for (int c = 0; c < v->grid_nz; ++c) {
+        double s0 = v->grid_z[c], s1 = v->grid_z[c + 1];
+        int overlap = zhi > zlo ? (s0 < zhi && s1 > zlo) : (s0 <= zlo && zlo < s1);
+        if (overlap && v->grid[((size_t)c * GH + py / k) * GW + px / k] != 0) return 1;
+    }
+    return 0;
+}
+
 static void exact_pixel(const or_vdi_t *v, const ocam_t *cO, const ocam_t *cN, double xc, double yc, double *out,
-                        ostat_t *st, uint8_t *touched_lists, uint8_t *touched_S, double *ts, piece_t *pc,
-                        int32_t *sub_list, double *sub_t)
+                        ostat_t *st, uint8_t *touched_lists, uint8_t *touched_S, uint8_t *touched_ess, double *ts,
+                        piece_t *pc, int32_t *sub_list, double *sub_t, uint8_t *sub_need)
 {
     out[0] = out[1] = out[2] = out[3] = 0.0;
-    if (st) st->lists = st->pieces = 0;
+    if (st) st->lists = st->pieces = st->lists_ess = 0;
     oray_t r;
     if (!oray_setup(v, cO, cN, xc, yc, &r)) return;
     int nts = 0;
@@ -252,12 +268,13 @@ static void exact_pixel(const or_vdi_t *v, const ocam_t *cO, const ocam_t *cN, d
         double tm = 0.5 * (ta + tb);
         int px = list_col(v, ox(&r, tm)), py = list_row(v, oy(&r, tm));
         int li = py * v->W + px;
+        double za = oz(&r, ta), zb = oz(&r, tb);
         sub_list[nsub] = li;
         sub_t[nsub] = ta;
+        sub_need[nsub] = touched_ess ? (uint8_t)in_nonempty_cell(v, px, py, fmin(za, zb), fmax(za, zb)) : 0;
         ++nsub;
         int n = v->count[li];
         if (n == 0) continue;
-        double za = oz(&r, ta), zb = oz(&r, tb);
         double cth = list_cos(v, cO, px, py);
         for (int j = 0; j < n; ++j) {
             size_t o = (size_t)j * plane + li;
@@ -300,13 +317,17 @@ static void exact_pixel(const or_vdi_t *v, const ocam_t *cO, const ocam_t *cN, d
         if (T <= T_TERM) { tstop = pc[k].thi; break; }
     }
     out[0] = C[0]; out[1] = C[1]; out[2] = C[2]; out[3] = 1.0 - T;
-    int64_t nl = 0;
+    int64_t nl = 0, ne = 0;
     for (int s = 0; s < nsub; ++s)
         if (sub_t[s] < tstop) {
             ++nl;
             if (touched_lists) touched_lists[sub_list[s]] = 1;
+            if (touched_ess && sub_need[s]) {
+                touched_ess[sub_list[s]] = 1;
+                ++ne;
+            }
         }
-    if (st) { st->lists = nl; st->pieces = used; }
+    if (st) { st->lists = nl; st->pieces = used; st->lists_ess = ne; }
 }
 
 static int max_breaks(const or_vdi_t *v) { return v->W + v->H + v->grid_nz + 8; }
@@ -315,12 +336,16 @@ static int max_breaks(const or_vdi_t *v) { return v->W + v->H + v->grid_nz + 8; 
  * Exact render.  aspect <= 0 means W/H (a downsampled render passes the
  * display's).  If pix is NULL, renders all W*H pixels of V_N (row-major,
  * row 0 = bottom) into out[H*W*4]; else renders the npix pixel indices
- * (py*W + px) into out[npix*4].  stats (optional) [npix or W*H][2] = lists, pieces.
+ * (py*W + px) into out[npix*4].  stats (optional) [npix or W*H][3] = lists,
+ * pieces, lists in non-empty grid cells (the last only with touched_ess).
+ * touched_ess (optional, needs v->grid) marks the lists entered before
+ * termination over a sub-interval that lies partly in a non-empty grid cell.
  */
 int or_render_exact(const or_vdi_t *v, const float *camN, int W, int H, double aspect, int64_t npix,
                     const int64_t *pix, double *out, int64_t *stats, uint8_t *touched_lists, uint8_t *touched_S,
-                    int nthreads)
+                    uint8_t *touched_ess, int nthreads)
 {
+    if (touched_ess && !v->grid) return -1;
     ocam_t cO, cN;
     ocam_init(&cO, v->cam, v->W, v->H, 0.0);
     ocam_init(&cN, camN, W, H, aspect);
@@ -336,16 +361,17 @@ int or_render_exact(const or_vdi_t *v, const float *camN, int W, int H, double a
         piece_t *pc = (piece_t *)malloc(sizeof(piece_t) * maxp);
         int32_t *sl = (int32_t *)malloc(sizeof(int32_t) * nb);
         double *stt = (double *)malloc(sizeof(double) * nb);
+        uint8_t *need = (uint8_t *)malloc(nb);
 #pragma omp for schedule(dynamic, 64)
         for (int64_t k = 0; k < npix; ++k) {
             int64_t id = pix ? pix[k] : k;
             int px = (int)(id % W), py = (int)(id / W);
             ostat_t st;
             exact_pixel(v, &cO, &cN, -1.0 + (2.0 * px + 1.0) / W, -1.0 + (2.0 * py + 1.0) / H, out + 4 * k, &st,
-                        touched_lists, touched_S, ts, pc, sl, stt);
-            if (stats) { stats[2 * k] = st.lists; stats[2 * k + 1] = st.pieces; }
+                        touched_lists, touched_S, touched_ess, ts, pc, sl, stt, need);
+            if (stats) { stats[3 * k] = st.lists; stats[3 * k + 1] = st.pieces; stats[3 * k + 2] = st.lists_ess; }
         }
-        free(ts); free(pc); free(sl); free(stt);
+        free(ts); free(pc); free(sl); free(stt); free(need);
     }
     return 0;
 }
@@ -355,9 +381,27 @@ int or_render_exact(const or_vdi_t *v, const float *camN, int W, int H, double a
 /* ------------------------------------------------------------------ */
 static inline int near_int(double x, double tol) { return fabs(x - nearbyint(x)) <= tol; }
 
+/*
+ * Tie resolution.  A point sample that lies exactly on a list edge or a
+ * supersegment face, or a sample count whose ceil argument is an integer, is
+ * decided by rounding and may land on either side.  bias (optional, NULL =
+ * none) moves every such decision of the ray the same way: bias[0] and
+ * bias[1] in {-1, 0, +1} shift the sample's list coordinates by that many
+ * 1e-9 pixel in x and y, bias[2] its depth by that many 1e-11 relative before
+ * the face tests, bias[3] each ceil argument by that many 1e-10 relative.
+ * These shifts are far above FP64 rounding and far below the flag tolerances
+ * (1e-6 pixel, 1e-7 relative), so they change only flagged decisions; the
+ * flags are taken on the unshifted values.
+ */
+#define BIAS_PX 1e-9
+#define BIAS_Z 1e-11
+#define BIAS_N 1e-10
+
 static void preview_pixel(const or_vdi_t *v, const ocam_t *cO, const ocam_t *cN, double xc, double yc, double DR,
-                          double *out, uint8_t *flag, int64_t *nsamples, double *ts)
+                          const double *bias, double *out, uint8_t *flag, int64_t *nsamples, double *ts)
 {
+    const double bx = bias ? bias[0] : 0.0, by = bias ? bias[1] : 0.0;
+    const double bz = bias ? bias[2] : 0.0, bn = bias ? bias[3] : 0.0;
     out[0] = out[1] = out[2] = out[3] = 0.0;
     *flag = 0;
     *nsamples = 0;
@@ -390,7 +434,7 @@ static void preview_pixel(const or_vdi_t *v, const ocam_t *cO, const ocam_t *cN,
         double dz = (double)v->grid_z[cz + 1] - (double)v->grid_z[cz];
         double x = ((ub - ua) / dz) * ((double)G / (double)(k * k)) / DR;
         if (near_int(x, 1e-7 * fmax(1.0, x))) *flag = 1;
-        int64_t n = (int64_t)ceil(x);
+        int64_t n = (int64_t)ceil(x + bn * BIAS_N * fmax(1.0, x));
         if (n < 1) n = 1;
         double h = (ub - ua) / (double)n;
         for (int64_t q = 0; q < n; ++q) {
@@ -398,7 +442,9 @@ static void preview_pixel(const or_vdi_t *v, const ocam_t *cO, const ocam_t *cN,
             double xn = ox(&r, u), yn = oy(&r, u), z = oz(&r, u);
             double fx = (xn + 1.0) * v->W / 2.0, fy = (yn + 1.0) * v->H / 2.0;
             if (near_int(fx, 1e-6) || near_int(fy, 1e-6)) *flag = 1;
-            int px = clampi((int)floor(fx), 0, v->W - 1), py = clampi((int)floor(fy), 0, v->H - 1);
+            int px = clampi((int)floor(fx + bx * BIAS_PX), 0, v->W - 1);
+            int py = clampi((int)floor(fy + by * BIAS_PX), 0, v->H - 1);
+            double zs = z + bz * BIAS_Z * z;
             int li = py * v->W + px;
             int nl = v->count[li];
             ++*nsamples;
@@ -406,7 +452,7 @@ static void preview_pixel(const or_vdi_t *v, const ocam_t *cO, const ocam_t *cN,
                 size_t o = (size_t)j * plane + li;
                 double f = v->depth[2 * o], b = v->depth[2 * o + 1];
                 if (fabs(z - f) <= 1e-7 * z || fabs(z - b) <= 1e-7 * z) *flag = 1;
-                if (f <= z && z < b) {
+                if (f <= zs && zs < b) {
                     const float *c = v->rgba + 4 * o;
                     double L0 = (b - f) / list_cos(v, cO, px, py);
                     double at = corrected_alpha(c[3], h / L0);
@@ -425,10 +471,11 @@ done:
 /*
  * Along-ray subsampled render (D_R > 0) of a w x h image with V_N's camera
  * (aspect <= 0: w/h; a downsampled render passes the display's W/H).  pix / npix as in or_render_exact.  flags[npix] receive the
- * tie flags; nsamp[npix] (optional) the number of point samples taken.
+ * tie flags; nsamp[npix] (optional) the number of point samples taken; bias
+ * (optional, 4 values) resolves ties one way (see preview_pixel).
  */
 int or_render_preview(const or_vdi_t *v, const float *camN, int w, int h, double aspect, double DR, int64_t npix,
-                      const int64_t *pix, double *out, uint8_t *flags, int64_t *nsamp, int nthreads)
+                      const int64_t *pix, double *out, uint8_t *flags, int64_t *nsamp, const double *bias, int nthreads)
 {
     if (!(DR > 0.0) || !v->grid) return -1;
     ocam_t cO, cN;
@@ -447,8 +494,8 @@ int or_render_preview(const or_vdi_t *v, const float *camN, int w, int h, double
             int64_t id = pix ? pix[q] : q;
             int px = (int)(id % w), py = (int)(id / w);
             int64_t ns;
-            preview_pixel(v, &cO, &cN, -1.0 + (2.0 * px + 1.0) / w, -1.0 + (2.0 * py + 1.0) / h, DR, out + 4 * q,
-                          flags + q, &ns, ts);
+            preview_pixel(v, &cO, &cN, -1.0 + (2.0 * px + 1.0) / w, -1.0 + (2.0 * py + 1.0) / h, DR, bias,
+                          out + 4 * q, flags + q, &ns, ts);
             if (nsamp) nsamp[q] = ns;
         }
         free(ts);

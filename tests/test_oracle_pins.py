@@ -258,6 +258,70 @@ def test_preview_slab_on_slice_faces_is_exact_from_vo():
         assert np.abs(pv - ex).max() < 1e-9
 
 
+def test_preview_tie_variants_closed_form():
+    """Preview rays along list edges (Section 4.4 sampling rule, point
+    location on a tie): from V_O at half its resolution every pixel-centre ray
+    runs along the edge between list columns 2px and 2px+1 and rows 2py and
+    2py+1.  The lists alternate in opacity by column, and the slab's faces are
+    grid slice boundaries, so every sample of a ray lies in the slab and a
+    ray's exponents h / L0 sum to cos_i / cos_ray.  Resolving the ties
+    towards +x (+y) must give list column 2px+1 (row 2py+1) in closed form,
+    towards -x (-y) column 2px (row 2py); the unresolved oracle flags them."""
+    v = synth.slab_vdi(16, 16, [(1.0, 2.0, 1.0, (0.2, 0.6, 0.9))], half=4.0)
+    z = v.grid_z
+    v.depth[0, ..., 0] = z[10]
+    v.depth[0, ..., 1] = z[14]
+    cols = np.arange(16)
+    alpha = np.where(cols % 2 == 0, 0.6, 0.3).astype(np.float32)
+    rgb = np.where((cols % 2 == 0)[:, None], [[1.0, 0.0, 0.0]], [[0.0, 0.0, 1.0]]).astype(np.float32)
+    v.rgba[0, ..., 3] = alpha[None, :]
+    v.rgba[0, ..., :3] = rgb[None, :, :]
+    cam = v.camera
+    pix = np.arange(64)
+    _, flags = oracle.render_preview(v, cam, 8, 8, 0.5, pixels=pix)
+    assert flags.all()
+    var = oracle.preview_tie_variants(v, cam, 8, 8, 0.5, pix)
+    th = math.tan(math.radians(cam.fov_y_deg) / 2.0)
+    cos_i = synth.list_cos(cam, 16, 16)
+    for k, (bx, by, _, _) in enumerate(oracle.TIE_BIASES):
+        for q in pix:
+            px, py = q % 8, q // 8
+            xc, yc = -1.0 + (2 * px + 1) / 8.0, -1.0 + (2 * py + 1) / 8.0
+            cos_ray = 1.0 / math.sqrt(1.0 + (xc * th) ** 2 + (yc * th) ** 2)
+            col = 2 * px + (1 if bx > 0 else 0)
+            row = 2 * py + (1 if by > 0 else 0)
+            A = 1.0 - (1.0 - float(alpha[col])) ** (cos_i[row, col] / cos_ray)
+            want = np.concatenate([rgb[col] * A, [A]])
+            assert np.abs(var[k, q] - want).max() < 1e-9, (k, q)
+
+
+def test_preview_tie_variants_agree_off_ties(tiny):
+    """Resolving ties changes only the results the oracle flags."""
+    cam = inputs.orbit_camera(9.0)
+    pix = np.arange(48 * 32)
+    ref, flags = oracle.render_preview(tiny, cam, 48, 32, 2.0, pixels=pix)
+    var = oracle.preview_tie_variants(tiny, cam, 48, 32, 2.0, pix)
+    assert (flags == 0).mean() > 0.9
+    assert np.array_equal(var[:, flags == 0], np.broadcast_to(ref[flags == 0], var[:, flags == 0].shape))
+
+
+@pytest.mark.parametrize("theta", [0.0, 20.0, -45.0])
+def test_touched_lists_with_skipping_bounds(tiny, theta):
+    """The lists that empty-space skipping must still read (entered over a
+    part of the ray inside a non-empty grid cell, Section 4.3) lie between
+    the lists holding a composited supersegment and all lists entered."""
+    cam = inputs.orbit_camera(theta)
+    out, st, tl, ts, te = oracle.render_exact(tiny, cam, 96, 80, stats=True, touched=True, ess=True)
+    holds = ts.astype(bool).any(axis=0)
+    assert (te <= tl).all() and (holds <= te.astype(bool)).all()
+    assert (st[..., 2] <= st[..., 0]).all()
+    assert te.sum() < tl.sum() and holds.sum() < te.sum()
+    assert np.array_equal(out, oracle.render_exact(tiny, cam, 96, 80))
+    v = synth.empty_vdi(16, 16, 3)
+    _, _, tl0, _, te0 = oracle.render_exact(v, cam, 20, 20, stats=True, touched=True, ess=True)
+    assert tl0.sum() > 0 and te0.sum() == 0
+
+
 def test_upsample_identities():
     rng = np.random.default_rng(1)
     lo = rng.random((7, 9, 4))
@@ -280,6 +344,23 @@ def test_full_render_di1_dr0_is_exact(tiny):
     a, fl = oracle.render(tiny, cam, 40, 30, 1.0, 0.0)
     b = oracle.render_exact(tiny, cam, 40, 30)
     assert np.array_equal(a, b) and not fl.any()
+
+
+@pytest.mark.parametrize("d_i", [2.0, 3.0, 4.0])
+@pytest.mark.parametrize("d_r", [0.0, 2.0])
+def test_render_points_equals_full_render(tiny, d_i, d_r):
+    """The sampled-pixel form used for large frames (each output pixel's four
+    low-res texels rendered one by one, then combined bilinearly) equals the
+    whole-frame render followed by the upsampling pass, flags included."""
+    cam = inputs.orbit_camera(11.0)
+    W, H = 128, 96
+    full, fl = oracle.render(tiny, cam, W, H, d_i, d_r)
+    pix = np.random.default_rng(int(d_i * 10 + d_r)).choice(W * H, 2000, replace=False)
+    pix = np.concatenate([pix, [0, W - 1, (H - 1) * W, W * H - 1]])
+    pts, pfl = oracle.render_points(tiny, cam, W, H, d_i, d_r, pix)
+    assert np.abs(pts - full.reshape(-1, 4)[pix]).max() < 1e-12
+    assert np.array_equal(pfl, fl.reshape(-1)[pix])
+    assert (full[..., 3] > 0).mean() > 0.2
 
 
 def test_lowres_size():
