@@ -735,6 +735,11 @@ VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, in
 // ---------------------------------------------------------------------------
 // Preview: adaptive along-ray subsampling (Section 4.4)
 // ---------------------------------------------------------------------------
+// Shift, in V_O pixels, added to a preview sample's list coordinates: far
+// above the FP64 rounding of a coordinate (about 1e-12 pixel at 16384
+// lists) and far below any distance that decides a sample off a tie.
+constexpr double kTieShift = 1e-9;
+
 // Part `part` of `parts` of the preview ray through V_N pixel (px, py) of
 // the (low-res) grid: the samples of a contiguous block of the grid cells the
 // ray crosses, composited front to back from full transmittance.  The blocks
@@ -825,13 +830,20 @@ VDI_HD Accum trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, i
         int p = -1;
         const int max_iter = 4 * (WO + HO) / k + 4 * V.gnz + 64;
         // List of sample q of the current cell (its count is fetched one sample ahead).
+        // A sample on a list edge belongs to the list on its +x (+y) side,
+        // the half-open cell rule; the shift of kTieShift pixel keeps that
+        // decision the same for every such sample of a ray, where rounding
+        // alone would put them on either side (a ray lying in an edge plane,
+        // e.g. a downsampled view from the generating viewpoint).
         double h = 0.0;
         auto sample_list = [&](int q, double &u, double &z) -> uint64_t {
             u = t + (q + 0.5) * h;
             z = F.Z0 + u * r.Zp;
             const double iz = rcp64(z);
-            const int lx = min(max((int)floor(((F.X0 + u * r.Xp) * iz + 1.0) * (0.5 * WO)), 0), WO - 1);
-            const int ly = min(max((int)floor(((F.Y0 + u * r.Yp) * iz + 1.0) * (0.5 * HO)), 0), HO - 1);
+            const double fx = ((F.X0 + u * r.Xp) * iz + 1.0) * (0.5 * WO) + kTieShift;
+            const double fy = ((F.Y0 + u * r.Yp) * iz + 1.0) * (0.5 * HO) + kTieShift;
+            const int lx = min(max((int)floor(fx), 0), WO - 1);
+            const int ly = min(max((int)floor(fy), 0), HO - 1);
             return (uint64_t)ly * WO + lx;
         };
         // One flat loop: every step either enters the current grid cell (and,

@@ -19,3 +19,45 @@ def sample_pixels(width, height, n, seed=0):
 def psnr(a, b):
     mse = float(np.mean((np.asarray(a, np.float64) - np.asarray(b, np.float64)) ** 2))
     return float("inf") if mse == 0 else 10.0 * np.log10(1.0 / mse)
+
+
+def tie_aware_errors(img, ref, flags, variants):
+    """Per-pixel error of preview pixels: |img - ref| (max over RGBA) where
+    the oracle's result is unique (flags == 0); where it rests on ties, the
+    distance to the nearest of the valid results `variants`
+    [n_variants, n_flagged, 4] (oracle.preview_tie_variants of the flagged
+    pixels, in order).  Returns (errors [n], index of the nearest variant
+    per flagged pixel)."""
+    img = np.asarray(img, np.float64)
+    err = np.abs(img - ref).max(axis=1)
+    fl = np.flatnonzero(flags != 0)
+    if len(fl) == 0:
+        return err, np.zeros(0, np.int64)
+    d = np.abs(np.asarray(variants)[:, :, :] - img[fl][None]).max(axis=2)
+    err[fl] = d.min(axis=0)
+    return err, d.argmin(axis=0)
+
+
+def preview_errors(img_px, src, cam, w, h, d_r, pix, aspect=0.0, grid=None, rgba=None):
+    """Errors of a w x h along-ray subsampled render (D_I = 1 on that grid)
+    at pixel list `pix` (img_px [n, 4]) against the oracle, ties included:
+    unflagged pixels against the unique result, flagged ones against the
+    nearest consistent tie resolution.  Returns (errors [n], flags [n],
+    oracle values [n, 4])."""
+    import oracle
+    pix = np.asarray(pix, np.int64)
+    ref, flags = oracle.render_preview(src, cam, w, h, d_r, pixels=pix, aspect=aspect, grid=grid, rgba=rgba)
+    var = None
+    if flags.any():
+        var = oracle.preview_tie_variants(src, cam, w, h, d_r, pix[flags != 0], aspect=aspect, grid=grid, rgba=rgba)
+    err, _ = tie_aware_errors(img_px, ref, flags, var)
+    return err, flags, ref
+
+
+def nonempty_stratum(img, n, seed=0):
+    """Up to n row-major indices of pixels with positive alpha in img [H, W, 4]
+    (picks where to look; the expected values come from the oracle)."""
+    idx = np.flatnonzero(np.asarray(img)[..., 3].reshape(-1) > 0)
+    if len(idx) <= n:
+        return idx
+    return np.random.default_rng(seed).choice(idx, n, replace=False)

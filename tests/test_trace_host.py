@@ -15,7 +15,7 @@ import inputs
 import oracle
 from paper_2206_08660_amd import vdi as V
 from tests import synth
-from tests.gpu_util import TOL
+from tests.gpu_util import TOL, tie_aware_errors
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -98,3 +98,27 @@ def test_preview_split_rays(host, tiny, parts, theta):
     assert np.abs(img - ref)[ok].max() <= TOL
     # The blocks take the whole ray's samples; only rounding and early termination differ.
     assert np.abs(img - whole).max() <= 1e-5
+
+
+@pytest.mark.parametrize("d_i", [2, 4])
+def test_preview_ties_resolved_one_way(host, tiny, d_i):
+    """The downsampled preview from the generating viewpoint puts every
+    low-res pixel centre on a V_O list edge (128 / 64 = 2, 128 / 32 = 4), so
+    every sample of a ray is a tie.  The per-ray code must resolve them one
+    way along the ray: every pixel, flagged or not, equals the oracle's
+    unique result or one of its consistent tie resolutions."""
+    cam = inputs.orbit_camera(0.0)
+    w = h = 128 // d_i
+    pix = np.arange(w * h)
+    ref, flags = oracle.render_preview(tiny, cam, w, h, 2.0, pixels=pix)
+    var = oracle.preview_tie_variants(tiny, cam, w, h, 2.0, pix[flags != 0])
+    nonempty = ref[:, 3] > 0
+    assert (nonempty & (flags != 0)).sum() >= 100
+    for parts in (1, 2, 8):
+        img = render(host, tiny, cam, w, h, preview=True, d_r=2.0, parts=parts).reshape(-1, 4)
+        err, _ = tie_aware_errors(img, ref, flags, var)
+        assert err.max() <= TOL, (parts, err.max())
+        # The x and y list edges are resolved towards +x and +y.
+        pos = [k for k, b in enumerate(oracle.TIE_BIASES) if b[0] == 1 and b[1] == 1]
+        err_pos, _ = tie_aware_errors(img, ref, flags, var[pos])
+        assert err_pos.max() <= TOL, (parts, err_pos.max())
