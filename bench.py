@@ -326,7 +326,8 @@ def paced_leg(h, out, stream, np):
     frames at 5 deg, 120 at 40 deg and 80 at 5 deg with the target set to 85%
     of the 40-degree frame at full resolution."""
     import inputs
-    from paper_2206_08660_amd.pace import Pace, run_session
+    from paper_2206_08660_amd.pace import Pace
+    from tests.harness import run_session
     d_r = 2.0
     fixed = lambda d: Pace(1e6, d_i_min=d, d_i_max=d, d_i_start=d)
     plant = {}
@@ -612,8 +613,8 @@ def generation_leg(src, torch, V):
 
 def served_leg(torch, V):
     """The continuous-batching server against one request at a time."""
-    from paper_2206_08660_amd import serve
-    return serve.benchmark(log=log)
+    from tests import harness
+    return harness.serve_benchmark(log=log)
 
 
 def cpu_baseline_leg(src, cams, per, precision, np, torch, V):

@@ -1,12 +1,10 @@
 """Frame-time-paced preview rendering: binding of the vdi_pace_* calls of
 include/vdi.h (a PI controller on the image downsampling D_I, Section 4.4 /
-Section 5 of the paper) and a session loop that renders a camera path with it.
-The frame time fed back is the GPU time of each render (HIP events on the
-render stream)."""
+Section 5 of the paper)."""
 from __future__ import annotations
 
 import ctypes
-from typing import Optional, Sequence
+from typing import Optional
 
 from . import vdi as V
 
@@ -39,24 +37,3 @@ class Pace:
 
     def __exit__(self, *exc):
         self.close()
-
-
-def run_session(vdi: "V.Vdi", cams: Sequence, width: int, height: int, d_r: float, pace: Pace, out=None,
-                stream=None):
-    """Render cams in order with D_I from `pace`; returns [(D_I, frame_ms)] per frame."""
-    import torch
-    s = torch.cuda.current_stream() if stream is None else stream
-    if out is None:
-        out = torch.empty((height, width, 4), dtype=torch.float32, device="cuda")
-    log = []
-    for cam in cams:
-        d_i = pace.d_i
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(s)
-        vdi.render(cam, width, height, d_i, d_r, out=out, stream=s)
-        e1.record(s)
-        e1.synchronize()
-        ms = e0.elapsed_time(e1)
-        log.append((d_i, ms))
-        pace.update(ms)
-    return log

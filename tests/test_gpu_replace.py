@@ -11,6 +11,8 @@ import numpy as np
 import pytest
 
 import inputs
+import oracle
+from tests.gpu_util import TOL, nonempty_stratum, sample_pixels
 
 pytestmark = pytest.mark.gpu
 
@@ -60,9 +62,18 @@ def test_replace_swaps_only_when_complete():
         assert np.array_equal(_render(h, cam, 96, 80), want_a)
         _wait_swap(h)
         assert not h.replace_poll()
-        assert np.array_equal(_render(h, cam, 96, 80), want_b)
-        assert np.array_equal(_render(h, cam, 96, 80, d_i=2.0, d_r=1.0), want_b_prev)
+        after = _render(h, cam, 96, 80)
+        after_prev = _render(h, cam, 96, 80, d_i=2.0, d_r=1.0)
+        assert np.array_equal(after, want_b)
+        assert np.array_equal(after_prev, want_b_prev)
         assert np.array_equal(h.grid(), grid_b)
+        # The swapped-in VDI renders as the oracle renders b (Section 5: the
+        # client renders the newest VDI it holds).
+        assert np.abs(after - oracle.render_exact(b, cam, 96, 80)).max() <= TOL
+        ref, flags = oracle.render(b, cam, 96, 80, 2.0, 1.0)
+        ok = flags == 0
+        assert ok.mean() > 0.9 and (ok & (ref[..., 3] > 0)).sum() >= 1000
+        assert np.abs(after_prev - ref)[ok].max() <= TOL
         # Back to a: the second replacement writes into the buffers a used before.
         h.replace_begin(a)
         _wait_swap(h)
@@ -126,3 +137,9 @@ def test_rendering_continues_during_replacement():
             want = want_a if k < swapped_at else want_b
             assert np.array_equal(img, want), k
         assert swapped_at >= 1
+    # The last frame, from the swapped-in VDI, against the oracle on b.
+    last = frames[-1].reshape(-1, 4).astype(np.float64)
+    pix = np.unique(np.concatenate([sample_pixels(W, H, 3000, seed=5), nonempty_stratum(frames[-1], 1500, seed=5)]))
+    ref = oracle.render_exact(b, cam, W, H, pixels=pix)
+    assert np.abs(last[pix] - ref).max() <= TOL
+    assert (ref[:, 3] > 0).sum() >= 1000

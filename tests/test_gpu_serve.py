@@ -1,12 +1,15 @@
 """Served form through the C ABI (needs an MI355X): each request's image is
 the same alone (vdi_render) and in the mix of concurrently admitted
-requests; admission by budget and slots; completion of every request."""
+requests, and matches the FP64 oracle (fed the stored, rounded colours);
+admission by budget and slots; completion of every request."""
 import sys
 
 import numpy as np
 import pytest
 
 import inputs
+import oracle
+from tests.gpu_util import TOL, nonempty_stratum, preview_errors, sample_pixels
 
 pytestmark = pytest.mark.gpu
 
@@ -27,23 +30,48 @@ def _gpu():
 
 
 @pytest.fixture(scope="module")
-def handles():
+def sources():
+    return [inputs.load_workload("tiny"), inputs.load_workload("720p", keep_dvr=False)]
+
+
+@pytest.fixture(scope="module")
+def handles(sources):
     from paper_2206_08660_amd import vdi as V
-    srcs = [inputs.load_workload("tiny"), inputs.load_workload("720p", keep_dvr=False)]
-    hs = [V.Vdi(srcs[0]), V.Vdi(srcs[1], store="f16")]
+    hs = [V.Vdi(sources[0]), V.Vdi(sources[1], store="f16")]
     yield hs
     for h in hs:
         h.close()
 
 
-def test_mixed_requests_match_single_renders(handles):
+def oracle_check(src, rgba, cam, W, H, d_i, d_r, img, n=1500, seed=0):
+    """A served image against the oracle on sampled pixels (a stratum of them
+    non-empty).  Exact frames and D_I = 1 previews pixel by pixel (preview
+    ties against every consistent resolution); downsampled previews on the
+    pixels whose four low-res texels rest on no tie.  Returns the number of
+    non-empty pixels compared."""
+    img = img.reshape(-1, 4).astype(np.float64)
+    pix = np.unique(np.concatenate([sample_pixels(W, H, n, seed=seed),
+                                    nonempty_stratum(img.reshape(H, W, 4), n // 2, seed=seed)]))
+    if d_r > 0 and d_i == 1.0:
+        err, _, ref = preview_errors(img[pix], src, cam, W, H, d_r, pix, rgba=rgba)
+        ok = np.ones(len(pix), bool)
+    else:
+        ref, flags = oracle.render_points(src, cam, W, H, d_i, d_r, pix, rgba=rgba)
+        ok = flags == 0
+        err = np.abs(img[pix] - ref).max(axis=1)
+    assert ok.mean() > 0.9
+    assert err[ok].max() <= TOL, (d_i, d_r, float(err[ok].max()))
+    return int((ok & (ref[:, 3] > 0)).sum())
+
+
+def test_mixed_requests_match_single_renders(sources, handles):
     from paper_2206_08660_amd import serve
     rng = np.random.default_rng(3)
     reqs = []
     for i in range(48):
         hi = i % 2
-        W, H = [(128, 128), (96, 64), (1280, 720), (640, 360)][(i // 2) % 4] if hi else [(128, 128), (70, 44)][i % 2]
-        di, dr = [(1.0, 0.0), (2.0, 2.0), (1.0, 0.5), (4.0, 2.0)][i % 4]
+        W, H = [(128, 128), (96, 64), (1280, 720), (640, 360)][(i // 8) % 4] if hi else [(128, 128), (70, 44)][(i // 8) % 2]
+        di, dr = [(1.0, 0.0), (2.0, 2.0), (1.0, 0.5), (4.0, 2.0)][(i // 2) % 4]
         reqs.append((hi, float(rng.uniform(-30, 30)), W, H, di, dr))
     outs = [torch.full((H, W, 4), -1.0, dtype=torch.float32, device="cuda") for (_, _, W, H, _, _) in reqs]
     # The server writes with its own kernel: buffers must be ready before submission.
@@ -66,25 +94,42 @@ def test_mixed_requests_match_single_renders(handles):
         torch.cuda.synchronize()
         a, b = alone.cpu().numpy(), buf.cpu().numpy()
         assert np.array_equal(a, b), (hi, yaw, W, H, di, dr, np.abs(a - b).max())
+    # Every mode of the mix on both VDIs (the 720p one stores FP16 colour:
+    # the oracle gets the same rounded colours) against the oracle.
+    rgba = [None, oracle.dequant_f16(sources[1].rgba)]
+    checked = [0, 2, 4, 6, 17, 19, 21, 23]   # the four modes on each VDI, 1280 x 720 on the 720p one
+    assert len({reqs[i][0:1] + reqs[i][4:] for i in checked}) == 8
+    for i in checked:
+        hi, yaw, W, H, di, dr = reqs[i]
+        say(f"[gpu] served request {i} vs oracle: VDI {hi}, yaw {yaw:.1f}, {W}x{H}, D_I={di}, D_R={dr}")
+        ne = oracle_check(sources[hi], rgba[hi], inputs.orbit_camera(yaw), W, H, di, dr, outs[i].cpu().numpy(),
+                          seed=i)
+        assert ne >= (100 if hi == 0 else 1000), ne
 
 
 def test_admission_by_budget_and_slots(handles):
+    """Budget: a request that cannot fit beside one in flight is rejected.
+    The request in flight is a D_R = 0.01 preview of the 720p VDI at 40 deg
+    (50 samples per cell crossed for every 1 of D_R = 2), tens of ms on the
+    GPU against microseconds between the two submissions, so it is still in
+    flight when the second one arrives; once it is done the same request is
+    admitted."""
     from paper_2206_08660_amd import serve
     one = 1280 * 720 * 16
-    with serve.Server(2 * one + 100, max_inflight=8) as srv:
-        bufs = [torch.empty((720, 1280, 4), dtype=torch.float32, device="cuda") for _ in range(3)]
-        cam = inputs.orbit_camera(10.0)
-        t1 = srv.submit(handles[1], cam, 1280, 720, 1.0, 0.0, bufs[0])
-        t2 = srv.submit(handles[1], cam, 1280, 720, 1.0, 0.0, bufs[1])
-        assert t1 is not None and t2 is not None
-        # A third one does not fit the budget until the first two are done.
-        t3 = srv.submit(handles[1], cam, 1280, 720, 1.0, 0.0, bufs[2])
-        if t3 is None:
-            assert srv.stats()["rejected_budget"] >= 1
-            srv.drain()
-            t3 = srv.submit(handles[1], cam, 1280, 720, 1.0, 0.0, bufs[2])
-        assert t3 is not None
+    with serve.Server(one + one // 2, max_inflight=8) as srv:
+        bufs = [torch.empty((720, 1280, 4), dtype=torch.float32, device="cuda") for _ in range(2)]
+        torch.cuda.synchronize()
+        t1 = srv.submit(handles[1], inputs.orbit_camera(40.0), 1280, 720, 1.0, 0.01, bufs[0])
+        assert t1 is not None
+        t2 = srv.submit(handles[1], inputs.orbit_camera(10.0), 1280, 720, 1.0, 0.0, bufs[1])
+        assert t2 is None and not srv.poll(t1)
+        st = srv.stats()
+        assert st["rejected_budget"] == 1 and st["inflight"] == 1 and st["bytes_in_flight"] == one
         srv.drain()
+        t2 = srv.submit(handles[1], inputs.orbit_camera(10.0), 1280, 720, 1.0, 0.0, bufs[1])
+        assert t2 is not None
+        srv.drain()
+        assert srv.poll(t1) and srv.poll(t2) and srv.stats()["completed"] == 2
     with serve.Server(2 ** 34, max_inflight=1) as srv:
         b = [torch.empty((128, 128, 4), dtype=torch.float32, device="cuda") for _ in range(2)]
         t = srv.submit(handles[0], inputs.orbit_camera(5.0), 128, 128, 1.0, 0.0, b[0])
@@ -100,16 +145,23 @@ def test_admission_by_budget_and_slots(handles):
         assert st["peak_inflight"] == 0 and st["inflight"] == 0
 
 
-def test_open_loop_trace_small(handles):
-    """A short Poisson trace: every request completes and matches its single render."""
-    from paper_2206_08660_amd import serve
-    arrivals, which, yaw, outsel = serve.make_trace(60, 2000.0, seed=11, nvdi=2)
+def test_open_loop_trace_small(sources, handles):
+    """A short Poisson trace: every request completes and matches its single
+    render; the kept images match the oracle."""
+    from tests import harness
+    arrivals, which, yaw, outsel = harness.make_trace(60, 2000.0, seed=11, nvdi=2)
     bases = [0.0, 0.0]
     keep = (0, 17, 42, 59)
-    lat, makespan, stats, outs = serve.run_served(handles, bases, (arrivals, which, yaw, outsel), 2 ** 34, 32, keep=keep)
+    lat, makespan, stats, outs = harness.run_served(handles, bases, (arrivals, which, yaw, outsel), 2 ** 34, 32,
+                                                    keep=keep)
     assert sorted(outs) == list(keep) and (lat >= 0).all() and stats["completed"] == 60
     for i in keep:
-        W, H, di, dr = serve.OUTPUTS[int(outsel[i])]
-        alone = handles[int(which[i])].render(inputs.orbit_camera(float(yaw[i]), bases[int(which[i])]), W, H, di, dr)
+        W, H, di, dr = harness.OUTPUTS[int(outsel[i])]
+        cam = inputs.orbit_camera(float(yaw[i]), bases[int(which[i])])
+        alone = handles[int(which[i])].render(cam, W, H, di, dr)
         torch.cuda.synchronize()
-        assert np.array_equal(alone.cpu().numpy(), outs[i].cpu().numpy())
+        img = outs[i].cpu().numpy()
+        assert np.array_equal(alone.cpu().numpy(), img)
+        hi = int(which[i])
+        rgba = None if hi == 0 else oracle.dequant_f16(sources[1].rgba)
+        oracle_check(sources[hi], rgba, cam, W, H, di, dr, img, n=800, seed=i)
