@@ -9,6 +9,7 @@ definitions they implement):
   render_exact      exact raycast of a VDI from a new viewpoint (Sections 4.1-4.2, Eq. 2)
   render_preview    along-ray subsampled preview (Section 4.4) with tie flags
   preview_tie_variants   the preview's valid results where samples rest on ties
+  exact_tie_variants     the exact mode's valid results for rays along list edges
   render            full entry point: D_I image downsampling + bilinear upsampling
   count_grid        per-cell supersegment counts (Section 4.3)
   march             brute-force fine-step marching of the same field (a check, not the method)
@@ -55,7 +56,7 @@ def _load():
         P = ctypes.c_void_p
         I = ctypes.c_int
         I64 = ctypes.c_int64
-        lib.or_render_exact.argtypes = [P, P, I, I, ctypes.c_double, I64, P, P, P, P, P, P, I]
+        lib.or_render_exact.argtypes = [P, P, I, I, ctypes.c_double, I64, P, P, P, P, P, P, P, P, I]
         lib.or_render_preview.argtypes = [P, P, I, I, ctypes.c_double, ctypes.c_double, I64, P, P, P, P, P, I]
         lib.or_upsample.argtypes = [P, P, I, I, I, I, P, P]
         lib.or_upsample.restype = None
@@ -102,9 +103,13 @@ def threads() -> int:
 
 def render_exact(vdi, camera, width: int, height: int, pixels=None, rgba: Optional[np.ndarray] = None,
                  stats: bool = False, touched: bool = False, nthreads: int = 0, aspect: float = 0.0,
-                 ess: bool = False):
+                 ess: bool = False, flags: bool = False, bias=None):
     """Exact FP64 render.  Returns out [H, W, 4] (or [npix, 4] for a pixel
     list of row-major indices py*W+px), premultiplied RGB + alpha.
+    flags=True returns (out, flags u8) instead: pixels whose ray runs along a
+    list edge over part of its length, where either side is a valid reading
+    of the field; bias = (bx, by), each -1, 0 or +1, resolves every such tie
+    of a ray one way (None: by rounding).
     With stats=True also returns int64 [.., 2] = (lists entered, pieces
     composited), [.., 3] with ess=True (and lists entered over a part of
     the ray inside a non-empty grid cell); with touched=True also
@@ -122,8 +127,14 @@ def render_exact(vdi, camera, width: int, height: int, pixels=None, rgba: Option
     tl = np.zeros((vdi.height, vdi.width), dtype=np.uint8) if touched else None
     ts = np.zeros((vdi.ns, vdi.height, vdi.width), dtype=np.uint8) if touched else None
     te = np.zeros((vdi.height, vdi.width), dtype=np.uint8) if (touched or stats) and ess else None
+    fl = np.zeros(n, dtype=np.uint8) if flags else None
+    bb = None if bias is None else np.ascontiguousarray(bias, dtype=np.float64)
+    assert bb is None or (bb.shape == (2,) and np.isin(bb, (-1.0, 0.0, 1.0)).all())
+    assert not (flags and (stats or touched))
     lib.or_render_exact(ctypes.byref(b.c), _p(cam), width, height, float(aspect), n, _p(pix), _p(out), _p(st),
-                        _p(tl), _p(ts), _p(te), nthreads)
+                        _p(tl), _p(ts), _p(te), _p(fl), _p(bb), nthreads)
+    if flags:
+        return (out.reshape(height, width, 4), fl.reshape(height, width)) if pix is None else (out, fl)
     if st is not None and not ess:
         st = st[:, :2]
     if pix is None:
@@ -200,6 +211,18 @@ def preview_tie_variants(vdi, camera, w: int, h: int, d_r: float, pixels, grid: 
                                     aspect=aspect, bias=b)[0] for b in TIE_BIASES])
 
 
+EXACT_TIE_BIASES = [(bx, by) for bx in (-1, 1) for by in (-1, 1)]
+
+
+def exact_tie_variants(vdi, camera, w: int, h: int, pixels, rgba: Optional[np.ndarray] = None, nthreads: int = 0,
+                       aspect: float = 0.0) -> np.ndarray:
+    """The valid exact results of pixels whose rays run along list edges:
+    rendered once per way of resolving those ties consistently along the ray
+    (EXACT_TIE_BIASES, 4 ways).  Returns [4, npix, 4]."""
+    return np.stack([render_exact(vdi, camera, w, h, pixels=pixels, rgba=rgba, nthreads=nthreads, aspect=aspect,
+                                  flags=True, bias=b)[0] for b in EXACT_TIE_BIASES])
+
+
 def upsample(lo: np.ndarray, width: int, height: int, lo_flags: Optional[np.ndarray] = None):
     """Bilinear upsampling (half-pixel centres, clamped) of lo [h, w, 4]."""
     lo = np.ascontiguousarray(lo, dtype=np.float64)
@@ -222,8 +245,7 @@ def render(vdi, camera, width: int, height: int, d_i: float = 1.0, d_r: float = 
     if d_r > 0.0:
         lo, fl = render_preview(vdi, camera, w, h, d_r, rgba=rgba, nthreads=nthreads, aspect=aspect)
     else:
-        lo = render_exact(vdi, camera, w, h, rgba=rgba, nthreads=nthreads, aspect=aspect)
-        fl = np.zeros((h, w), dtype=np.uint8)
+        lo, fl = render_exact(vdi, camera, w, h, rgba=rgba, nthreads=nthreads, aspect=aspect, flags=True)
     if (w, h) == (width, height):
         return lo, fl
     return upsample(lo, width, height, fl)
@@ -282,8 +304,7 @@ def render_points(vdi, camera, width: int, height: int, d_i: float, d_r: float, 
     def lo_render(pix):
         if d_r > 0.0:
             return render_preview(vdi, camera, w, h, d_r, pixels=pix, rgba=rgba, nthreads=nthreads, aspect=aspect)
-        return render_exact(vdi, camera, w, h, pixels=pix, rgba=rgba, nthreads=nthreads, aspect=aspect), \
-            np.zeros(len(pix), np.uint8)
+        return render_exact(vdi, camera, w, h, pixels=pix, rgba=rgba, nthreads=nthreads, aspect=aspect, flags=True)
 
     if (w, h) == (width, height):
         return lo_render(pixels)

@@ -245,11 +245,32 @@ static int in_nonempty_cell(const or_vdi_t *v, int px, int py, double zlo, doubl
     return 0;
 }
 
-static void exact_pixel(const or_vdi_t *v, const ocam_t *cO, const ocam_t *cN, double xc, double yc, double *out,
-                        ostat_t *st, uint8_t *touched_lists, uint8_t *touched_S, uint8_t *touched_ess, double *ts,
-                        piece_t *pc, int32_t *sub_list, double *sub_t, uint8_t *sub_need)
+/*
+ * Ties in exact mode.  A ray that lies in a list-edge plane over a part of its
+ * length (e.g. a pixel-centre ray of a downsampled grid seen from V_O itself,
+ * which runs along the corner of four lists) has no unique list there: either
+ * side is a valid reading of the field.  The list of each sub-interval is
+ * located at its midpoint; bx, by in {-1, 0, +1} shift that location by that
+ * many BIAS_PX pixel, so every such decision of the ray goes the same way.
+ * *flag is set when the ray runs along an edge plane (its list coordinate in
+ * x or y varies by at most 2e-6 pixel over the clipped ray) and a
+ * sub-interval of positive length has both ends within 1e-6 pixel of an edge.
+ */
+#define BIAS_PX 1e-9
+
+/* Both ends of a sub-interval within 1e-6 pixel of one list edge. */
+static int on_edge(double fa, double fb)
+{
+    return fabs(fa - nearbyint(fa)) <= 1e-6 && fabs(fb - nearbyint(fb)) <= 1e-6 && nearbyint(fa) == nearbyint(fb);
+}
+
+static void exact_pixel(const or_vdi_t *v, const ocam_t *cO, const ocam_t *cN, double xc, double yc, double bx,
+                        double by, double *out, uint8_t *flag, ostat_t *st, uint8_t *touched_lists,
+                        uint8_t *touched_S, uint8_t *touched_ess, double *ts, piece_t *pc, int32_t *sub_list,
+                        double *sub_t, uint8_t *sub_need)
 {
     out[0] = out[1] = out[2] = out[3] = 0.0;
+    if (flag) *flag = 0;
     if (st) st->lists = st->pieces = st->lists_ess = 0;
     oray_t r;
     if (!oray_setup(v, cO, cN, xc, yc, &r)) return;
@@ -259,6 +280,10 @@ static void exact_pixel(const or_vdi_t *v, const ocam_t *cO, const ocam_t *cN, d
     nts = add_crossings(&r, 0, v->W, 1, ts, nts);
     nts = add_crossings(&r, 1, v->H, 1, ts, nts);
     qsort(ts, nts, sizeof(double), cmp_dbl);
+    /* The ray runs along a list-edge plane (x or y) when its list coordinate
+     * varies by at most 2e-6 pixel over the whole clipped ray. */
+    const int along_x = fabs(ox(&r, r.t1) - ox(&r, r.t0)) * v->W / 2.0 <= 2e-6;
+    const int along_y = fabs(oy(&r, r.t1) - oy(&r, r.t0)) * v->H / 2.0 <= 2e-6;
     const size_t plane = (size_t)v->W * v->H;
     int np = 0, nsub = 0;
     const int zflat = fabs(r.Zp) < 1e-12;
@@ -266,7 +291,11 @@ static void exact_pixel(const or_vdi_t *v, const ocam_t *cO, const ocam_t *cN, d
         double ta = ts[s], tb = ts[s + 1];
         if (!(tb > ta)) continue;
         double tm = 0.5 * (ta + tb);
-        int px = list_col(v, ox(&r, tm)), py = list_row(v, oy(&r, tm));
+        if (flag && ((along_x && on_edge((ox(&r, ta) + 1.0) * v->W / 2.0, (ox(&r, tb) + 1.0) * v->W / 2.0)) ||
+                     (along_y && on_edge((oy(&r, ta) + 1.0) * v->H / 2.0, (oy(&r, tb) + 1.0) * v->H / 2.0))))
+            *flag = 1;
+        int px = clampi((int)floor((ox(&r, tm) + 1.0) * v->W / 2.0 + bx * BIAS_PX), 0, v->W - 1);
+        int py = clampi((int)floor((oy(&r, tm) + 1.0) * v->H / 2.0 + by * BIAS_PX), 0, v->H - 1);
         int li = py * v->W + px;
         double za = oz(&r, ta), zb = oz(&r, tb);
         sub_list[nsub] = li;
@@ -343,7 +372,7 @@ static int max_breaks(const or_vdi_t *v) { return v->W + v->H + v->grid_nz + 8; 
  */
 int or_render_exact(const or_vdi_t *v, const float *camN, int W, int H, double aspect, int64_t npix,
                     const int64_t *pix, double *out, int64_t *stats, uint8_t *touched_lists, uint8_t *touched_S,
-                    uint8_t *touched_ess, int nthreads)
+                    uint8_t *touched_ess, uint8_t *flags, const double *bias, int nthreads)
 {
     if (touched_ess && !v->grid) return -1;
     ocam_t cO, cN;
@@ -367,7 +396,8 @@ int or_render_exact(const or_vdi_t *v, const float *camN, int W, int H, double a
             int64_t id = pix ? pix[k] : k;
             int px = (int)(id % W), py = (int)(id / W);
             ostat_t st;
-            exact_pixel(v, &cO, &cN, -1.0 + (2.0 * px + 1.0) / W, -1.0 + (2.0 * py + 1.0) / H, out + 4 * k, &st,
+            exact_pixel(v, &cO, &cN, -1.0 + (2.0 * px + 1.0) / W, -1.0 + (2.0 * py + 1.0) / H,
+                        bias ? bias[0] : 0.0, bias ? bias[1] : 0.0, out + 4 * k, flags ? flags + k : NULL, &st,
                         touched_lists, touched_S, touched_ess, ts, pc, sl, stt, need);
             if (stats) { stats[3 * k] = st.lists; stats[3 * k + 1] = st.pieces; stats[3 * k + 2] = st.lists_ess; }
         }
@@ -393,7 +423,6 @@ static inline int near_int(double x, double tol) { return fabs(x - nearbyint(x))
  * (1e-6 pixel, 1e-7 relative), so they change only flagged decisions; the
  * flags are taken on the unshifted values.
  */
-#define BIAS_PX 1e-9
 #define BIAS_Z 1e-11
 #define BIAS_N 1e-10
 

@@ -54,6 +54,22 @@ def preview_errors(img_px, src, cam, w, h, d_r, pix, aspect=0.0, grid=None, rgba
     return err, flags, ref
 
 
+def exact_errors(img_px, src, cam, w, h, pix, aspect=0.0, rgba=None):
+    """Errors of an exact w x h render at pixel list `pix` (img_px [n, 4])
+    against the oracle: rays off list edges against the unique result, rays
+    running along a list edge (oracle flag) against the nearest of its four
+    consistent tie resolutions.  Returns (errors [n], flags [n], oracle
+    values [n, 4])."""
+    import oracle
+    pix = np.asarray(pix, np.int64)
+    ref, flags = oracle.render_exact(src, cam, w, h, pixels=pix, aspect=aspect, rgba=rgba, flags=True)
+    var = None
+    if flags.any():
+        var = oracle.exact_tie_variants(src, cam, w, h, pix[flags != 0], aspect=aspect, rgba=rgba)
+    err, _ = tie_aware_errors(img_px, ref, flags, var)
+    return err, flags, ref
+
+
 def nonempty_stratum(img, n, seed=0):
     """Up to n row-major indices of pixels with positive alpha in img [H, W, 4]
     (picks where to look; the expected values come from the oracle)."""

@@ -295,6 +295,57 @@ def test_preview_tie_variants_closed_form():
             assert np.abs(var[k, q] - want).max() < 1e-9, (k, q)
 
 
+def test_exact_tie_variants_closed_form():
+    """Exact rays along list edges (Sections 4.1-4.2; the field is ambiguous
+    on an edge): from V_O at half its resolution every pixel-centre ray runs
+    along the corner of list columns 2px, 2px+1 and rows 2py, 2py+1 and stays
+    there.  With lists alternating in opacity by column, resolving the ties
+    towards +x (+y) must give column 2px+1 (row 2py+1) alone, in closed form
+    (Eq. 2 with l = cos_i / cos_ray through the slab), towards -x (-y) column
+    2px (row 2py); the unresolved oracle flags every such ray."""
+    v = synth.slab_vdi(16, 16, [(1.0, 2.0, 1.0, (0.2, 0.6, 0.9))], half=4.0)
+    cols = np.arange(16)
+    alpha = np.where(cols % 2 == 0, 0.6, 0.3).astype(np.float32)
+    rgb = np.where((cols % 2 == 0)[:, None], [[1.0, 0.0, 0.0]], [[0.0, 0.0, 1.0]]).astype(np.float32)
+    v.rgba[0, ..., 3] = alpha[None, :]
+    v.rgba[0, ..., :3] = rgb[None, :, :]
+    cam = v.camera
+    pix = np.arange(64)
+    _, flags = oracle.render_exact(v, cam, 8, 8, pixels=pix, flags=True)
+    assert flags.all()
+    var = oracle.exact_tie_variants(v, cam, 8, 8, pix)
+    th = math.tan(math.radians(cam.fov_y_deg) / 2.0)
+    cos_i = synth.list_cos(cam, 16, 16)
+    for k, (bx, by) in enumerate(oracle.EXACT_TIE_BIASES):
+        for q in pix:
+            px, py = q % 8, q // 8
+            xc, yc = -1.0 + (2 * px + 1) / 8.0, -1.0 + (2 * py + 1) / 8.0
+            cos_ray = 1.0 / math.sqrt(1.0 + (xc * th) ** 2 + (yc * th) ** 2)
+            col = 2 * px + (1 if bx > 0 else 0)
+            row = 2 * py + (1 if by > 0 else 0)
+            A = 1.0 - (1.0 - float(alpha[col])) ** (cos_i[row, col] / cos_ray)
+            want = np.concatenate([rgb[col] * A, [A]])
+            assert np.abs(var[k, q] - want).max() < 1e-9, (k, q)
+
+
+@pytest.mark.parametrize("theta", [9.0, -31.0])
+def test_exact_tie_variants_agree_off_ties(tiny, theta):
+    """Off list edges the exact result is unique: no ray of a rotated view at
+    an even height is flagged and every resolution gives the unresolved
+    result.  At an odd height the middle row lies in V_O's plane y = 0, a
+    list-row edge of the 128-row VDI: exactly that row is flagged."""
+    cam = inputs.orbit_camera(theta)
+    pix = np.arange(48 * 32)
+    ref, flags = oracle.render_exact(tiny, cam, 48, 32, pixels=pix, flags=True)
+    assert not flags.any()
+    var = oracle.exact_tie_variants(tiny, cam, 48, 32, pix)
+    assert np.array_equal(var, np.broadcast_to(ref, var.shape))
+    img, fl = oracle.render_exact(tiny, cam, 63, 63, flags=True)
+    hit = img[..., 3] > 0
+    assert not fl[np.arange(63) != 31].any()
+    assert fl[31][hit[31]].all()
+
+
 def test_preview_tie_variants_agree_off_ties(tiny):
     """Resolving ties changes only the results the oracle flags."""
     cam = inputs.orbit_camera(9.0)
