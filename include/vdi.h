@@ -161,6 +161,27 @@ int vdi_create(const vdi_desc *desc, vdi_t *out);
 int vdi_render(vdi_t v, const vdi_camera *cam_VN, int32_t width, int32_t height, float D_I, float D_R,
                float *out_rgba, void *hip_stream);
 
+/*
+ * vdi_render for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, kernels and image as vdi_render (bit for bit), but it calls no
+ * hipMalloc, hipFree or pool allocation: the low-res image of a downsampled
+ * render (D_I > 1) is kept in a static device array of the library,
+ * VDI_NOALLOC_SCRATCH_TEXELS float4 texels (32 MiB), one copy per device,
+ * held until the process ends.  The caller still owns out_rgba.
+ * Every call on one device shares that device's array: calls that overlap on
+ * one device (other streams or threads, without ordering between them) race
+ * on it and give undefined images; calls on one stream are ordered and safe.
+ * The first call on a device looks the array's device address up
+ * (hipGetSymbolAddress).
+ * Errors: those of vdi_render, and VDI_ERR_ARG when the low-res image,
+ * round(width/D_I) x round(height/D_I), exceeds VDI_NOALLOC_SCRATCH_TEXELS
+ * (1920 x 1080 at any D_I > 1 fits).
+ */
+#define VDI_NOALLOC_SCRATCH_TEXELS (1u << 21)
+int vdi_render_noalloc(vdi_t v, const vdi_camera *cam_VN, int32_t width, int32_t height, float D_I, float D_R,
+                       float *out_rgba, void *hip_stream);
+
 /* vdi_render with explicit options (opts NULL = defaults: ESS on, window search). */
 int vdi_render_ex(vdi_t v, const vdi_camera *cam_VN, int32_t width, int32_t height, float D_I, float D_R,
                   const vdi_render_opts *opts, float *out_rgba, void *hip_stream);

@@ -187,14 +187,47 @@ hipError_t scratch_pool(int device, hipMemPool_t *out)
     return hipSuccess;
 }
 
-// Renders into `out` (W x H); uses stream-ordered scratch for D_I > 1.
+// Allocation-free downsampled renders (vdi_render_noalloc) keep their
+// low-res image in this library-owned array, one copy per device, held until
+// the process ends.  In host code `scratch` names a host-side stand-in, not
+// device memory: its device address on each device comes from
+// hipGetSymbolAddress (noalloc_scratch), and only that address is passed on.
+constexpr size_t kNoAllocTexels = VDI_NOALLOC_SCRATCH_TEXELS;  // 32 MiB of float4
+static __device__ __align__(256) float4 scratch[kNoAllocTexels];
+
+// Device address of `scratch` on `device` (current), looked up once per device.
+hipError_t noalloc_scratch(int device, float4 **out)
+{
+    static std::mutex mu;
+    static std::vector<float4 *> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (device < 0) return hipErrorInvalidDevice;
+    if ((int)addr.size() <= device) addr.resize(device + 1, nullptr);
+    if (!addr[device]) {
+        float4 *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[device] = p;
+    }
+    *out = addr[device];
+    return hipSuccess;
+}
+
+// Renders into `out` (W x H).  For D_I > 1 the low-res image goes to
+// stream-ordered scratch from the library's pool, or, with noalloc, to the
+// library's static array (no allocation of any kind).
 int render_impl(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, float D_I, float D_R,
-                const vdi_render_opts *opts, float *out, hipStream_t s)
+                const vdi_render_opts *opts, float *out, hipStream_t s, bool noalloc = false)
 {
     int rc = check_args(v, cam, W, H, D_I, D_R, out);
     if (rc) return rc;
     int32_t w, h;
     lowres_dims(W, H, D_I, &w, &h);
+    const bool down = (w != W || h != H);
+    if (noalloc && down && (size_t)w * (size_t)h > kNoAllocTexels)
+        return fail(VDI_ERR_ARG, "low-res image %dx%d exceeds the allocation-free scratch (%zu texels)", w, h,
+                    kNoAllocTexels);
     const vdi::VdiSet S = vdi::current(v);
     vdi::Frame f;
     rc = build_frame(S, *cam, w, h, (double)W / (double)H, f);
@@ -202,9 +235,10 @@ int render_impl(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, float D_I,
     rc = check_opts(opts, f);
     if (rc) return rc;
     HIP_OR_FAIL(hipSetDevice(v->device), "hipSetDevice");
-    const bool down = (w != W || h != H);
     float4 *lo = nullptr;
-    if (down) {
+    if (down && noalloc) {
+        HIP_OR_FAIL(noalloc_scratch(v->device, &lo), "hipGetSymbolAddress(scratch)");
+    } else if (down) {
         hipMemPool_t pool = nullptr;
         HIP_OR_FAIL(scratch_pool(v->device, &pool), "scratch pool");
         // Sizes rounded up to a power of two (at least 1 MiB): a D_I that
@@ -217,7 +251,7 @@ int render_impl(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, float D_I,
     f.DR = D_R;
     hipError_t e = D_R > 0.0f ? vdi::launch_render_preview(S.dev, f, s) : vdi::launch_render_exact(S.dev, f, false, s);
     if (e == hipSuccess && down) e = vdi::launch_upsample(lo, w, h, reinterpret_cast<float4 *>(out), W, H, s);
-    if (down) {
+    if (down && !noalloc) {
         hipError_t e2 = hipFreeAsync(lo, s);
         if (e == hipSuccess) e = e2;
     }
@@ -655,6 +689,12 @@ int vdi_render(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, float D_I, 
 {
     g_err.clear();
     return render_impl(v, cam, W, H, D_I, D_R, nullptr, out, static_cast<hipStream_t>(stream));
+}
+
+int vdi_render_noalloc(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, float D_I, float D_R, float *out,
+                       void *stream)
+{
+    return render_impl(v, cam, W, H, D_I, D_R, nullptr, out, static_cast<hipStream_t>(stream), true);
 }
 
 int vdi_render_ex(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, float D_I, float D_R,

@@ -31,7 +31,7 @@ EXPORTS = ("vdi_create", "vdi_render", "vdi_render_ex", "vdi_render_counters", "
            "vdi_server_submit", "vdi_server_poll", "vdi_server_drain", "vdi_server_get_stats",
            "vdi_server_reset_stats", "vdi_server_destroy", "vdi_replace_begin", "vdi_replace_poll",
            "vdi_pace_create", "vdi_pace_update", "vdi_pace_destroy", "vdi_generate", "vdi_dvr",
-           "vdi_image_quality")
+           "vdi_image_quality", "vdi_render_noalloc")
 
 VOXEL = {"f32": 0, "u16": 1}
 TF = {"ramp": 0, "knots4": 1}
@@ -106,6 +106,7 @@ def lib() -> ctypes.CDLL:
         P, I32, F = ctypes.c_void_p, ctypes.c_int32, ctypes.c_float
         L.vdi_create.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(P)]
         L.vdi_render.argtypes = [P, ctypes.POINTER(Camera), I32, I32, F, F, P, P]
+        L.vdi_render_noalloc.argtypes = [P, ctypes.POINTER(Camera), I32, I32, F, F, P, P]
         L.vdi_render_ex.argtypes = [P, ctypes.POINTER(Camera), I32, I32, F, F, ctypes.POINTER(Opts), P, P]
         L.vdi_render_counters.argtypes = [P, ctypes.POINTER(Camera), I32, I32, ctypes.POINTER(Opts), P, P, P, P, P]
         L.vdi_get_grid.argtypes = [P, P, ctypes.c_size_t]
@@ -282,6 +283,21 @@ class Vdi:
         o = _opts(ess, search)
         _check(lib().vdi_render_ex(self.handle, ctypes.byref(c), width, height, d_i, d_r, ctypes.byref(o),
                                    ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+        return out
+
+    def render_noalloc(self, cam, width: int, height: int, d_i: float = 1.0, d_r: float = 0.0, out=None,
+                       stream=None):
+        """vdi_render_noalloc: the vdi_render image, with the low-res image of a
+        downsampled render in the library's static device scratch (no device
+        allocation by the library).  `out` as in render()."""
+        import torch
+        if out is None:
+            out = torch.empty((height, width, 4), dtype=torch.float32, device="cuda")
+        if out.dtype != torch.float32 or not out.is_cuda or not out.is_contiguous() or out.numel() < height * width * 4:
+            raise ValueError("out must be a contiguous float32 CUDA tensor with height*width*4 elements")
+        c = camera(cam)
+        _check(lib().vdi_render_noalloc(self.handle, ctypes.byref(c), width, height, d_i, d_r,
+                                        ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
         return out
 
     def render_counters(self, cam, width: int, height: int, ess: bool = False, search: str = "window",
