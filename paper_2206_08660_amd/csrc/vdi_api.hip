@@ -394,7 +394,7 @@ uint64_t set_bytes_of(const vdi_desc *d)
     const uint64_t colour = d->rgba_fmt_store == VDI_F32 ? 16 : 8;
     const uint64_t gw = (d->width + d->grid_k - 1) / d->grid_k, gh = (d->height + d->grid_k - 1) / d->grid_k;
     const uint64_t cells = (uint64_t)d->grid_nz * gw * gh;
-    return plane + vdi::plane_elems(plane, d->max_supersegments) * (8 + colour) + cells * sizeof(uint32_t) +
+    return plane + vdi::plane_elems(d->width, d->height, d->max_supersegments) * (8 + colour) + cells * sizeof(uint32_t) +
            (cells + 31) / 32 * sizeof(uint32_t) + (uint64_t)(d->grid_nz + 1) * sizeof(float);
 }
 
@@ -428,7 +428,7 @@ hipError_t upload_set(vdi::VdiSet &S, const vdi_desc *d, const uint8_t *counts, 
     S.cam_o = d->camera_VO;
     memcpy(S.bmin, d->aabb_min, sizeof S.bmin);
     memcpy(S.bmax, d->aabb_max, sizeof S.bmax);
-    const uint64_t elems = vdi::plane_elems(plane, (int)ns);
+    const uint64_t elems = vdi::plane_elems(d->width, d->height, (int)ns);
     const size_t grid_bytes = (size_t)D.gnz * D.GH * D.GW * sizeof(uint32_t);
     const size_t gbits_bytes = ((size_t)D.gnz * D.GH * D.GW + 31) / 32 * sizeof(uint32_t);
     hipError_t e = hipSuccess;
@@ -517,7 +517,7 @@ uint64_t vdi_plane_bytes(int32_t width, int32_t height, int32_t n_s, int32_t fmt
     if (width < 1 || height < 1 || n_s < 1) return 0;
     const uint64_t plane = (uint64_t)width * height;
     const uint64_t colour = fmt == VDI_F32 ? 16 : 8;
-    return plane + vdi::plane_elems(plane, n_s) * (8 + colour);
+    return plane + vdi::plane_elems(width, height, n_s) * (8 + colour);
 }
 
 struct vdi_pace_s {

@@ -22,6 +22,17 @@ constexpr double kFlatZ = 1e-12;
 #endif
 constexpr int kTileW = 64;
 constexpr int kTileH = VDI_TILE_H;
+// Exact renders use square tiles of kXTileW x kXTileH rays (one wavefront).
+// Rays of vertically neighbouring pixels cross the same column of V_O lists
+// in step, one list row apart and at nearly the same depth, where
+// horizontal neighbours walk the same row of lists a list apart in time:
+// an 8 x 8 tile keeps each column of 8 lanes in step (a 64 x 1 row tile:
+// 17% slower on the 1080p sweep, 16 x 4: 4%, 4 x 16: 1%).
+#ifndef VDI_EXACT_TW
+#define VDI_EXACT_TW 8
+#endif
+constexpr int kXTileW = VDI_EXACT_TW;
+constexpr int kXTileH = 64 / VDI_EXACT_TW;
 constexpr int kXcds = 8;
 
 // Preview rays are split over `parts` adjacent lanes when there are few of
@@ -39,36 +50,64 @@ __host__ __device__ inline int preview_parts(int w, int h)
     while (p < 8 && rays * p < VDI_PREVIEW_LANES) p <<= 1;
     return p;
 }
+// A preview wavefront renders a tile of 64 / parts rays, at most
+// kPreviewTileH rows tall (the rays of a tile column cross neighbouring
+// lists in step, as in exact tiles); the `parts` lanes of a ray are adjacent.
+#ifndef VDI_PREVIEW_TH
+#define VDI_PREVIEW_TH 8
+#endif
+__host__ __device__ inline void preview_tile_dims(int parts, int &tw, int &th)
+{
+    const int rays = kTileW * kTileH / parts;
+    th = rays < VDI_PREVIEW_TH ? rays : VDI_PREVIEW_TH;
+    tw = rays / th;
+}
 // Workgroups (one wavefront each) of a preview launch over a w x h ray grid.
 __host__ __device__ inline uint32_t preview_tiles(int w, int h)
 {
-    const int tw = kTileW / preview_parts(w, h);
-    return (uint32_t)(((w + tw - 1) / tw) * ((h + kTileH - 1) / kTileH));
+    int tw, th;
+    preview_tile_dims(preview_parts(w, h), tw, th);
+    return (uint32_t)(((w + tw - 1) / tw) * ((h + th - 1) / th));
 }
 
-// Storage order of the depth and colour planes on the device.  Lists, taken
-// in row-major order, are grouped in bricks of kBrick; a brick stores slot 0
-// of its lists, then slot 1, and so on.  Slot j of list li is element
-// list_base(li) + j * kBrick, and a 128-byte line holds a few slots of a few
-// horizontally adjacent lists: the supersegments a ray meets next, whether it
-// runs along the list or across neighbouring lists.  kBrick = 0 keeps whole
-// slot planes (element j * WO * HO + li), the order of the input.
+// Storage order of the depth and colour planes on the device.  Lists are
+// grouped in bricks of kBrickW x kBrickH neighbouring lists (2 x 2); a brick
+// stores slot 0 of its lists, then slot 1, and so on.  Slot j of list
+// (ix, iy) is element list_base_xy(ix, iy) + j * kBrick, and a 128-byte line
+// holds four slots of depth pairs (two of colours) of a 2 x 2 block of
+// lists: the supersegments a ray meets next whether it runs along its list or
+// across neighbouring lists, and those the lanes of a tile column, which
+// cross vertically neighbouring lists in step, read together.  kBrick = 0
+// keeps whole slot planes (element j * WO * HO + li), the order of the input.
 #ifndef VDI_BRICK
 #define VDI_BRICK 4
 #endif
 constexpr int kBrick = VDI_BRICK;
-static_assert(kBrick == 0 || (kBrick & (kBrick - 1)) == 0, "brick width must be a power of two");
+static_assert(kBrick == 0 || (kBrick & (kBrick - 1)) == 0, "bricks must hold a power of two of lists");
 
-__host__ __device__ inline uint64_t list_base(uint64_t li, int NS)
+#ifndef VDI_BRICK_W
+#define VDI_BRICK_W 2
+#endif
+constexpr int kBrickW = kBrick == 0 ? 1 : VDI_BRICK_W;
+constexpr int kBrickH = kBrick == 0 ? 1 : kBrick / kBrickW;
+
+// Storage offset of slot 0 of list (ix, iy) of a WO-wide list grid.
+__host__ __device__ inline uint64_t list_base_xy(int ix, int iy, int NS, int WO)
 {
-    if constexpr (kBrick == 0) return li;
-    return (li / kBrick) * ((uint64_t)NS * kBrick) + li % kBrick;
+    if constexpr (kBrick == 0) return (uint64_t)iy * WO + ix;
+    const uint32_t bw = (uint32_t)(WO + kBrickW - 1) / kBrickW;
+    const uint64_t brick = (uint64_t)((uint32_t)iy / kBrickH) * bw + (uint32_t)ix / kBrickW;
+    return brick * ((uint64_t)NS * kBrick) + ((uint32_t)iy % kBrickH) * kBrickW + (uint32_t)ix % kBrickW;
 }
-// Elements of one plane set (count of lists rounded up to whole bricks, times NS).
-__host__ __device__ inline uint64_t plane_elems(uint64_t lists, int NS)
+__host__ __device__ inline uint64_t list_base(uint64_t li, int NS, int WO)
 {
-    if constexpr (kBrick == 0) return lists * (uint64_t)NS;
-    return (lists + kBrick - 1) / kBrick * kBrick * (uint64_t)NS;
+    return list_base_xy((int)(li % (uint64_t)WO), (int)(li / (uint64_t)WO), NS, WO);
+}
+// Elements of one plane set (the list grid rounded up to whole bricks, times NS).
+__host__ __device__ inline uint64_t plane_elems(int WO, int HO, int NS)
+{
+    if constexpr (kBrick == 0) return (uint64_t)WO * HO * (uint64_t)NS;
+    return (uint64_t)((WO + kBrickW - 1) / kBrickW) * ((HO + kBrickH - 1) / kBrickH) * kBrick * (uint64_t)NS;
 }
 
 // A resident VDI as the kernels see it.
@@ -78,7 +117,7 @@ struct DevVDI {
     uint64_t plane;            // WO * HO
     uint64_t sstride;          // element distance between slots j and j + 1 of a list
     const uint8_t *count;      // [HO][WO]
-    const float2 *depth;       // (f, b), plane_elems(plane, NS) in brick order
+    const float2 *depth;       // (f, b), plane_elems(WO, HO, NS) in brick order
     const void *rgba;          // same order; float4 or 4 x 16-bit
     const uint32_t *grid;      // [gnz][GH][GW]
     const uint32_t *gbits;     // occupancy of the same cells, 32 per word: bit c % 32 of word c / 32 is (grid[c] != 0)

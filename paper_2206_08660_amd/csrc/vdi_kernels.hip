@@ -3,18 +3,21 @@
 // bilinear upsampling, the count grid (Section 4.3) and colour storage
 // conversion.  The per-ray code they run is in vdi_trace.h.
 //
-// Execution model.  One lane per ray; a workgroup is one wavefront covering
-// a tile of 64 horizontally adjacent pixels (kTileW x kTileH), so a CU slot
-// is freed as soon as its 64 rays are done (with 64 x 4 tiles the finished
-// wavefronts of a tile wait for its slowest one: 6% slower).  Their
-// projected lines in V_O are near-parallel and offset by about one list, so
-// neighbouring lanes read the same or neighbouring lists at similar depths.
-// The planes are stored in bricks of four horizontally adjacent lists (see
-// list_base), so one 128-byte line holds several slots of several
-// neighbouring lists, and lists revisited by neighbouring rays are served from
-// L1/L2 (the paper's spatial smoothness).  Tiles are dealt to the 8 XCDs in
-// interleaved bands of rows (xcd_tile), so neighbouring tiles share an L2 and
-// every XCD gets part of the image centre.
+// Execution model.  One lane per ray; a workgroup is one wavefront, so a CU
+// slot is freed as soon as its 64 rays are done (with four wavefronts per
+// workgroup the finished ones wait for the slowest: 6% slower).  An exact
+// wavefront covers an 8 x 8 tile of pixels (kXTileW x kXTileH): their
+// projected lines in V_O are near-parallel, and the 8 lanes of a tile column
+// cross vertically neighbouring lists in step, at nearly the same depth,
+// while the columns follow each other along the same lists a step apart.
+// The planes are stored in bricks of 2 x 2 neighbouring lists (see
+// list_base_xy), so one 128-byte line holds several slots of the lists a
+// tile column reads together, and lists revisited by neighbouring rays are
+// served from L1/L2 (the paper's spatial smoothness).  Preview wavefronts
+// cover 64 x 1 tiles of the low-res grid, split by lanes per ray.  Tiles are
+// dealt to the 8 XCDs in interleaved bands of rows (xcd_tile), so
+// neighbouring tiles share an L2 and every XCD gets part of the image
+// centre.
 //
 // Precision.  Ray set-up, list crossings and supersegment overlaps run in
 // FP64 (the crossing depth of a ray with a list edge is ill-conditioned near
@@ -45,10 +48,10 @@ __global__ __launch_bounds__(kBlock) VDI_EXACT_OCC void k_render_exact(DevVDI V,
         for (int i = threadIdx.x; i <= V.gnz; i += kBlock) s_gz[i] = V.gz[i];
         __syncthreads();
     }
-    const int tiles_x = (F.W + kTileW - 1) / kTileW, tiles_y = (F.H + kTileH - 1) / kTileH;
-    const int tile = xcd_tile(blockIdx.x, tiles_x, tiles_y);
-    const int px = (tile % tiles_x) * kTileW + (threadIdx.x % kTileW);
-    const int py = (tile / tiles_x) * kTileH + (threadIdx.x / kTileW);
+    const int tiles_x = (F.W + kXTileW - 1) / kXTileW, tiles_y = (F.H + kXTileH - 1) / kXTileH;
+    const int tile = xcd_tile(blockIdx.x, tiles_x, tiles_y, kXBandRows);
+    const int px = (tile % tiles_x) * kXTileW + (threadIdx.x % kXTileW);
+    const int py = (tile / tiles_x) * kXTileH + (threadIdx.x / kXTileW);
     if (px >= F.W || py >= F.H) return;
     Counters cnt = {0, 0};
     F.out[(uint64_t)py * F.W + px] = trace_exact<FMT, SEARCH, ESS, COUNT>(V, F, s_gz, px, py, cnt);
@@ -60,17 +63,20 @@ __global__ __launch_bounds__(kBlock) VDI_EXACT_OCC void k_render_exact(DevVDI V,
     }
 }
 
-// One preview tile: kTileW / F.parts rays by kTileH, F.parts lanes per ray.
-// Lanes outside the image take part in the combination with an empty result.
+// One preview tile (preview_tile_dims): tw x th rays, F.parts adjacent lanes
+// per ray.  Lanes outside the image take part in the combination with an
+// empty result.
 template <int FMT>
 __device__ __forceinline__ void preview_tile(const DevVDI &V, const Frame &F, const float *s_gz, int tile_index)
 {
-    const int parts = F.parts, tw = kTileW / parts;
-    const int tiles_x = (F.W + tw - 1) / tw, tiles_y = (F.H + kTileH - 1) / kTileH;
-    const int tile = xcd_tile(tile_index, tiles_x, tiles_y);
-    const int lane = threadIdx.x;
-    const int px = (tile % tiles_x) * tw + (lane % kTileW) / parts;
-    const int py = (tile / tiles_x) * kTileH + lane / kTileW;
+    const int parts = F.parts;
+    int tw, th;
+    preview_tile_dims(parts, tw, th);
+    const int tiles_x = (F.W + tw - 1) / tw, tiles_y = (F.H + th - 1) / th;
+    const int tile = xcd_tile(tile_index, tiles_x, tiles_y, VDI_BAND_ROWS / th > 0 ? VDI_BAND_ROWS / th : 1);
+    const int lane = threadIdx.x, ray = lane / parts;
+    const int px = (tile % tiles_x) * tw + ray % tw;
+    const int py = (tile / tiles_x) * th + ray / tw;
     const bool in = px < F.W && py < F.H;
     Accum a = {0.0f, 0.0f, 0.0f, 1.0f};
     if (in) a = trace_preview<FMT>(V, F, s_gz, px, py, lane % parts, parts);
@@ -117,10 +123,10 @@ __global__ __launch_bounds__(kBlock) VDI_EXACT_OCC void k_render_batch(const Bat
     if constexpr (PREVIEW) {
         preview_tile<FMT>(J.V, J.F, s_gz, (int)local);
     } else {
-        const int tiles_x = (J.F.W + kTileW - 1) / kTileW, tiles_y = (J.F.H + kTileH - 1) / kTileH;
-        const int tile = xcd_tile((int)local, tiles_x, tiles_y);
-        const int px = (tile % tiles_x) * kTileW + (threadIdx.x % kTileW);
-        const int py = (tile / tiles_x) * kTileH + (threadIdx.x / kTileW);
+        const int tiles_x = (J.F.W + kXTileW - 1) / kXTileW, tiles_y = (J.F.H + kXTileH - 1) / kXTileH;
+        const int tile = xcd_tile((int)local, tiles_x, tiles_y, kXBandRows);
+        const int px = (tile % tiles_x) * kXTileW + (threadIdx.x % kXTileW);
+        const int py = (tile / tiles_x) * kXTileH + (threadIdx.x / kXTileW);
         if (px >= J.F.W || py >= J.F.H) return;
         Counters cnt = {0, 0};
         J.F.out[(uint64_t)py * J.F.W + px] = trace_exact<FMT, VDI_SEARCH_WINDOW, true, false>(J.V, J.F, s_gz, px, py, cnt);
@@ -167,7 +173,7 @@ __global__ __launch_bounds__(256) void k_grid_build(DevVDI V, uint32_t *__restri
     __syncthreads();
     const int lx = cx * k + (int)threadIdx.x % k, ly = cy * k + (int)threadIdx.x / k;
     if ((int)threadIdx.x < k * k && lx < V.WO && ly < V.HO) {
-        const uint64_t li = (uint64_t)ly * V.WO + lx, lb = list_base(li, V.NS);
+        const uint64_t li = (uint64_t)ly * V.WO + lx, lb = list_base_xy(lx, ly, V.NS, V.WO);
         const int n = V.count[li];
         for (int j = 0; j < n; ++j) {
             const float2 fb = V.depth[(uint64_t)j * V.sstride + lb];
@@ -221,11 +227,11 @@ __device__ inline uint2 to16(float4 v, int fmt)
 // S -> D element by element; CONV: store S as is, or a float4 as 16-bit format CONV.
 template <typename S, typename D, int CONV>
 __global__ __launch_bounds__(256) void k_scatter(const S *__restrict__ src, D *__restrict__ dst, uint64_t n,
-                                                 uint64_t plane, int NS, int j0, uint64_t sstride)
+                                                 uint64_t plane, int NS, int j0, uint64_t sstride, int WO)
 {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t j = j0 + i / plane, li = i % plane;
-        const uint64_t o = list_base(li, NS) + j * sstride;
+        const uint64_t o = list_base(li, NS, WO) + j * sstride;
         if constexpr (CONV == 0) dst[o] = src[i];
         else dst[o] = to16(src[i], CONV);
     }
@@ -257,7 +263,7 @@ hipError_t launch_exact_fmt(const DevVDI &v, const Frame &f, dim3 grid, hipStrea
 
 inline dim3 tile_grid(int W, int H)
 {
-    return dim3((unsigned)(((W + kTileW - 1) / kTileW) * ((H + kTileH - 1) / kTileH)));
+    return dim3((unsigned)(((W + kXTileW - 1) / kXTileW) * ((H + kXTileH - 1) / kXTileH)));
 }
 
 }  // namespace
@@ -348,19 +354,19 @@ hipError_t launch_scatter_slots(const void *src, int32_t fmt_in, void *dst, int3
     const int NS = v.NS;
     if (depth)
         k_scatter<float2, float2, 0><<<g, 256, 0, s>>>(static_cast<const float2 *>(src), static_cast<float2 *>(dst), n,
-                                                       plane, NS, j0, st);
+                                                       plane, NS, j0, st, v.WO);
     else if (fmt_store == VDI_F32)
         k_scatter<float4, float4, 0><<<g, 256, 0, s>>>(static_cast<const float4 *>(src), static_cast<float4 *>(dst), n,
-                                                       plane, NS, j0, st);
+                                                       plane, NS, j0, st, v.WO);
     else if (fmt_in != VDI_F32)
         k_scatter<uint2, uint2, 0><<<g, 256, 0, s>>>(static_cast<const uint2 *>(src), static_cast<uint2 *>(dst), n,
-                                                     plane, NS, j0, st);
+                                                     plane, NS, j0, st, v.WO);
     else if (fmt_store == VDI_F16)
         k_scatter<float4, uint2, VDI_F16><<<g, 256, 0, s>>>(static_cast<const float4 *>(src), static_cast<uint2 *>(dst),
-                                                            n, plane, NS, j0, st);
+                                                            n, plane, NS, j0, st, v.WO);
     else
         k_scatter<float4, uint2, VDI_BF16><<<g, 256, 0, s>>>(static_cast<const float4 *>(src), static_cast<uint2 *>(dst),
-                                                             n, plane, NS, j0, st);
+                                                             n, plane, NS, j0, st, v.WO);
     return hipGetLastError();
 }
 

@@ -73,10 +73,13 @@ struct Lane {
     bool busy = false;
 };
 
-uint32_t tiles_of(int w, int h)
+// Workgroups of an exact render of w x h rays.
+uint32_t exact_tiles(int w, int h)
 {
-    return (uint32_t)(((w + kTileW - 1) / kTileW) * ((h + kTileH - 1) / kTileH));
+    return (uint32_t)(((w + kXTileW - 1) / kXTileW) * ((h + kXTileH - 1) / kXTileH));
 }
+// Workgroups of 256 threads upsampling a W x H image (64 x 4 pixels each).
+uint32_t upsample_tiles(int W, int H) { return (uint32_t)(((W + 63) / 64) * ((H + 3) / 4)); }
 // Job starts are multiples of the XCD count.
 uint64_t align_up(uint64_t x) { return (x + kXcds - 1) / kXcds * kXcds; }
 
@@ -351,11 +354,11 @@ int vdi_server_submit(vdi_server_t s, vdi_t v, const vdi_camera *cam, int32_t W,
     r.job.F.ess = 1;
     r.job.F.search = VDI_SEARCH_WINDOW;
     r.job.tile0 = 0;
-    r.job.ntiles = D_R > 0.0f ? vdi::preview_tiles(w, h) : vdi::tiles_of(w, h);
+    r.job.ntiles = D_R > 0.0f ? vdi::preview_tiles(w, h) : vdi::exact_tiles(w, h);
     r.fmt = S.dev.fmt;
     r.preview = D_R > 0.0f;
     r.down = down;
-    if (down) r.up = vdi::UpsampleJob{r.lowres, reinterpret_cast<float4 *>(out), w, h, W, H, 0, vdi::tiles_of(W, H)};
+    if (down) r.up = vdi::UpsampleJob{r.lowres, reinterpret_cast<float4 *>(out), w, h, W, H, 0, vdi::upsample_tiles(W, H)};
     r.bytes = bytes;
     r.lowres_bytes = lowres_bytes;
     const uint64_t t = s->next_ticket++;

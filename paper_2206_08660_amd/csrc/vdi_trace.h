@@ -42,31 +42,33 @@ constexpr int kBlock = kTileW * kTileH;
 VDI_HD inline double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
 // Tile of workgroup `bid`.  Workgroups are dealt to the 8 XCDs round-robin
-// and each XCD has its own L2.  Tile rows are grouped into bands of kBandRows;
-// band b belongs to XCD b % 8, so each XCD renders whole bands (horizontal
-// neighbours, whose rays cross the same V_O lists, share an L2) while the
-// bands of every XCD are spread over the image (the work is balanced).
-// The map is a bijection from [0, tiles_x * tiles_y) onto itself.
+// and each XCD has its own L2.  Tile rows are grouped into bands of
+// `band_rows` tile rows (8 pixel rows); band b belongs to XCD b % 8, so each
+// XCD renders whole bands (horizontal neighbours, whose rays cross the same
+// V_O lists, share an L2) while the bands of every XCD are spread over the
+// image (the work is balanced).  The map is a bijection from
+// [0, tiles_x * tiles_y) onto itself.
 #ifndef VDI_BAND_ROWS
 #define VDI_BAND_ROWS 8
 #endif
-constexpr int kBandRows = VDI_BAND_ROWS / kTileH > 0 ? VDI_BAND_ROWS / kTileH : 1;  // tile rows per band
+constexpr int kBandRows = VDI_BAND_ROWS / kTileH > 0 ? VDI_BAND_ROWS / kTileH : 1;     // rows of 64 x 1 tiles
+constexpr int kXBandRows = VDI_BAND_ROWS / kXTileH > 0 ? VDI_BAND_ROWS / kXTileH : 1;  // rows of exact tiles
 
-VDI_HD inline int xcd_tile(int bid, int tiles_x, int tiles_y)
+VDI_HD inline int xcd_tile(int bid, int tiles_x, int tiles_y, int band_rows = kBandRows)
 {
     const int total = tiles_x * tiles_y;
     const int x = bid % kXcds, k = bid / kXcds;
     // Position of this block in the XCD-major order of all blocks.
     const int pos = x * (total / kXcds) + min(x, total % kXcds) + k;
     // Bands in XCD-group order: group g holds bands g, g + 8, g + 16, ...
-    const int nb = (tiles_y + kBandRows - 1) / kBandRows;
-    const int last_rows = tiles_y - (nb - 1) * kBandRows;
-    const int band_tiles = kBandRows * tiles_x;
+    const int nb = (tiles_y + band_rows - 1) / band_rows;
+    const int last_rows = tiles_y - (nb - 1) * band_rows;
+    const int band_tiles = band_rows * tiles_x;
     int start = 0;
     for (int g = 0; g < kXcds; ++g) {
         const int nbg = g < nb ? (nb - 1 - g) / kXcds + 1 : 0;
         int size = nbg * band_tiles;
-        if (nbg > 0 && (nb - 1) % kXcds == g) size -= (kBandRows - last_rows) * tiles_x;
+        if (nbg > 0 && (nb - 1) % kXcds == g) size -= (band_rows - last_rows) * tiles_x;
         if (pos < start + size) {
             const int local = pos - start;
             const int b = g + kXcds * (local / band_tiles);
@@ -438,7 +440,7 @@ VDI_HD bool do_list(const DevVDI &V, const Frame &F, int ix, int iy, int n, doub
     const double za = Z0 + ta * Zp, zb = Z0 + tb * Zp;
     const float cth = list_cos(V, ix, iy);
     const float2 *__restrict__ dep = V.depth;
-    const uint64_t stride = slot_stride(V), lb = list_base(li, V.NS);
+    const uint64_t stride = slot_stride(V), lb = list_base_xy(ix, iy, V.NS, V.WO);
     auto piece = [&](int j, float2 d, float4 c, double zl, double zh, double inv) -> bool {
         composite(A, c, (float)((zh - zl) * inv) * cth * rcp32(d.y - d.x));
         if constexpr (COUNT) {
@@ -617,8 +619,9 @@ VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, in
     };
     auto locate = [&](double tt) {
         const double z = F.Z0 + tt * r.Zp;
-        ix = cell_of((F.X0 + tt * r.Xp) / z, WO, sx);
-        iy = cell_of((F.Y0 + tt * r.Yp) / z, HO, sy);
+        const double iz = rcp64(z);
+        ix = cell_of((F.X0 + tt * r.Xp) * iz, WO, sx);
+        iy = cell_of((F.Y0 + tt * r.Yp) * iz, HO, sy);
         const int mx = ix + ox, my = iy + oy;
         tx = (sx != 0 && mx > 0 && mx < WO) ? line_t(mx, V.dcx, F.X0, r.Xp, F.Z0, r.Zp) : inf;
         ty = (sy != 0 && my > 0 && my < HO) ? line_t(my, V.dcy, F.Y0, r.Yp, F.Z0, r.Zp) : inf;
@@ -654,16 +657,20 @@ VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, in
             if (cellmode) {
                 const double te = fmin(fmin(tx, ty), fmin(tz, r.t1));
                 if (te >= r.t1) break;
-                if (tx <= ty && tx <= tz) {
-                    ix += sx;
-                    tx = cell_tx(ix);
-                } else if (ty <= tz) {
-                    iy += sy;
-                    ty = cell_ty(iy);
-                } else {
-                    cz += fwd ? 1 : -1;
-                    tz = slice_t(cz);
-                }
+                // One crossing solve per step whichever face the lanes leave by.
+                const bool ax = tx <= ty && tx <= tz, ay = !ax && ty <= tz, az = !ax && !ay;
+                ix += ax ? sx : 0;
+                iy += ay ? sy : 0;
+                cz += az ? (fwd ? 1 : -1) : 0;
+                const int cc = ax ? ix : iy, sc = ax ? sx : sy, lim = ax ? WO : HO;
+                const int m = sc > 0 ? min((cc + 1) * gk, lim) : cc * gk;
+                const double tl = (sc != 0 && m > 0 && m < lim && !az)
+                                      ? line_t(m, ax ? V.dcx : V.dcy, ax ? F.X0 : F.Y0, ax ? r.Xp : r.Yp, F.Z0, r.Zp)
+                                      : inf;
+                const double tzn = az ? slice_t(cz) : tz;
+                tx = ax ? tl : tx;
+                ty = ay ? tl : ty;
+                tz = tzn;
                 if ((unsigned)ix >= (unsigned)V.GW || (unsigned)iy >= (unsigned)V.GH || (unsigned)cz >= (unsigned)V.gnz)
                     break;
                 t = fmax(t, te);
@@ -717,12 +724,14 @@ VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, in
         const int n_next = more ? V.count[(uint64_t)ny * WO + nx] : 0;
         if (tn > t && do_list<FMT, SEARCH, COUNT>(V, F, ix, iy, n, t, tn, F.Z0, r.Zp, invZp, A, p, cnt)) break;
         if (!more) break;
-        if (stepx) {
-            const int mx = nx + ox;
-            tx = (mx > 0 && mx < WO) ? line_t(mx, V.dcx, F.X0, r.Xp, F.Z0, r.Zp) : inf;
-        } else {
-            const int my = ny + oy;
-            ty = (my > 0 && my < HO) ? line_t(my, V.dcy, F.Y0, r.Yp, F.Z0, r.Zp) : inf;
+        {
+            // One crossing solve per step, for the axis the ray stepped in.
+            const int mm = stepx ? nx + ox : ny + oy, lim = stepx ? WO : HO;
+            const double tl = (mm > 0 && mm < lim)
+                                  ? line_t(mm, stepx ? V.dcx : V.dcy, stepx ? F.X0 : F.Y0, stepx ? r.Xp : r.Yp, F.Z0, r.Zp)
+                                  : inf;
+            tx = stepx ? tl : tx;
+            ty = stepx ? ty : tl;
         }
         ix = nx;
         iy = ny;
@@ -836,15 +845,14 @@ VDI_HD Accum trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, i
         // alone would put them on either side (a ray lying in an edge plane,
         // e.g. a downsampled view from the generating viewpoint).
         double h = 0.0;
-        auto sample_list = [&](int q, double &u, double &z) -> uint64_t {
+        auto sample_list = [&](int q, double &u, double &z, int &lx, int &ly) {
             u = t + (q + 0.5) * h;
             z = F.Z0 + u * r.Zp;
             const double iz = rcp64(z);
             const double fx = ((F.X0 + u * r.Xp) * iz + 1.0) * (0.5 * WO) + kTieShift;
             const double fy = ((F.Y0 + u * r.Yp) * iz + 1.0) * (0.5 * HO) + kTieShift;
-            const int lx = min(max((int)floor(fx), 0), WO - 1);
-            const int ly = min(max((int)floor(fy), 0), HO - 1);
-            return (uint64_t)ly * WO + lx;
+            lx = min(max((int)floor(fx), 0), WO - 1);
+            ly = min(max((int)floor(fy), 0), HO - 1);
         };
         // One flat loop: every step either enters the current grid cell (and,
         // when the cell is non-empty, sets up its samples) or takes one
@@ -854,7 +862,7 @@ VDI_HD Accum trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, i
         int it = 0;        // cells entered
         int q = 0, n = 0;  // sample q of n in the current cell; n == 0 between cells
         double tn = 0.0, u = 0.0, z = 0.0;
-        uint64_t li = 0;
+        int lx = 0, ly = 0;
         int nl = 0;
         for (;;) {
             bool advance = true;
@@ -870,31 +878,32 @@ VDI_HD Accum trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, i
                         n = (int)fmin(fmax(ceil(x), 1.0), 16777216.0);
                         h = (tn - t) / n;
                         q = 0;
-                        li = sample_list(0, u, z);
-                        nl = V.count[li];
+                        sample_list(0, u, z, lx, ly);
+                        nl = V.count[(uint64_t)ly * WO + lx];
                         advance = false;
                     }
                 }
             } else {
                 double un = 0.0, zn = 0.0;
-                const uint64_t lin = q + 1 < n ? sample_list(q + 1, un, zn) : li;
-                const int nln = q + 1 < n ? (int)V.count[lin] : 0;
+                int lxn = lx, lyn = ly;
+                if (q + 1 < n) sample_list(q + 1, un, zn, lxn, lyn);
+                const int nln = q + 1 < n ? (int)V.count[(uint64_t)lyn * WO + lxn] : 0;
                 if (nl > 0) {
                     // Point location: the supersegment with f <= z < b.
-                    const uint64_t lb = list_base(li, V.NS);
+                    const uint64_t lb = list_base_xy(lx, ly, V.NS, WO);
                     const int j = first_back_above_win(dep, stride, lb, nl, z, fwd ? win_start_fwd(p) : win_start_bwd(p));
                     if (j < nl) {
                         const float2 fb = dep[(uint64_t)j * stride + lb];
                         p = j;
                         if ((double)fb.x <= z) {
-                            const int lx = (int)(li % (uint64_t)WO), ly = (int)(li / (uint64_t)WO);
                             const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * stride + lb, V.fmt);
                             composite(A, c, (float)h * list_cos(V, lx, ly) * rcp32(fb.y - fb.x));
                             if (A.T <= kTTerm) break;
                         }
                     }
                 }
-                li = lin;
+                lx = lxn;
+                ly = lyn;
                 nl = nln;
                 u = un;
                 z = zn;

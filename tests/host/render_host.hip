@@ -23,12 +23,12 @@ extern "C" int host_render(const vdi_desc *d, const uint32_t *grid, const vdi_ca
     D.fmt = VDI_F32;
     D.plane = (uint64_t)d->width * d->height;
     D.sstride = vdi::kBrick ? (uint64_t)vdi::kBrick : D.plane;
-    const uint64_t elems = vdi::plane_elems(D.plane, D.NS);
+    const uint64_t elems = vdi::plane_elems(D.WO, D.HO, D.NS);
     std::vector<float2> dep(elems, make_float2(NAN, NAN));
     std::vector<float4> col(elems, make_float4(NAN, NAN, NAN, NAN));
     for (int j = 0; j < D.NS; ++j)
         for (uint64_t li = 0; li < D.plane; ++li) {
-            const uint64_t o = vdi::list_base(li, D.NS) + (uint64_t)j * D.sstride;
+            const uint64_t o = vdi::list_base(li, D.NS, D.WO) + (uint64_t)j * D.sstride;
             dep[o] = reinterpret_cast<const float2 *>(d->depth)[(uint64_t)j * D.plane + li];
             col[o] = static_cast<const float4 *>(d->rgba)[(uint64_t)j * D.plane + li];
         }

@@ -85,6 +85,25 @@ def test_exact_random_vdi(host):
         assert np.abs(render(host, v, cam, 40, 26) - ref).max() <= TOL
 
 
+@pytest.mark.parametrize("ns,seed", [(70, 3), (255, 4)])
+def test_exact_long_lists(host, ns, seed):
+    """Lists of every length from 0 to N_S, up to 255, thin supersegments
+    (alpha <= 0.12, so rays pass many of them): the directory bracket, the
+    bisection that narrows it for lists over about 60 slots, windows that
+    continue past their end, forwards (3 and 25 deg) and backwards (135 deg),
+    every search against the oracle."""
+    v = synth.random_vdi(24, 16, ns, seed=seed, alpha_max=0.12, empty_frac=0.1)
+    assert v.count.max() > 60 and (v.count <= 8).any()
+    for theta in (3.0, 25.0, 135.0):
+        cam = inputs.orbit_camera(theta)
+        ref = oracle.render_exact(v, cam, 40, 26)
+        assert (ref[..., 3] > 0).mean() > 0.5
+        for search in ("window", "binary"):
+            for ess in (True, False):
+                img = render(host, v, cam, 40, 26, search=search, ess=ess)
+                assert np.abs(img - ref).max() <= TOL, (theta, search, ess)
+
+
 @pytest.mark.parametrize("theta", [9.0, 150.0])
 @pytest.mark.parametrize("parts", [1, 2, 4, 8])
 def test_preview_split_rays(host, tiny, parts, theta):
