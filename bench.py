@@ -204,7 +204,39 @@ def main():
     torch.cuda.synchronize()
     total_b = sum(balg.values())
     total_s = sum(exact_ms.values()) / 1e3
-    achieved = total_b / total_s / 1e9
+    total_flushed_s = sum(flushed.values()) / 1e3
+    # The roofline fraction takes the MALL-flushed frame times (nothing of the
+    # VDI left in the 256 MB Infinity Cache); the warm figure sits beside it.
+    achieved = total_b / total_flushed_s / 1e9
+    achieved_warm = total_b / total_s / 1e9
+    exact_mpix = len(ANGLES) * W * H / total_s / 1e6
+    log(f"exact frames: {exact_mpix:.1f} Mpixels/s; roofline {achieved:.0f} GB/s flushed, {achieved_warm:.0f} GB/s warm")
+    # Preview frames: algorithmic bytes from the instrumented preview kernel
+    # (per list sampled its count byte and (f, b) pairs, per supersegment
+    # composited its colour, 4 bytes per grid cell read, the low-res image
+    # written and read back by the upsampling, the output written) against
+    # the whole render (preview kernel + upsampling), warm.
+    preview_roof = {}
+    for (di, dr) in MODES:
+        if dr == 0.0:
+            continue
+        pb, pms, samples = 0, 0.0, 0
+        for th in ANGLES:
+            lo_img, tl, ts, tc, st = h.preview_counters(cams[th], W, H, di, dr)
+            touched = tl.bool()
+            lw, lh = lo_img.shape[1], lo_img.shape[0]
+            pb += int(touched.sum().item() + 8 * count_d[touched].sum().item()
+                      + 16 * ts.sum(dtype=torch.int64).item() + 4 * tc.sum(dtype=torch.int64).item()
+                      + 16 * (2 * lw * lh + W * H))
+            samples += int(st[..., 0].sum(dtype=torch.int64).item())
+            pms += per[(th, di, dr)]
+            del lo_img, tl, ts, tc, st
+        preview_roof[f"D_I={di:g},D_R={dr:g}"] = {
+            "algorithmic_MB_per_frame": round(pb / len(ANGLES) / 1e6, 2), "ms_per_frame": round(pms / len(ANGLES), 4),
+            "achieved_GBs": round(pb / (pms / 1e3) / 1e9, 1), "frac": round(pb / (pms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "samples_M_per_frame": round(samples / len(ANGLES) / 1e6, 3)}
+    torch.cuda.synchronize()
+    log("preview roofline: " + ", ".join(f"{k} {v['achieved_GBs']} GB/s ({v['frac']})" for k, v in preview_roof.items()))
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         tr = json.load(open(TRAFFIC_FILE))
@@ -248,10 +280,15 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_render_exact (exact mode, FP32 colour, ESS, window search)",
+                     "timing": "MALL-flushed launches (512 MB written before each), mean over the 10 viewpoints",
                      "algorithmic_bytes_per_launch": int(total_b / len(ANGLES)),
+                     "launch_ms": round(1e3 * total_flushed_s / len(ANGLES), 4),
+                     "achieved_warm": round(achieved_warm, 1), "frac_warm": round(achieved_warm / HBM_PEAK_GBS, 4),
+                     "launch_ms_warm": round(1e3 * total_s / len(ANGLES), 4),
                      "copy_kernel_GBs": round(copy_gbs, 1),
-                     "frac_of_copy_kernel": round(achieved / copy_gbs, 4),
-                     "launch_ms": round(1e3 * total_s / len(ANGLES), 4)},
+                     "frac_of_copy_kernel": round(achieved / copy_gbs, 4)},
+        "preview_roofline": preview_roof,
+        "exact_only": {"Mpixels_per_s": round(exact_mpix, 1), "frames_per_s": round(len(ANGLES) / total_s, 1)},
         "breakdown": breakdown,
     }
 
@@ -661,6 +698,23 @@ def cpu_baseline_leg(src, cams, per, precision, np, torch, V):
         hh.close()
     cpu_s = time.time() - t_all
     mpix = len(per) * W * H / t_frames / 1e6
+    # One core: the exact frames at 0, 20 and 45 degrees on 0.2% of their pixels.
+    t1, n1 = 0.0, 0
+    for th in (0.0, 20.0, 45.0):
+        pix = np.sort(rng.choice(W * H, size=int(0.002 * W * H), replace=False))
+        t = time.perf_counter()
+        oracle.render_exact(src, cams[th], W, H, pixels=pix, nthreads=1)
+        t1 += time.perf_counter() - t
+        n1 += len(pix)
+    mpix_1 = n1 / t1 / 1e6
+    cpu_model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     acc = {}
     for fmt in ("f32", "f16", "bf16"):
         mse = sq[fmt][0] / max(1, sq[fmt][1])
@@ -668,11 +722,15 @@ def cpu_baseline_leg(src, cams, per, precision, np, torch, V):
                     "psnr_db_vs_fp64_oracle": (None if mse == 0 else round(10 * math.log10(1.0 / mse), 2))}
         if fmt != "f32":
             acc[fmt]["max_abs_vs_oracle_on_dequantized"] = max(errs[fmt + "_vs_dequantized"])
-    log(f"cpu baseline: {mpix:.4f} Mpixels/s extrapolated, {n_px} pixels in {cpu_s:.1f}s on {oracle.threads()} threads")
+    log(f"cpu baseline: {mpix:.4f} Mpixels/s extrapolated, {n_px} pixels in {cpu_s:.1f}s on {oracle.threads()} threads"
+        f" ({cpu_model}); one thread, exact: {mpix_1:.4f} Mpixels/s")
     return {"value": round(mpix, 5), "unit": "Mpixels/s", "cores": oracle.threads(), "kind": "oracle",
             "sample": f"{n_px} random pixels of the 30 frames of one step (2% of each exact frame, 0.2% of each "
                       f"preview frame), frame time extrapolated per frame",
-            "accuracy_exact_mode_sampled": acc, "host_seconds": round(cpu_s, 1)}
+            "cpu_model": cpu_model,
+            "single_core": {"Mpixels_per_s": round(mpix_1, 5),
+                            "sample": f"exact frames at 0, 20, 45 deg, {n1} random pixels (0.2% of each), one thread"},
+            "accuracy_exact_mode_sampled": acc, "host_seconds": round(cpu_s + t1, 1)}
 
 
 if __name__ == "__main__":

@@ -199,6 +199,24 @@ int vdi_render_counters(vdi_t v, const vdi_camera *cam_VN, int32_t width, int32_
                         const vdi_render_opts *opts, float *out_rgba, uint8_t *touched_lists,
                         uint8_t *touched_slots, int32_t *ray_stats, void *hip_stream);
 
+/*
+ * Instrumented preview (Section 4.4 along-ray sampling) of the low-res ray
+ * grid of a width x height, D_I, D_R render (D_R > 0): renders the
+ * round(width/D_I) x round(height/D_I) image, with the display's aspect, into
+ * lowres_out (device, float32 RGBA, that many pixels; the texels vdi_render
+ * upsamples) and records what the samples read, to measure the algorithmic
+ * bytes of a preview frame: touched_lists [H_O][W_O] uint8 (the list of every
+ * sample), touched_slots [N_S][H_O][W_O] uint8 (every supersegment
+ * composited) and touched_cells [grid_nz][grid_h][grid_w] uint8 (every grid
+ * cell whose count was read); device pointers zeroed by the caller.
+ * ray_stats [h][w][2] int32 (device, zeroed, may be NULL) receive per ray
+ * (samples taken, supersegments composited).  Slower than vdi_render.
+ * Errors: those of vdi_render, VDI_ERR_ARG for D_R = 0 or a null buffer.
+ */
+int vdi_preview_counters(vdi_t v, const vdi_camera *cam_VN, int32_t width, int32_t height, float D_I, float D_R,
+                         float *lowres_out, uint8_t *touched_lists, uint8_t *touched_slots, uint8_t *touched_cells,
+                         int32_t *ray_stats, void *hip_stream);
+
 /* Copy the count grid, uint32 [grid_nz][grid_h][grid_w], to host memory. */
 int vdi_get_grid(vdi_t v, uint32_t *host_out, size_t capacity_elems);
 

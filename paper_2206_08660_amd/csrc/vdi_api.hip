@@ -249,7 +249,7 @@ int render_impl(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, float D_I,
     }
     f.out = down ? lo : reinterpret_cast<float4 *>(out);
     f.DR = D_R;
-    hipError_t e = D_R > 0.0f ? vdi::launch_render_preview(S.dev, f, s) : vdi::launch_render_exact(S.dev, f, false, s);
+    hipError_t e = D_R > 0.0f ? vdi::launch_render_preview(S.dev, f, false, s) : vdi::launch_render_exact(S.dev, f, false, s);
     if (e == hipSuccess && down) e = vdi::launch_upsample(lo, w, h, reinterpret_cast<float4 *>(out), W, H, s);
     if (down && !noalloc) {
         hipError_t e2 = hipFreeAsync(lo, s);
@@ -723,6 +723,32 @@ int vdi_render_counters(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, co
     f.touched_slots = touched_slots;
     f.ray_stats = ray_stats;
     HIP_OR_FAIL(vdi::launch_render_exact(S.dev, f, true, static_cast<hipStream_t>(stream)), "counter render launch");
+    return VDI_OK;
+}
+
+int vdi_preview_counters(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, float D_I, float D_R, float *lowres_out,
+                         uint8_t *touched_lists, uint8_t *touched_slots, uint8_t *touched_cells, int32_t *ray_stats,
+                         void *stream)
+{
+    g_err.clear();
+    int rc = check_args(v, cam, W, H, D_I, D_R, lowres_out);
+    if (rc) return rc;
+    if (!(D_R > 0.0f)) return fail(VDI_ERR_ARG, "vdi_preview_counters needs D_R > 0");
+    if (!touched_lists || !touched_slots || !touched_cells) return fail(VDI_ERR_ARG, "null counter buffer");
+    int32_t w, h;
+    lowres_dims(W, H, D_I, &w, &h);
+    const vdi::VdiSet S = vdi::current(v);
+    vdi::Frame f;
+    rc = build_frame(S, *cam, w, h, (double)W / (double)H, f);
+    if (rc) return rc;
+    HIP_OR_FAIL(hipSetDevice(v->device), "hipSetDevice");
+    f.out = reinterpret_cast<float4 *>(lowres_out);
+    f.DR = D_R;
+    f.touched_lists = touched_lists;
+    f.touched_slots = touched_slots;
+    f.touched_cells = touched_cells;
+    f.ray_stats = ray_stats;
+    HIP_OR_FAIL(vdi::launch_render_preview(S.dev, f, true, static_cast<hipStream_t>(stream)), "counter preview launch");
     return VDI_OK;
 }
 

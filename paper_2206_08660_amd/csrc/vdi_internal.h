@@ -144,8 +144,8 @@ struct Frame {
     double DR;                 // > 0: along-ray subsampling
     int32_t parts;             // preview: lanes per ray (preview_parts)
     float4 *out;               // [H][W]
-    // counters (instrumented kernel only)
-    uint8_t *touched_lists, *touched_slots;
+    // counters (instrumented kernels only)
+    uint8_t *touched_lists, *touched_slots, *touched_cells;
     int32_t *ray_stats;
 };
 
@@ -222,7 +222,7 @@ VdiSet current(vdi_s *v);
 
 // Launchers (vdi_kernels.hip).  All run on `stream` and return the launch status.
 hipError_t launch_render_exact(const DevVDI &v, const Frame &f, bool counters, hipStream_t stream);
-hipError_t launch_render_preview(const DevVDI &v, const Frame &f, hipStream_t stream);
+hipError_t launch_render_preview(const DevVDI &v, const Frame &f, bool counters, hipStream_t stream);
 hipError_t launch_upsample(const float4 *lo, int32_t w, int32_t h, float4 *out, int32_t W, int32_t H,
                            hipStream_t stream);
 hipError_t launch_grid_build(const DevVDI &v, uint32_t *grid, hipStream_t stream);

@@ -66,7 +66,7 @@ __global__ __launch_bounds__(kBlock) VDI_EXACT_OCC void k_render_exact(DevVDI V,
 // One preview tile (preview_tile_dims): tw x th rays, F.parts adjacent lanes
 // per ray.  Lanes outside the image take part in the combination with an
 // empty result.
-template <int FMT>
+template <int FMT, bool COUNT = false>
 __device__ __forceinline__ void preview_tile(const DevVDI &V, const Frame &F, const float *s_gz, int tile_index)
 {
     const int parts = F.parts;
@@ -79,18 +79,25 @@ __device__ __forceinline__ void preview_tile(const DevVDI &V, const Frame &F, co
     const int py = (tile / tiles_x) * th + ray / tw;
     const bool in = px < F.W && py < F.H;
     Accum a = {0.0f, 0.0f, 0.0f, 1.0f};
-    if (in) a = trace_preview<FMT>(V, F, s_gz, px, py, lane % parts, parts);
+    Counters cnt = {0, 0};
+    if (in) a = trace_preview<FMT, COUNT>(V, F, s_gz, px, py, lane % parts, parts, &cnt);
     a = combine_parts(a, parts, lane);
     if (in && lane % parts == 0) F.out[(uint64_t)py * F.W + px] = to_rgba(a);
+    if constexpr (COUNT) {
+        if (in && F.ray_stats) {
+            atomicAdd(&F.ray_stats[2 * ((uint64_t)py * F.W + px)], cnt.lists);
+            atomicAdd(&F.ray_stats[2 * ((uint64_t)py * F.W + px) + 1], cnt.pieces);
+        }
+    }
 }
 
-template <int FMT>
+template <int FMT, bool COUNT>
 __global__ __launch_bounds__(kBlock) void k_render_preview(DevVDI V, Frame F)
 {
     __shared__ float s_gz[VDI_MAX_GRID_NZ + 1];
     for (int i = threadIdx.x; i <= V.gnz; i += kBlock) s_gz[i] = V.gz[i];
     __syncthreads();
-    preview_tile<FMT>(V, F, s_gz, blockIdx.x);
+    preview_tile<FMT, COUNT>(V, F, s_gz, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -285,14 +292,22 @@ hipError_t launch_render_exact(const DevVDI &v, const Frame &f, bool counters, h
     }
 }
 
-hipError_t launch_render_preview(const DevVDI &v, const Frame &f, hipStream_t s)
+hipError_t launch_render_preview(const DevVDI &v, const Frame &f, bool counters, hipStream_t s)
 {
     if (f.parts != preview_parts(f.W, f.H)) return hipErrorInvalidValue;
     const dim3 g(preview_tiles(f.W, f.H));
+    if (counters) {
+        switch (v.fmt) {
+        case VDI_F16: k_render_preview<VDI_F16, true><<<g, kBlock, 0, s>>>(v, f); break;
+        case VDI_BF16: k_render_preview<VDI_BF16, true><<<g, kBlock, 0, s>>>(v, f); break;
+        default: k_render_preview<VDI_F32, true><<<g, kBlock, 0, s>>>(v, f); break;
+        }
+        return hipGetLastError();
+    }
     switch (v.fmt) {
-    case VDI_F16: k_render_preview<VDI_F16><<<g, kBlock, 0, s>>>(v, f); break;
-    case VDI_BF16: k_render_preview<VDI_BF16><<<g, kBlock, 0, s>>>(v, f); break;
-    default: k_render_preview<VDI_F32><<<g, kBlock, 0, s>>>(v, f); break;
+    case VDI_F16: k_render_preview<VDI_F16, false><<<g, kBlock, 0, s>>>(v, f); break;
+    case VDI_BF16: k_render_preview<VDI_BF16, false><<<g, kBlock, 0, s>>>(v, f); break;
+    default: k_render_preview<VDI_F32, false><<<g, kBlock, 0, s>>>(v, f); break;
     }
     return hipGetLastError();
 }

@@ -31,7 +31,7 @@ EXPORTS = ("vdi_create", "vdi_render", "vdi_render_ex", "vdi_render_counters", "
            "vdi_server_submit", "vdi_server_poll", "vdi_server_drain", "vdi_server_get_stats",
            "vdi_server_reset_stats", "vdi_server_destroy", "vdi_replace_begin", "vdi_replace_poll",
            "vdi_pace_create", "vdi_pace_update", "vdi_pace_destroy", "vdi_generate", "vdi_dvr",
-           "vdi_image_quality", "vdi_render_noalloc")
+           "vdi_image_quality", "vdi_render_noalloc", "vdi_preview_counters")
 
 VOXEL = {"f32": 0, "u16": 1}
 TF = {"ramp": 0, "knots4": 1}
@@ -109,6 +109,7 @@ def lib() -> ctypes.CDLL:
         L.vdi_render_noalloc.argtypes = [P, ctypes.POINTER(Camera), I32, I32, F, F, P, P]
         L.vdi_render_ex.argtypes = [P, ctypes.POINTER(Camera), I32, I32, F, F, ctypes.POINTER(Opts), P, P]
         L.vdi_render_counters.argtypes = [P, ctypes.POINTER(Camera), I32, I32, ctypes.POINTER(Opts), P, P, P, P, P]
+        L.vdi_preview_counters.argtypes = [P, ctypes.POINTER(Camera), I32, I32, F, F, P, P, P, P, P, P]
         L.vdi_get_grid.argtypes = [P, P, ctypes.c_size_t]
         L.vdi_get_info.argtypes = [P, ctypes.POINTER(Info)]
         L.vdi_destroy.argtypes = [P]
@@ -299,6 +300,26 @@ class Vdi:
         _check(lib().vdi_render_noalloc(self.handle, ctypes.byref(c), width, height, d_i, d_r,
                                         ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
         return out
+
+    def preview_counters(self, cam, width: int, height: int, d_i: float, d_r: float, stream=None):
+        """Instrumented preview of the low-res ray grid (vdi_preview_counters):
+        (low-res image [h, w, 4], touched_lists [H_O, W_O] u8, touched_slots
+        [N_S, H_O, W_O] u8, touched_cells [N_z, GH, GW] u8, ray_stats [h, w, 2]
+        i32), all torch CUDA tensors."""
+        import torch
+        w, h = lowres_size(width, height, d_i)
+        inf = self.info()
+        out = torch.empty((h, w, 4), dtype=torch.float32, device="cuda")
+        tl = torch.zeros((self.height, self.width), dtype=torch.uint8, device="cuda")
+        ts = torch.zeros((self.ns, self.height, self.width), dtype=torch.uint8, device="cuda")
+        tc = torch.zeros((inf.grid_nz, inf.grid_h, inf.grid_w), dtype=torch.uint8, device="cuda")
+        st = torch.zeros((h, w, 2), dtype=torch.int32, device="cuda")
+        c = camera(cam)
+        _check(lib().vdi_preview_counters(self.handle, ctypes.byref(c), width, height, d_i, d_r,
+                                          ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(tl.data_ptr()),
+                                          ctypes.c_void_p(ts.data_ptr()), ctypes.c_void_p(tc.data_ptr()),
+                                          ctypes.c_void_p(st.data_ptr()), _stream_handle(stream)))
+        return out, tl, ts, tc, st
 
     def render_counters(self, cam, width: int, height: int, ess: bool = False, search: str = "window",
                         stream=None):

@@ -220,6 +220,41 @@ def test_random_preview_backward():
     assert err.max() <= TOL and (ref[:, 3] > 0).sum() >= 1000
 
 
+# ------------------------------------------------------------------ preview counters
+@pytest.mark.parametrize("theta,d_i", [(9.0, 2.0), (-27.0, 4.0)])
+def test_preview_counters_match_oracle(tiny, tiny_h, theta, d_i):
+    """The instrumented preview (the algorithmic bytes of preview frames):
+    its low-res image is the one vdi_render upsamples, its per-ray sample
+    counts equal the oracle's (Section 4.4 sampling rule) on every ray off a
+    tie, every composited supersegment lies in a sampled list, and the grid
+    cells read are those of the rays' walks (at least every cell holding a
+    sampled list's column)."""
+    cam = inputs.orbit_camera(theta)
+    W, H, d_r = 128, 96, 2.0
+    lo, tl, ts, tc, st = tiny_h.preview_counters(cam, W, H, d_i, d_r)
+    torch.cuda.synchronize()
+    w, h = oracle.lowres_size(W, H, d_i)
+    full = gpu_render(tiny_h, cam, W, H, d_i=d_i, d_r=d_r)
+    lo = lo.cpu().numpy().astype(np.float64)
+    assert np.abs(oracle.upsample(lo, W, H)[0] - full).max() <= 1e-6
+    pix = np.arange(w * h)
+    _, flags, ns = oracle.render_preview(tiny, cam, w, h, d_r, pixels=pix, aspect=W / H, samples=True)
+    st = st.cpu().numpy().reshape(-1, 2)
+    ok = flags == 0
+    assert ok.mean() > 0.9 and (ns[ok] > 0).sum() > 100
+    assert np.array_equal(st[ok, 0], ns[ok])
+    assert (st[:, 1] <= st[:, 0]).all()
+    tl, ts = tl.cpu().numpy().astype(bool), ts.cpu().numpy().astype(bool)
+    assert (ts.any(axis=0) <= tl).all() and ts.sum() > 0
+    assert int(ts.sum()) <= int(st[:, 1].sum())
+    k = tiny.grid_k
+    tc = tc.cpu().numpy().astype(bool)
+    cols = np.zeros(tc.shape[1:], bool)
+    ys, xs = np.nonzero(tl)
+    cols[ys // k, xs // k] = True
+    assert (cols <= tc.any(axis=0)).all()
+
+
 # ------------------------------------------------------------------ counters (B_alg)
 def test_counters_match_oracle(tiny, tiny_h):
     cam = inputs.orbit_camera(14.0)
