@@ -127,8 +127,11 @@ typedef struct {
  * Upload a VDI and build its count grid (Section 4.3: per grid cell, the
  * number of supersegments of its lists whose [f, b] overlaps the cell's depth
  * slice with positive length).  Copies every array: the caller may free them
- * on return.  Synchronous.  Device planes must be complete (their writers
- * finished) when it is called.  Writes *out only on success.
+ * on return.  Synchronous for the calling thread: the upload runs on a stream
+ * of its own, which is all it waits for, so work on the device's other
+ * streams (a server's batches, renders of other VDIs) goes on meanwhile.
+ * Device planes must be complete (their writers finished) when it is called.
+ * Writes *out only on success.
  * Errors: VDI_ERR_ARG (null pointers, sizes, N_S or grid shape out of range,
  * non-finite camera or AABB, formats, and with validate != 0 an invalid list),
  * VDI_ERR_OOM, VDI_ERR_HIP.
@@ -224,8 +227,15 @@ int vdi_get_grid(vdi_t v, uint32_t *host_out, size_t capacity_elems);
 int vdi_get_info(vdi_t v, vdi_info_t *info);
 
 /*
- * Synchronize outstanding work on the device, then free the VDI's device
- * memory.  NULL is a no-op.  Destroying the same handle twice is undefined.
+ * Wait for the work that reads the VDI, then free its device memory: the
+ * last render of v on each stream that rendered it (tracked for up to eight
+ * streams at a time; a ninth stream waits for the least recently used one
+ * when it renders), a replacement upload in progress, and requests on v that
+ * a server still holds (VDI_ERR_STATE, nothing freed, if they are not done
+ * within 60 s).  No device-wide synchronization is requested; the runtime's
+ * release of the device memory itself (hipFree) may still wait for the
+ * device.  NULL is a no-op.  Destroying the same handle twice, or while
+ * another thread renders it, is undefined.
  */
 int vdi_destroy(vdi_t v);
 

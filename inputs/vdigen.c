@@ -346,8 +346,8 @@ static int split_ray(const smp_t *s, int ns, double t0, double len, double gamma
  *   cam11: V_O camera (eye, target, up, fov_y_deg, near).
  *   W,H,NS: VDI resolution and max supersegments per list.
  *   tf: TF_RAMP or TF_KNOTS4.
- *   gamma_fixed > 0: fixed sensitivity; else per-ray bisection (Alg. S1) with
- *   gamma0 = 1e-5, [0, sqrt 3], delta = floor(0.15 NS), eps = 1e-6, <= 25 iters.
+ *   gamma_fixed > 0: fixed sensitivity; else a per-ray bracket search (Alg. S1) with
+ *   first trial 1e-5, bracket [0, sqrt 3], delta = floor(0.15 NS), width 1e-6, <= 25 trials.
  * Outputs (caller-allocated, zero-filled here):
  *   count[H*W] u8, depth[NS*H*W*2] f32, rgba[NS*H*W*4] f32,
  *   dvr[H*W*4] f64 (FP64 DVR composite of the same samples, premultiplied RGB + A; may be NULL),
@@ -416,29 +416,36 @@ int64_t vg_generate(int nx, int ny, int nz, int is_u16, const void *data, const 
                 if (gamma_fixed > 0.0) {
                     gamma = gamma_fixed;
                 } else {
-                    double low = 0.0, high = sqrt(3.0);
-                    gamma = 1e-5;
-                    int first = 1;
-                    for (int it = 0;; ++it) {
-                        int n = split_ray(sm, ns, t0, len, gamma, 0, NULL);
-                        int found = 0;
-                        if (fabs(high - low) < 1e-6) {
-                            found = 1;
-                            gamma = (n == 0) ? low : high;
-                        } else if (n > NS) {
-                            low = gamma;
-                        } else if (n < NS - delta) {
-                            high = gamma;
-                        } else {
-                            found = 1;
+                    /* The ray's sensitivity (supplement Alg. S1, with the bracket
+                     * updates read as in the design notes).  The count n(g) does not
+                     * grow with g on [0, sqrt 3]; wanted is N_S - delta <= n(g) <= N_S.
+                     * The trial g0 = 1e-5 stands whenever n(g0) <= N_S.  Otherwise
+                     * [lo, hi] brackets the answer, n(lo) > N_S and hi = sqrt 3 or
+                     * n(hi) < N_S - delta, and every further trial is its midpoint.
+                     * Once the bracket is narrower than 1e-6 the trial in hand ends
+                     * the search with hi (lo if that trial yields nothing); 25 trials
+                     * in all, then hi. */
+                    const double g0 = 1e-5;
+                    gamma = g0;
+                    if (split_ray(sm, ns, t0, len, g0, 0, NULL) > NS) {
+                        double lo = g0, hi = sqrt(3.0);
+                        int settled = 0;
+                        for (int trial = 2; trial <= 25 && !settled; ++trial) {
+                            const double g = 0.5 * (lo + hi);
+                            const int n = split_ray(sm, ns, t0, len, g, 0, NULL);
+                            if (hi - lo < 1e-6) {
+                                gamma = (n == 0) ? lo : hi;
+                                settled = 1;
+                            } else if (n > NS) {
+                                lo = g;
+                            } else if (n < NS - delta) {
+                                hi = g;
+                            } else {
+                                gamma = g;
+                                settled = 1;
+                            }
                         }
-                        if (first) {
-                            first = 0;
-                            if (n < NS) found = 1;
-                        }
-                        if (found) break;
-                        if (it + 1 >= 25) { gamma = high; break; }
-                        gamma = 0.5 * (low + high);
+                        if (!settled) gamma = hi;
                     }
                 }
                 if (gamma_out) gamma_out[li] = gamma;

@@ -8,9 +8,11 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "vdi_internal.h"
@@ -255,6 +257,7 @@ int render_impl(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, float D_I,
         hipError_t e2 = hipFreeAsync(lo, s);
         if (e == hipSuccess) e = e2;
     }
+    if (e == hipSuccess) e = vdi::note_use(v, s);
     if (e != hipSuccess) return hip_fail(e, "render launch");
     return VDI_OK;
 }
@@ -302,9 +305,13 @@ void free_set(vdi::VdiSet &S)
 void free_vdi(vdi_s *v)
 {
     if (!v) return;
+    if (v->copy) (void)hipStreamSynchronize(v->copy);
     free_set(v->cur);
     free_set(v->back);
-    if (v->stage) (void)hipFree(v->stage);
+    if (v->stage) (void)hipFreeAsync(v->stage, v->copy);
+    if (v->copy) (void)hipStreamSynchronize(v->copy);
+    for (int i = 0; i < vdi_s::kUseSlots; ++i)
+        if (v->use_ev[i]) (void)hipEventDestroy(v->use_ev[i]);
     if (v->start) (void)hipEventDestroy(v->start);
     if (v->ready) (void)hipEventDestroy(v->ready);
     if (v->copy) (void)hipStreamDestroy(v->copy);
@@ -398,6 +405,44 @@ uint64_t set_bytes_of(const vdi_desc *d)
            (cells + 31) / 32 * sizeof(uint32_t) + (uint64_t)(d->grid_nz + 1) * sizeof(float);
 }
 
+// Host-to-device copies of a VDI's arrays.  A copy from pageable host memory
+// waits for the device's other streams (measured: a create stalled behind a
+// server's running batch); copies from pinned memory are ordered on their
+// stream only.  Host arrays therefore go through two pinned halves of the
+// library, taken in turn: a half is refilled once the copy that last read it
+// has completed.  The halves are allocated on first use and kept.
+constexpr size_t kPinHalf = (size_t)32 << 20;
+std::mutex g_pin_mu;
+void *g_pin[2] = {nullptr, nullptr};
+hipEvent_t g_pin_ev[2] = {nullptr, nullptr};
+
+hipError_t h2d(void *dst, const void *src, size_t n, hipStream_t st)
+{
+    std::lock_guard<std::mutex> lock(g_pin_mu);
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+        if (!g_pin[k]) e = hipHostMalloc(&g_pin[k], kPinHalf, hipHostMallocDefault);
+        if (e == hipSuccess && !g_pin_ev[k]) e = hipEventCreateWithFlags(&g_pin_ev[k], hipEventDisableTiming);
+    }
+    static int k = 0;
+    for (size_t off = 0; off < n && e == hipSuccess; off += kPinHalf, k ^= 1) {
+        const size_t m = std::min(n - off, kPinHalf);
+        e = hipEventSynchronize(g_pin_ev[k]);
+        if (e != hipSuccess) break;
+        memcpy(g_pin[k], static_cast<const char *>(src) + off, m);
+        e = hipMemcpyAsync(static_cast<char *>(dst) + off, g_pin[k], m, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipEventRecord(g_pin_ev[k], st);
+    }
+    return e;
+}
+
+// A copy of a VDI array: device to device when the planes are on the device.
+hipError_t copy_in(void *dst, const void *src, size_t n, bool on_device, hipStream_t st)
+{
+    if (on_device) return hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToDevice, st);
+    return h2d(dst, src, n, st);
+}
+
 // Upload d into the set S on stream st: allocate S's buffers if it has none,
 // copy the count plane and slice boundaries, stage whole slot planes through
 // `stage` (stage_bytes) and scatter them into storage order (colour
@@ -449,9 +494,9 @@ hipError_t upload_set(vdi::VdiSet &S, const vdi_desc *d, const uint8_t *counts, 
     D.gbits = S.d_gbits;
     D.gz = S.d_gz;
     *what = "upload";
-    const hipMemcpyKind kind = d->planes_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-    e = hipMemcpyAsync(S.d_count, d->count, plane, kind, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(S.d_gz, gz.data(), gz.size() * sizeof(float), hipMemcpyHostToDevice, st);
+    const bool on_dev = d->planes_on_device != 0;
+    e = copy_in(S.d_count, d->count, plane, on_dev, st);
+    if (e == hipSuccess) e = h2d(S.d_gz, gz.data(), gz.size() * sizeof(float), st);
     const size_t colour_in = d->rgba_fmt_in == VDI_F32 ? 16 : 8;
     const uint64_t slots = std::max<uint64_t>(1, std::min<uint64_t>(ns, stage_bytes / (plane * 16)));
     for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
@@ -461,7 +506,7 @@ hipError_t upload_set(vdi::VdiSet &S, const vdi_desc *d, const uint8_t *counts, 
         for (uint64_t j0 = 0; j0 < ns && e == hipSuccess; j0 += slots) {
             const uint64_t nj = std::min(slots, ns - j0);
             // Stream order keeps the staging buffer from being refilled before it is scattered.
-            e = hipMemcpyAsync(stage, src + j0 * plane * esz, nj * plane * esz, kind, st);
+            e = copy_in(stage, src + j0 * plane * esz, nj * plane * esz, on_dev, st);
             if (e == hipSuccess)
                 e = vdi::launch_scatter_slots(stage, d->rgba_fmt_in, dep ? (void *)S.d_depth : S.d_rgba, d->rgba_fmt_store,
                                               dep, nj * plane, D, (int32_t)j0, st);
@@ -480,6 +525,27 @@ hipError_t upload_set(vdi::VdiSet &S, const vdi_desc *d, const uint8_t *counts, 
 }  // namespace
 
 namespace vdi {
+hipError_t note_use(vdi_s *v, hipStream_t stream)
+{
+    std::lock_guard<std::mutex> lock(v->mu);
+    int k = -1;
+    for (int i = 0; i < v->use_n; ++i)
+        if (v->use_st[i] == stream) k = i;
+    if (k < 0 && v->use_n < vdi_s::kUseSlots) k = v->use_n++;
+    if (k < 0) {
+        // More streams than slots: the least recently used one is waited for
+        // and its slot taken over.
+        k = 0;
+        for (int i = 1; i < vdi_s::kUseSlots; ++i)
+            if (v->use_tick[i] < v->use_tick[k]) k = i;
+        const hipError_t e = hipEventSynchronize(v->use_ev[k]);
+        if (e != hipSuccess) return e;
+    }
+    v->use_st[k] = stream;
+    v->use_tick[k] = ++v->use_clock;
+    return hipEventRecord(v->use_ev[k], stream);
+}
+
 int set_error(int code, const char *fmt, ...)
 {
     char buf[512];
@@ -596,13 +662,26 @@ int vdi_create(const vdi_desc *d, vdi_t *out)
     const uint64_t plane = (uint64_t)d->width * d->height;
     const uint64_t stage_bytes = std::max<uint64_t>(256ull << 20, plane * 16);
     void *stage = nullptr;
-    const char *what = "staging";
-    e = hipMalloc(&stage, stage_bytes);
-    if (e == hipSuccess) e = upload_set(v->cur, d, counts, ob, gz, 0, stage, stage_bytes, &what);
-    if (e == hipSuccess) what = "upload", e = hipDeviceSynchronize();
+    const char *what = "events";
+    for (int i = 0; i < vdi_s::kUseSlots && e == hipSuccess; ++i)
+        e = hipEventCreateWithFlags(&v->use_ev[i], hipEventDisableTiming);
+    // The upload runs on the VDI's own stream and only that stream is waited
+    // for: work on the device's other streams (a server's batches, other
+    // VDIs' renders) goes on meanwhile.  The staging buffer is stream-ordered
+    // on it (hipFree would wait for the whole device).  The planes come from
+    // hipMalloc: from the stream-ordered pool, growing it by a VDI's size
+    // waited for the device's other work as well (measured).
+    if (e == hipSuccess) what = "VDI stream", e = hipStreamCreateWithFlags(&v->copy, hipStreamNonBlocking);
+    hipStream_t st = v->copy;
+    if (e == hipSuccess) what = "staging", e = hipMallocAsync(&stage, stage_bytes, st);
+    if (e == hipSuccess) e = upload_set(v->cur, d, counts, ob, gz, st, stage, stage_bytes, &what);
     if (stage) {
-        const hipError_t ef = hipFree(stage);
+        const hipError_t ef = hipFreeAsync(stage, st);
         if (e == hipSuccess) e = ef;
+    }
+    if (st) {
+        const hipError_t es = hipStreamSynchronize(st);
+        if (e == hipSuccess) what = "upload", e = es;
     }
     if (e != hipSuccess) {
         rc = hip_fail(e, what);
@@ -644,13 +723,12 @@ int vdi_replace_begin(vdi_t v, const vdi_desc *d, void *stream)
     const uint64_t plane = (uint64_t)d->width * d->height;
     const char *what = "replacement set-up";
     hipError_t e = hipSetDevice(v->device);
-    if (e == hipSuccess && !v->copy) {
-        e = hipStreamCreateWithFlags(&v->copy, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&v->start, hipEventDisableTiming);
+    if (e == hipSuccess && !v->start) {
+        e = hipEventCreateWithFlags(&v->start, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&v->ready, hipEventDisableTiming);
         if (e == hipSuccess) {
             v->stage_bytes = std::max<uint64_t>(256ull << 20, plane * 16);
-            e = hipMalloc(&v->stage, v->stage_bytes);
+            e = hipMallocAsync(&v->stage, v->stage_bytes, v->copy);
         }
     }
     // The back set may be the one renders used before the last swap: the
@@ -723,6 +801,7 @@ int vdi_render_counters(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, co
     f.touched_slots = touched_slots;
     f.ray_stats = ray_stats;
     HIP_OR_FAIL(vdi::launch_render_exact(S.dev, f, true, static_cast<hipStream_t>(stream)), "counter render launch");
+    HIP_OR_FAIL(vdi::note_use(v, static_cast<hipStream_t>(stream)), "render bookkeeping");
     return VDI_OK;
 }
 
@@ -749,6 +828,7 @@ int vdi_preview_counters(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, f
     f.touched_cells = touched_cells;
     f.ray_stats = ray_stats;
     HIP_OR_FAIL(vdi::launch_render_preview(S.dev, f, true, static_cast<hipStream_t>(stream)), "counter preview launch");
+    HIP_OR_FAIL(vdi::note_use(v, static_cast<hipStream_t>(stream)), "render bookkeeping");
     return VDI_OK;
 }
 
@@ -788,9 +868,24 @@ int vdi_destroy(vdi_t v)
     g_err.clear();
     if (!v) return VDI_OK;
     hipError_t e = hipSetDevice(v->device);
-    if (e == hipSuccess) e = hipDeviceSynchronize();
+    // Wait for what reads v's buffers: its renders (the last one on each
+    // stream that rendered it), a replacement upload, and a server's requests.
+    {
+        std::lock_guard<std::mutex> lock(v->mu);
+        for (int i = 0; i < v->use_n && e == hipSuccess; ++i) e = hipEventSynchronize(v->use_ev[i]);
+    }
+    if (e == hipSuccess && v->copy) e = hipStreamSynchronize(v->copy);
+    for (int waited_ms = 0; e == hipSuccess && v->server_refs.load() > 0; ++waited_ms) {
+        if (waited_ms >= 60000)
+            return fail(VDI_ERR_STATE, "a server still holds %d requests on this VDI", v->server_refs.load());
+        std::this_thread::sleep_for(std::chrono::milliseconds(1));
+    }
+    if (e != hipSuccess) {
+        const int rc = hip_fail(e, "waiting for work on the VDI before destroy");
+        free_vdi(v);
+        return rc;
+    }
     free_vdi(v);
-    if (e != hipSuccess) return hip_fail(e, "synchronize before destroy");
     return VDI_OK;
 }
 

@@ -267,6 +267,37 @@ __host__ __device__ inline int sample_count(const GenParams &G, double t0, doubl
     return N;
 }
 
+// Sensitivity of one ray (supplement Alg. S1; bracket updates as read in
+// the design notes).  count(g), the ray's supersegments at sensitivity g,
+// does not grow with g; the search wants N_S - delta <= count(g) <= N_S.
+// A first trial at 1e-5 stands if it gives at most N_S.  Otherwise the
+// bracket (lo, hi) always has count(lo) > N_S, and hi is sqrt 3 or gives
+// fewer than N_S - delta; each further trial halves it.  A bracket narrower
+// than 1e-6 ends the search at hi, or at lo if the trial in hand gives no
+// supersegment; so does the 25th trial.
+template <typename Count>
+__host__ __device__ double search_gamma(int NS, int delta, Count count)
+{
+#pragma clang fp contract(off)
+    double lo = 1e-5;
+    if (count(lo) <= NS) return lo;
+    double hi = sqrt(3.0);
+    int trials = 1;
+    for (;;) {
+        const double g = 0.5 * (lo + hi);
+        const int c = count(g);
+        ++trials;
+        if (hi - lo < 1e-6) return c == 0 ? lo : hi;
+        if (c > NS)
+            lo = g;
+        else if (c < NS - delta)
+            hi = g;
+        else
+            return g;
+        if (trials == 25) return hi;
+    }
+}
+
 // The whole generation of list (px, py): ray, samples, gamma, supersegments.
 __host__ __device__ inline void gen_ray(const GenParams &G, const SampleCache &C, int px, int py, uint8_t *count,
                                         float2 *depth, float4 *rgba, double *gamma_out)
@@ -294,36 +325,9 @@ __host__ __device__ inline void gen_ray(const GenParams &G, const SampleCache &C
         if (G.gamma > 0.0) {
             gamma = G.gamma;
         } else {
-            // Supplement Alg. S1: bisection on gamma until the ray yields between
-            // N_S - delta and N_S supersegments (the first trial, gamma = 1e-5,
-            // is accepted whenever it already yields fewer than N_S).
-            double lo_g = 0.0, hi_g = sqrt(3.0);
-            gamma = 1e-5;
-            bool first = true;
-            for (int it = 0;; ++it) {
-                const int c = split_ray<false>(G, C, d, cth, t0, len, ns, gamma, 0, li, plane, nullptr, nullptr);
-                bool found = false;
-                if (fabs(hi_g - lo_g) < 1e-6) {
-                    found = true;
-                    gamma = (c == 0) ? lo_g : hi_g;
-                } else if (c > G.NS) {
-                    lo_g = gamma;
-                } else if (c < G.NS - G.delta) {
-                    hi_g = gamma;
-                } else {
-                    found = true;
-                }
-                if (first) {
-                    first = false;
-                    if (c < G.NS) found = true;
-                }
-                if (found) break;
-                if (it + 1 >= 25) {
-                    gamma = hi_g;
-                    break;
-                }
-                gamma = 0.5 * (lo_g + hi_g);
-            }
+            gamma = search_gamma(G.NS, G.delta, [&](double g) {
+                return split_ray<false>(G, C, d, cth, t0, len, ns, g, 0, li, plane, nullptr, nullptr);
+            });
         }
         n = split_ray<true>(G, C, d, cth, t0, len, ns, gamma, G.NS, li, plane, depth, rgba);
     }

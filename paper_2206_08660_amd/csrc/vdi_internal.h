@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -193,7 +194,7 @@ struct vdi_s {
     int device = 0;
     uint64_t set_bytes = 0;          // device bytes of one set
     std::mutex mu;                   // guards cur, back and the replacement state
-    hipStream_t copy = nullptr;      // replacement uploads
+    hipStream_t copy = nullptr;      // the VDI's own stream: uploads (create, replacement) and its stream-ordered memory
     hipEvent_t start = nullptr;      // caller's stream reached vdi_replace_begin
     hipEvent_t ready = nullptr;      // the pending upload has finished
     void *stage = nullptr;           // staging buffer of replacement uploads
@@ -201,6 +202,16 @@ struct vdi_s {
     bool pending = false;            // a replacement was started and not yet swapped in
     bool enqueued = false;           // ... and all of its work is on the copy stream
     std::vector<float> gz_host;      // slice boundaries of the pending upload
+    // Renders in flight, for vdi_destroy: an event recorded after the last
+    // render of v on each of up to kUseSlots streams (created with v, so a
+    // render allocates nothing), and the requests a server holds on v.
+    static constexpr int kUseSlots = 8;
+    hipEvent_t use_ev[kUseSlots] = {};
+    hipStream_t use_st[kUseSlots] = {};
+    uint64_t use_tick[kUseSlots] = {};
+    uint64_t use_clock = 0;
+    int use_n = 0;
+    std::atomic<int> server_refs{0};
 };
 
 namespace vdi {
@@ -210,6 +221,8 @@ namespace vdi {
 int set_error(int code, const char *fmt, ...);
 int hip_error(hipError_t e, const char *what);
 int check_render_args(vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, float D_I, float D_R, const float *out);
+// Record that v's buffers are read by work enqueued on `stream` (see vdi_s).
+hipError_t note_use(vdi_s *v, hipStream_t stream);
 // Ray-grid size for downsampling factor D_I.
 void lowres_size(int32_t W, int32_t H, float D_I, int32_t *w, int32_t *h);
 // The library's stream-ordered memory pool on `device` (freed blocks are kept

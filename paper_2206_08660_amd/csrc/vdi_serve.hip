@@ -55,6 +55,7 @@ constexpr uint64_t kBatchUpTiles = 1ull << 22;
 
 // An admitted request.
 struct Request {
+    vdi_s *owner = nullptr;  // the VDI rendered (its server_refs counts this request)
     BatchJob job;       // tile0 is set when its batch is built
     int32_t fmt = VDI_F32;
     bool preview = false, down = false;
@@ -187,6 +188,7 @@ void finish_batch(vdi_server_s *s, Lane &L)
         auto it = s->requests.find(tk);
         Request &r = it->second;
         if (r.lowres) s->free_lowres.emplace(r.lowres_bytes, r.lowres);
+        r.owner->server_refs--;
         s->st.bytes_in_flight -= r.bytes;
         s->st.inflight--;
         s->st.completed++;
@@ -241,6 +243,8 @@ void release(vdi_server_s *s)
         if (L.d_up) (void)hipFree(L.d_up);
     }
     for (float4 *p : s->all_lowres) (void)hipFree(p);
+    // Requests never retired (the server failed): their VDIs are not read any more.
+    for (auto &kv : s->requests) kv.second.owner->server_refs--;
     delete s;
 }
 
@@ -361,6 +365,8 @@ int vdi_server_submit(vdi_server_t s, vdi_t v, const vdi_camera *cam, int32_t W,
     if (down) r.up = vdi::UpsampleJob{r.lowres, reinterpret_cast<float4 *>(out), w, h, W, H, 0, vdi::upsample_tiles(W, H)};
     r.bytes = bytes;
     r.lowres_bytes = lowres_bytes;
+    r.owner = v;
+    v->server_refs++;
     const uint64_t t = s->next_ticket++;
     s->requests.emplace(t, r);
     s->queue.push_back(t);

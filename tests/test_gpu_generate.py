@@ -166,3 +166,78 @@ def test_generated_vdi_is_rendered_without_a_host_copy(tiny_vol):
                 assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
     with pytest.raises(V.VdiError):
         V.Vdi(dev0, validate=True)   # list validation needs host planes
+
+
+# ------------------------------------------------------- pins not through the CPU generator
+from tests import slabs  # noqa: E402
+from tests.synth import composite_at_vo  # noqa: E402
+
+
+@pytest.mark.parametrize("side", [-1, 1])
+def test_eq1_two_layers_closed_form_on_gpu(side):
+    """Eq. 1 at an intermediate gamma on the GPU: the centre ray of a
+    two-layer volume splits just below d = |c1 a1 - c2 a2| and merges just
+    above it, with closed-form faces, colours and opacities."""
+    runs = slabs.run(slabs.TWO)
+    g = slabs.eq1_distance(runs[:1], slabs.TWO[1][0]) * (1.0 + side * 1e-6)
+    count, depth, rgba, _ = gpu_generate(to_device(slabs.volume(slabs.TWO)), slabs.camera(), slabs.W, slabs.H, 4,
+                                         inputs.TF_RAMP, g)
+    slabs.check(count, depth, rgba, slabs.expected(slabs.TWO, g, 4))
+
+
+@pytest.mark.parametrize("gamma,n", slabs.THREE_CASES)
+def test_eq1_three_layers_on_gpu(gamma, n):
+    count, depth, rgba, _ = gpu_generate(to_device(slabs.volume(slabs.THREE)), slabs.camera(), slabs.W, slabs.H, 8,
+                                         inputs.TF_RAMP, gamma)
+    want = slabs.expected(slabs.THREE, gamma, 8)
+    assert len(want) == n
+    slabs.check(count, depth, rgba, want)
+
+
+def test_gamma_search_end_states_on_gpu():
+    """The bracket search on layered rays (closed forms as in the CPU
+    suite): the first trial stands at N_S = 2, the first midpoint at N_S = 1,
+    the fourth midpoint for three layers at N_S = 2."""
+    cam = slabs.camera()
+    c, d, r, g = gpu_generate(to_device(slabs.volume(slabs.TWO)), cam, slabs.W, slabs.H, 2, inputs.TF_RAMP, 0.0)
+    assert g[slabs.CY, slabs.CX] == 1e-5 and c[slabs.CY, slabs.CX] == 2
+    c, d, r, g = gpu_generate(to_device(slabs.volume(slabs.TWO)), cam, slabs.W, slabs.H, 1, inputs.TF_RAMP, 0.0)
+    assert abs(g[slabs.CY, slabs.CX] - 0.5 * (1e-5 + 3.0 ** 0.5)) < 1e-12
+    slabs.check(c, d, r, slabs.expected(slabs.TWO, 1.0, 1))
+    c, d, r, g = gpu_generate(to_device(slabs.volume(slabs.THREE)), cam, slabs.W, slabs.H, 2, inputs.TF_RAMP, 0.0)
+    assert abs(g[slabs.CY, slabs.CX] - slabs.searched_gamma_three()) < 1e-12
+    slabs.check(c, d, r, slabs.expected(slabs.THREE, float(g[slabs.CY, slabs.CX]), 2))
+
+
+def test_720p_generated_vdi_invariants_on_gpu():
+    """On the GPU's own 720p VDI (N_S = 20): its composite from V_O equals
+    the GPU's FP64 DVR of the volume within 2e-6 (compositing inside a
+    supersegment is exact, smearing included); every count is at most N_S;
+    every searched ray ends with its first trial (gamma = 1e-5) or with a
+    count in [N_S - delta, N_S], but for the rare rays whose bracket closed
+    between two counts (at most 0.1% of the rays that hit)."""
+    from paper_2206_08660_amd import vdi as V
+    spec = inputs.WORKLOADS["720p"]
+    vol = inputs.make_volume(spec)
+    dvol = to_device(vol)
+    del vol
+    nz, ny, nx = dvol.shape
+    bmin, bmax = inputs.aabb_for((nx, ny, nz))
+    W, H, ns = spec["width"], spec["height"], spec["ns"]
+    cam = inputs.orbit_camera(0.0)
+    count, depth, rgba, gam = gpu_generate(dvol, cam, W, H, ns, spec["tf"], 0.0)
+    dvr = V.dvr(dvol, bmin, bmax, cam, W, H, tf="knots4", precision="f64")
+    torch.cuda.synchronize()
+    dvr = dvr.cpu().numpy().astype(np.float64)
+    v = inputs.VDI(width=W, height=H, ns=ns, camera=cam, bmin=bmin, bmax=bmax, count=count, depth=depth, rgba=rgba)
+    comp = composite_at_vo(v)
+    err = float(np.abs(comp - dvr).max())
+    say(f"[gpu] 720p generated VDI: composite vs FP64 DVR max |d| = {err:.2e}")
+    assert err <= 2e-6
+    assert (count <= ns).all()
+    delta = int(0.15 * ns)
+    hit = count > 0
+    first = gam == 1e-5
+    ok = first | ((count >= ns - delta) & (count <= ns))
+    assert (hit & ~ok).sum() <= 1e-3 * hit.sum()
+    assert hit.sum() > 100000

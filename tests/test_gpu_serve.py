@@ -165,3 +165,43 @@ def test_open_loop_trace_small(sources, handles):
         hi = int(which[i])
         rgba = None if hi == 0 else oracle.dequant_f16(sources[1].rgba)
         oracle_check(sources[hi], rgba, cam, W, H, di, dr, img, n=800, seed=i)
+
+
+def test_vdi_create_and_destroy_beside_a_running_server(sources, handles):
+    """With a long request of another VDI on the server (a D_R = 0.002
+    preview of the 720p VDI, about 70 ms), a new VDI is created, rendered on a
+    side stream and destroyed with that render still in flight (vdi_destroy
+    waits for it): the render matches the oracle and the served image the
+    single render.  That vdi_create waits only for its own upload stream is
+    checked in a child process given sixteen hardware queues
+    (serve_create_child.py): with the default four, the VDI's stream may share
+    a queue with the server's busy one."""
+    import os
+    import subprocess
+    from paper_2206_08660_amd import serve
+    from paper_2206_08660_amd import vdi as V
+    cam = inputs.orbit_camera(40.0)
+    with serve.Server(2 ** 34, max_inflight=8) as srv:
+        buf = torch.empty((720, 1280, 4), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        t = srv.submit(handles[1], cam, 1280, 720, 1.0, 0.002, buf)
+        assert t is not None
+        h = V.Vdi(sources[0])
+        side = torch.cuda.Stream()
+        with torch.cuda.stream(side):
+            img = h.render(inputs.orbit_camera(9.0), 128, 128, stream=side)
+        h.close()   # waits for the render on `side`
+        side.synchronize()
+        ref = oracle.render_exact(sources[0], inputs.orbit_camera(9.0), 128, 128)
+        assert np.abs(img.cpu().numpy() - ref).max() <= TOL
+        srv.drain()
+        assert srv.poll(t)
+    single = handles[1].render(cam, 1280, 720, d_r=0.002)
+    torch.cuda.synchronize()
+    assert torch.equal(single, buf)
+
+    env = dict(os.environ, GPU_MAX_HW_QUEUES="16")
+    child = os.path.join(os.path.dirname(os.path.abspath(__file__)), "serve_create_child.py")
+    r = subprocess.run([sys.executable, child], capture_output=True, text=True, timeout=180, env=env)
+    say(r.stdout.strip())
+    assert r.returncode == 0 and "create: ok" in r.stdout, r.stdout + r.stderr

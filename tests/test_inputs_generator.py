@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import inputs
+from tests import slabs
 
 
 def _structure_ok(v: inputs.VDI):
@@ -152,3 +153,53 @@ def test_vdi_byte_sizes_match_paper():
                        count=np.zeros((1, 1), np.uint8), depth=np.zeros((1,), np.float32),
                        rgba=np.zeros((1,), np.float32), grid_z=np.zeros(21, np.float32))
         assert abs(v.nbytes_fp32 / 2 ** 20 - mib) < 1.0   # the paper rounds (949.2 -> "950")
+
+
+# ---------------------------------------------------------------- closed forms
+@pytest.mark.parametrize("side", [-1, 1])
+def test_eq1_two_layers_closed_form(side):
+    """Eq. 1 at an intermediate gamma: the centre ray meets 16 samples of
+    v = 0.8 then 16 of v = 0.3; their distance d = |c1 a1 - c2 a2| = 0.1375 is
+    the only one that can split it.  Just below d: two supersegments, each
+    layer's own colour and opacity 1 - (1 - a)^16, faces at depths 1.0, 1.5,
+    2.0; just above: one, their front-to-back merge."""
+    runs = slabs.run(slabs.TWO)
+    d = slabs.eq1_distance(runs[:1], slabs.TWO[1][0])
+    assert abs(d - 0.13747) < 1e-4
+    g = d * (1.0 + side * 1e-6)
+    v = inputs.generate_vdi(slabs.volume(slabs.TWO), slabs.camera(), slabs.W, slabs.H, 4, inputs.TF_RAMP, gamma=g)
+    want = slabs.expected(slabs.TWO, g, 4)
+    assert len(want) == (2 if side < 0 else 1)
+    slabs.check(v.count, v.depth, v.rgba, want)
+
+
+@pytest.mark.parametrize("gamma,n", slabs.THREE_CASES)
+def test_eq1_three_layers_normalised_open_supersegment(gamma, n):
+    """With three layers the distance to the third depends on what the open
+    supersegment holds: the second layer alone (0.0591) or the first two
+    merged (0.1126, their opacity normalised to one sample length, the
+    reading under which a constant run never splits).  Counts 3, 2, 2, 1 at
+    gamma 0.05, 0.08, 0.105, 0.2, with the closed-form faces and colours."""
+    v = inputs.generate_vdi(slabs.volume(slabs.THREE), slabs.camera(), slabs.W, slabs.H, 8, inputs.TF_RAMP,
+                            gamma=gamma)
+    want = slabs.expected(slabs.THREE, gamma, 8)
+    assert len(want) == n
+    slabs.check(v.count, v.depth, v.rgba, want)
+
+
+def test_gamma_search_end_states_closed_form():
+    """The bracket search (supplement Alg. S1) on layered rays: with two
+    layers and N_S = 2 the first trial (1e-5, two supersegments) stands; with
+    N_S = 1 it gives too many, and the first midpoint (1e-5 + sqrt 3) / 2,
+    above d, gives one and stands.  With three layers and N_S = 2 the fourth
+    midpoint stands (searched_gamma_three)."""
+    cam = slabs.camera()
+    v2 = inputs.generate_vdi(slabs.volume(slabs.TWO), cam, slabs.W, slabs.H, 2, inputs.TF_RAMP, gamma=0.0)
+    assert v2.gamma[slabs.CY, slabs.CX] == 1e-5 and v2.count[slabs.CY, slabs.CX] == 2
+    v1 = inputs.generate_vdi(slabs.volume(slabs.TWO), cam, slabs.W, slabs.H, 1, inputs.TF_RAMP, gamma=0.0)
+    assert abs(v1.gamma[slabs.CY, slabs.CX] - 0.5 * (1e-5 + math.sqrt(3.0))) < 1e-12
+    slabs.check(v1.count, v1.depth, v1.rgba, slabs.expected(slabs.TWO, 1.0, 1))
+    v3 = inputs.generate_vdi(slabs.volume(slabs.THREE), cam, slabs.W, slabs.H, 2, inputs.TF_RAMP, gamma=0.0)
+    g = v3.gamma[slabs.CY, slabs.CX]
+    assert abs(g - slabs.searched_gamma_three()) < 1e-12
+    slabs.check(v3.count, v3.depth, v3.rgba, slabs.expected(slabs.THREE, g, 2))
