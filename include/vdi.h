@@ -442,6 +442,8 @@ typedef struct {
     int32_t inflight, peak_inflight;  /* admitted and not yet done */
     int32_t queued;         /* admitted, waiting for a free stream */
     int32_t peak_batch;     /* most requests in one batch */
+    uint64_t paced_completed;  /* requests of paced sessions done */
+    uint64_t deadlines_met;    /* ... of them within their session's target frame time */
 } vdi_server_stats;
 
 /*
@@ -466,6 +468,22 @@ int vdi_server_create(uint64_t hbm_budget_bytes, int32_t max_inflight, int32_t s
  */
 int vdi_server_submit(vdi_server_t s, vdi_t v, const vdi_camera *cam_VN, int32_t width, int32_t height, float D_I,
                       float D_R, float *out, uint64_t *ticket);
+
+/*
+ * Submit a request of a paced session (the frame-time control of Section
+ * 4.4, which the paper's remote client runs with a PI controller on D_I,
+ * Section 6): the request is rendered at the session's current D_I (written
+ * to *D_I_used; D_R and the other arguments as in vdi_server_submit), and
+ * when it is done the server feeds its latency, from submission to
+ * completion in ms, to the session's controller, so that the session's next
+ * request gets the next D_I.  The session's target frame time is the
+ * request's deadline (counted in deadlines_met).  The session must outlive
+ * its requests, and must not be updated by its owner while the server holds
+ * one of them.  Errors: those of vdi_server_submit, VDI_ERR_ARG for a null
+ * session or D_I_used.
+ */
+int vdi_server_submit_paced(vdi_server_t s, vdi_t v, const vdi_camera *cam_VN, int32_t width, int32_t height,
+                            vdi_pace_t session, float D_R, float *out_rgba, uint64_t *ticket, float *D_I_used);
 
 /* *done = 1 once the request's image is complete and visible to later work.
  * A failed batch (a HIP error) makes this and every later call return VDI_ERR_HIP. */

@@ -525,6 +525,25 @@ hipError_t upload_set(vdi::VdiSet &S, const vdi_desc *d, const uint8_t *counts, 
 }  // namespace
 
 namespace vdi {
+// PI control of x = ln D_I on the error e = ln(frame / target), velocity
+// form: x += kp (e - e_prev) + ki e, clamped to [ln D_I_min, ln D_I_max].
+double pace_feed(vdi_pace_s *p, double frame_ms)
+{
+    std::lock_guard<std::mutex> lock(p->mu);
+    const double e = log(frame_ms / p->target);
+    const double de = p->first ? 0.0 : e - p->e_prev;
+    p->x = std::min(p->xmax, std::max(p->xmin, p->x + p->kp * de + p->ki * e));
+    p->e_prev = e;
+    p->first = false;
+    return exp(p->x);
+}
+
+double pace_d_i(vdi_pace_s *p)
+{
+    std::lock_guard<std::mutex> lock(p->mu);
+    return exp(p->x);
+}
+
 hipError_t note_use(vdi_s *v, hipStream_t stream)
 {
     std::lock_guard<std::mutex> lock(v->mu);
@@ -586,10 +605,6 @@ uint64_t vdi_plane_bytes(int32_t width, int32_t height, int32_t n_s, int32_t fmt
     return plane + vdi::plane_elems(width, height, n_s) * (8 + colour);
 }
 
-struct vdi_pace_s {
-    double target, kp, ki, xmin, xmax, x, e_prev;
-    bool first;
-};
 
 int vdi_pace_create(float target_ms, float kp, float ki, float D_I_min, float D_I_max, float D_I_start,
                     vdi_pace_t *out)
@@ -620,12 +635,7 @@ int vdi_pace_update(vdi_pace_t p, float frame_ms, float *next_D_I)
     g_err.clear();
     if (!p || !next_D_I) return fail(VDI_ERR_ARG, "null argument");
     if (!isfinite(frame_ms) || !(frame_ms > 0.0f)) return fail(VDI_ERR_ARG, "frame_ms must be > 0");
-    const double e = log((double)frame_ms / p->target);
-    const double de = p->first ? 0.0 : e - p->e_prev;
-    p->x = std::min(p->xmax, std::max(p->xmin, p->x + p->kp * de + p->ki * e));
-    p->e_prev = e;
-    p->first = false;
-    *next_D_I = (float)exp(p->x);
+    *next_D_I = (float)vdi::pace_feed(p, frame_ms);
     return VDI_OK;
 }
 

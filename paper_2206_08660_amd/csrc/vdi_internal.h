@@ -214,7 +214,20 @@ struct vdi_s {
     std::atomic<int> server_refs{0};
 };
 
+// Frame-time controller of a session (vdi_pace_*): its state is shared
+// between the caller and a server's scheduler thread, hence the lock.
+struct vdi_pace_s {
+    double target, kp, ki, xmin, xmax, x, e_prev;
+    bool first;
+    std::mutex mu;
+};
+
 namespace vdi {
+
+// Feed a frame time (ms) to a pace controller; returns the next D_I.
+double pace_feed(vdi_pace_s *p, double frame_ms);
+// The controller's current D_I.
+double pace_d_i(vdi_pace_s *p);
 
 // Host helpers shared by the render and serving entry points (vdi_api.hip).
 // Each returns VDI_OK or an error code after recording the reason.

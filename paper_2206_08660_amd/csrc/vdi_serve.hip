@@ -56,6 +56,8 @@ constexpr uint64_t kBatchUpTiles = 1ull << 22;
 // An admitted request.
 struct Request {
     vdi_s *owner = nullptr;  // the VDI rendered (its server_refs counts this request)
+    vdi_pace_s *pace = nullptr;  // session fed the request's latency when it is done (paced requests)
+    std::chrono::steady_clock::time_point t_submit;
     BatchJob job;       // tile0 is set when its batch is built
     int32_t fmt = VDI_F32;
     bool preview = false, down = false;
@@ -189,6 +191,14 @@ void finish_batch(vdi_server_s *s, Lane &L)
         Request &r = it->second;
         if (r.lowres) s->free_lowres.emplace(r.lowres_bytes, r.lowres);
         r.owner->server_refs--;
+        if (r.pace) {
+            // The request's latency is the session's frame time.
+            const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                                         r.t_submit).count();
+            s->st.paced_completed++;
+            if (ms <= r.pace->target) s->st.deadlines_met++;
+            pace_feed(r.pace, std::max(ms, 1e-3));
+        }
         s->st.bytes_in_flight -= r.bytes;
         s->st.inflight--;
         s->st.completed++;
@@ -251,56 +261,10 @@ void release(vdi_server_s *s)
 }  // namespace
 }  // namespace vdi
 
-extern "C" {
-
-int vdi_server_create(uint64_t hbm_budget_bytes, int32_t max_inflight, int32_t streams, vdi_server_t *out)
-{
-    if (!out) return vdi::set_error(VDI_ERR_ARG, "null output");
-    *out = nullptr;
-    if (hbm_budget_bytes == 0) return vdi::set_error(VDI_ERR_ARG, "hbm_budget_bytes must be > 0");
-    if (max_inflight < 1 || max_inflight > vdi::kMaxSlots)
-        return vdi::set_error(VDI_ERR_ARG, "max_inflight must be in [1, %d]", vdi::kMaxSlots);
-    if (streams < 0 || streams > vdi::kMaxStreams)
-        return vdi::set_error(VDI_ERR_ARG, "streams must be in [0, %d]", vdi::kMaxStreams);
-    vdi_server_s *s = new (std::nothrow) vdi_server_s();
-    if (!s) return vdi::set_error(VDI_ERR_OOM, "host allocation");
-    hipError_t e = hipGetDevice(&s->device);
-    if (e != hipSuccess) {
-        delete s;
-        return vdi::hip_error(e, "hipGetDevice");
-    }
-    s->budget = hbm_budget_bytes;
-    s->max_inflight = max_inflight;
-    s->lanes.resize(streams ? streams : vdi::kDefaultStreams);
-    for (vdi::Lane &L : s->lanes) {
-        const char *what = "stream";
-        e = hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking);
-        if (e == hipSuccess) what = "event", e = hipEventCreateWithFlags(&L.done, hipEventDisableTiming);
-        if (e == hipSuccess)
-            what = "job table", e = hipHostMalloc((void **)&L.h_jobs, sizeof(vdi::BatchJob) * vdi::kMaxBatch, 0);
-        if (e == hipSuccess)
-            what = "job table", e = hipHostMalloc((void **)&L.h_up, sizeof(vdi::UpsampleJob) * vdi::kMaxBatch, 0);
-        if (e == hipSuccess) what = "job table", e = hipMalloc((void **)&L.d_jobs, sizeof(vdi::BatchJob) * vdi::kMaxBatch);
-        if (e == hipSuccess)
-            what = "job table", e = hipMalloc((void **)&L.d_up, sizeof(vdi::UpsampleJob) * vdi::kMaxBatch);
-        if (e != hipSuccess) {
-            const int rc = vdi::hip_error(e, what);
-            vdi::release(s);
-            return rc;
-        }
-    }
-    try {
-        s->scheduler = std::thread(vdi::run_scheduler, s);
-    } catch (...) {
-        vdi::release(s);
-        return vdi::set_error(VDI_ERR_OOM, "scheduler thread");
-    }
-    *out = s;
-    return VDI_OK;
-}
-
-int vdi_server_submit(vdi_server_t s, vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, float D_I, float D_R,
-                      float *out, uint64_t *ticket)
+namespace vdi {
+namespace {
+int submit(vdi_server_t s, vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, float D_I, float D_R, float *out,
+           uint64_t *ticket, vdi_pace_s *pace)
 {
     if (!s || !ticket) return vdi::set_error(VDI_ERR_ARG, "null argument");
     int rc = vdi::check_render_args(v, cam, W, H, D_I, D_R, out);
@@ -366,6 +330,8 @@ int vdi_server_submit(vdi_server_t s, vdi_t v, const vdi_camera *cam, int32_t W,
     r.bytes = bytes;
     r.lowres_bytes = lowres_bytes;
     r.owner = v;
+    r.pace = pace;
+    r.t_submit = std::chrono::steady_clock::now();
     v->server_refs++;
     const uint64_t t = s->next_ticket++;
     s->requests.emplace(t, r);
@@ -379,6 +345,73 @@ int vdi_server_submit(vdi_server_t s, vdi_t v, const vdi_camera *cam, int32_t W,
     s->wake.notify_one();
     *ticket = t;
     return VDI_OK;
+}
+}  // namespace
+}  // namespace vdi
+
+extern "C" {
+
+int vdi_server_create(uint64_t hbm_budget_bytes, int32_t max_inflight, int32_t streams, vdi_server_t *out)
+{
+    if (!out) return vdi::set_error(VDI_ERR_ARG, "null output");
+    *out = nullptr;
+    if (hbm_budget_bytes == 0) return vdi::set_error(VDI_ERR_ARG, "hbm_budget_bytes must be > 0");
+    if (max_inflight < 1 || max_inflight > vdi::kMaxSlots)
+        return vdi::set_error(VDI_ERR_ARG, "max_inflight must be in [1, %d]", vdi::kMaxSlots);
+    if (streams < 0 || streams > vdi::kMaxStreams)
+        return vdi::set_error(VDI_ERR_ARG, "streams must be in [0, %d]", vdi::kMaxStreams);
+    vdi_server_s *s = new (std::nothrow) vdi_server_s();
+    if (!s) return vdi::set_error(VDI_ERR_OOM, "host allocation");
+    hipError_t e = hipGetDevice(&s->device);
+    if (e != hipSuccess) {
+        delete s;
+        return vdi::hip_error(e, "hipGetDevice");
+    }
+    s->budget = hbm_budget_bytes;
+    s->max_inflight = max_inflight;
+    s->lanes.resize(streams ? streams : vdi::kDefaultStreams);
+    for (vdi::Lane &L : s->lanes) {
+        const char *what = "stream";
+        e = hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking);
+        if (e == hipSuccess) what = "event", e = hipEventCreateWithFlags(&L.done, hipEventDisableTiming);
+        if (e == hipSuccess)
+            what = "job table", e = hipHostMalloc((void **)&L.h_jobs, sizeof(vdi::BatchJob) * vdi::kMaxBatch, 0);
+        if (e == hipSuccess)
+            what = "job table", e = hipHostMalloc((void **)&L.h_up, sizeof(vdi::UpsampleJob) * vdi::kMaxBatch, 0);
+        if (e == hipSuccess) what = "job table", e = hipMalloc((void **)&L.d_jobs, sizeof(vdi::BatchJob) * vdi::kMaxBatch);
+        if (e == hipSuccess)
+            what = "job table", e = hipMalloc((void **)&L.d_up, sizeof(vdi::UpsampleJob) * vdi::kMaxBatch);
+        if (e != hipSuccess) {
+            const int rc = vdi::hip_error(e, what);
+            vdi::release(s);
+            return rc;
+        }
+    }
+    try {
+        s->scheduler = std::thread(vdi::run_scheduler, s);
+    } catch (...) {
+        vdi::release(s);
+        return vdi::set_error(VDI_ERR_OOM, "scheduler thread");
+    }
+    *out = s;
+    return VDI_OK;
+}
+
+
+int vdi_server_submit(vdi_server_t s, vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, float D_I, float D_R,
+                      float *out, uint64_t *ticket)
+{
+    return vdi::submit(s, v, cam, W, H, D_I, D_R, out, ticket, nullptr);
+}
+
+int vdi_server_submit_paced(vdi_server_t s, vdi_t v, const vdi_camera *cam, int32_t W, int32_t H, vdi_pace_t session,
+                            float D_R, float *out, uint64_t *ticket, float *D_I_used)
+{
+    if (!session || !D_I_used) return vdi::set_error(VDI_ERR_ARG, "null argument");
+    const float D_I = (float)vdi::pace_d_i(session);
+    const int rc = vdi::submit(s, v, cam, W, H, D_I, D_R, out, ticket, session);
+    if (rc == VDI_OK) *D_I_used = D_I;
+    return rc;
 }
 
 int vdi_server_poll(vdi_server_t s, uint64_t ticket, int *done)
@@ -415,6 +448,7 @@ int vdi_server_reset_stats(vdi_server_t s)
     std::lock_guard<std::mutex> lock(s->mu);
     vdi_server_stats &st = s->st;
     st.submitted = st.completed = st.rejected_budget = st.rejected_slots = st.batches = 0;
+    st.paced_completed = st.deadlines_met = 0;
     st.peak_bytes_in_flight = st.bytes_in_flight;
     st.peak_inflight = st.inflight;
     st.peak_batch = 0;

@@ -27,6 +27,12 @@ class Pace:
         self.d_i = nd.value
         return self.d_i
 
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if self._h is None:
+            raise V.VdiError(V.VDI_ERR_STATE, "pace controller already destroyed")
+        return self._h
+
     def close(self):
         if self._h is not None:
             h, self._h = self._h, None

@@ -28,6 +28,20 @@ class Server:
         V._check(rc)
         return t.value
 
+    def submit_paced(self, vdi: "V.Vdi", cam, width: int, height: int, session, d_r: float, out):
+        """A request of a paced session (vdi_server_submit_paced): (ticket,
+        D_I used), or None when it does not fit the budget or slots now.
+        `session` is a pace.Pace whose controller the server feeds."""
+        c = V.camera(cam)
+        t = ctypes.c_uint64()
+        d_i = ctypes.c_float()
+        rc = V.lib().vdi_server_submit_paced(self._h, vdi.handle, ctypes.byref(c), width, height, session.handle,
+                                             d_r, ctypes.c_void_p(out.data_ptr()), ctypes.byref(t), ctypes.byref(d_i))
+        if rc == V.VDI_ERR_BUDGET:
+            return None
+        V._check(rc)
+        return t.value, d_i.value
+
     def poll(self, ticket: int) -> bool:
         d = ctypes.c_int()
         V._check(V.lib().vdi_server_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(d)))

@@ -31,7 +31,7 @@ EXPORTS = ("vdi_create", "vdi_render", "vdi_render_ex", "vdi_render_counters", "
            "vdi_server_submit", "vdi_server_poll", "vdi_server_drain", "vdi_server_get_stats",
            "vdi_server_reset_stats", "vdi_server_destroy", "vdi_replace_begin", "vdi_replace_poll",
            "vdi_pace_create", "vdi_pace_update", "vdi_pace_destroy", "vdi_generate", "vdi_dvr",
-           "vdi_image_quality", "vdi_render_noalloc", "vdi_preview_counters")
+           "vdi_image_quality", "vdi_render_noalloc", "vdi_preview_counters", "vdi_server_submit_paced")
 
 VOXEL = {"f32": 0, "u16": 1}
 TF = {"ramp": 0, "knots4": 1}
@@ -74,7 +74,8 @@ class ServerStats(ctypes.Structure):
                 ("rejected_budget", ctypes.c_uint64), ("rejected_slots", ctypes.c_uint64),
                 ("bytes_in_flight", ctypes.c_uint64), ("peak_bytes_in_flight", ctypes.c_uint64),
                 ("batches", ctypes.c_uint64), ("inflight", ctypes.c_int32), ("peak_inflight", ctypes.c_int32),
-                ("queued", ctypes.c_int32), ("peak_batch", ctypes.c_int32)]
+                ("queued", ctypes.c_int32), ("peak_batch", ctypes.c_int32),
+                ("paced_completed", ctypes.c_uint64), ("deadlines_met", ctypes.c_uint64)]
 
 
 class Volume(ctypes.Structure):
@@ -125,6 +126,8 @@ def lib() -> ctypes.CDLL:
         L.vdi_server_create.argtypes = [ctypes.c_uint64, I32, I32, ctypes.POINTER(P)]
         L.vdi_server_submit.argtypes = [P, P, ctypes.POINTER(Camera), I32, I32, F, F, P,
                                         ctypes.POINTER(ctypes.c_uint64)]
+        L.vdi_server_submit_paced.argtypes = [P, P, ctypes.POINTER(Camera), I32, I32, P, F, P,
+                                              ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(F)]
         L.vdi_server_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
         L.vdi_server_drain.argtypes = [P]
         L.vdi_server_get_stats.argtypes = [P, ctypes.POINTER(ServerStats)]

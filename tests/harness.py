@@ -230,3 +230,27 @@ def run_session(vdi: "V.Vdi", cams: Sequence, width: int, height: int, d_r: floa
             kept[len(log) - 1] = out.clone()
         pace.update(ms)
     return (log, kept) if keep else log
+
+
+def run_served_session(srv, vdi: "V.Vdi", cams: Sequence, width: int, height: int, d_r: float, pace: Pace,
+                       keep=()):
+    """An interactive client of a server: each frame is submitted as a
+    request of the paced session `pace` once the previous one is done, with
+    the D_I the server takes from the session.  Returns [(D_I, latency ms)]
+    per frame (latency from submission to the client seeing it done), and
+    with `keep` also {frame index: image} of those frames."""
+    import torch
+    out = torch.empty((height, width, 4), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    log, kept = [], {}
+    for cam in cams:
+        t0 = time.perf_counter()
+        r = srv.submit_paced(vdi, cam, width, height, pace, d_r, out)
+        assert r is not None, "paced request rejected"
+        ticket, d_i = r
+        while not srv.poll(ticket):
+            time.sleep(0)
+        log.append((d_i, 1e3 * (time.perf_counter() - t0)))
+        if len(log) - 1 in keep:
+            kept[len(log) - 1] = out.clone()
+    return (log, kept) if keep else log

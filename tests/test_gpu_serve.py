@@ -205,3 +205,46 @@ def test_vdi_create_and_destroy_beside_a_running_server(sources, handles):
     r = subprocess.run([sys.executable, child], capture_output=True, text=True, timeout=180, env=env)
     say(r.stdout.strip())
     assert r.returncode == 0 and "create: ok" in r.stdout, r.stdout + r.stderr
+
+
+
+def test_paced_session_in_the_server_holds_its_deadline(sources, handles):
+    """Frame-time control inside the server (Section 4.4; the paper's remote
+    client holds its frame rate with a PI controller on D_I, Section 6): an
+    interactive session renders 1920 x 1080 previews (D_R = 0.5) of the 720p
+    VDI at 40 deg, each request submitted when the previous one is done, its
+    D_I taken by the server from the session and its latency fed back.  The
+    target lies between the latencies at D_I = 1 and D_I = 4; the session
+    settles on an intermediate D_I and holds the target, and the images at
+    the D_I chosen match the oracle."""
+    from paper_2206_08660_amd import serve
+    from paper_2206_08660_amd.pace import Pace
+    from tests.harness import run_served_session
+    cam = inputs.orbit_camera(40.0)
+    W, H, d_r = 1920, 1080, 0.5
+    with serve.Server(2 ** 33, max_inflight=16) as srv:
+        plant = {}
+        for d in (1.0, 4.0):
+            with Pace(1e6, d_i_min=d, d_i_max=d, d_i_start=d) as fixed:
+                lat = [ms for _, ms in run_served_session(srv, handles[1], [cam] * 12, W, H, d_r, fixed)][2:]
+            plant[d] = float(np.median(lat))
+        say(f"[gpu] served plant at 40 deg: latency {plant[1.0]:.3f} ms at D_I = 1, {plant[4.0]:.3f} ms at D_I = 4")
+        assert plant[1.0] > 1.5 * plant[4.0]
+        target = float(np.sqrt(plant[1.0] * plant[4.0]))
+        srv.reset_stats()
+        with Pace(target, d_i_max=8.0) as p:
+            log, kept = run_served_session(srv, handles[1], [cam] * 100, W, H, d_r, p, keep=(5, 99))
+        st = srv.stats()
+    d_i = np.array([d for d, _ in log])
+    ms = np.array([t for _, t in log])
+    rel = np.abs(ms[50:] / target - 1.0)
+    say(f"[gpu] paced session: target {target:.3f} ms, D_I {d_i[50:].mean():.2f}, median error {np.median(rel):.3f}, "
+        f"within 20%: {np.mean(rel < 0.2):.2f}, deadlines met {st['deadlines_met']} of {st['paced_completed']}")
+    assert st["paced_completed"] == 100
+    assert 1.05 < d_i[50:].mean() < 4.0
+    assert np.median(rel) < 0.15 and np.mean(rel < 0.2) >= 0.6
+    rgba = oracle.dequant_f16(sources[1].rgba)
+    for k, img in kept.items():
+        say(f"[gpu] paced frame {k} at D_I = {d_i[k]:.3f} vs oracle")
+        ne = oracle_check(sources[1], rgba, cam, W, H, float(d_i[k]), d_r, img.cpu().numpy(), seed=k)
+        assert ne >= 500
