@@ -171,6 +171,18 @@ static int cmp_dbl(const void *a, const void *b)
     return (x > y) - (x < y);
 }
 
+/* Threads of one parallel region: nthreads > 0, else the OpenMP default
+ * (set per region, so a one-thread call leaves later calls unchanged). */
+static int oracle_threads(int nthreads)
+{
+#ifdef _OPENMP
+    return nthreads > 0 ? nthreads : omp_get_max_threads();
+#else
+    (void)nthreads;
+    return 1;
+#endif
+}
+
 static inline int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
 
 static inline int list_col(const or_vdi_t *v, double xn) { return clampi((int)floor((xn + 1.0) * v->W / 2.0), 0, v->W - 1); }
@@ -381,10 +393,7 @@ int or_render_exact(const or_vdi_t *v, const float *camN, int W, int H, double a
     if (!pix) npix = (int64_t)W * H;
     int nb = max_breaks(v);
     int maxp = nb * (v->NS + 1);
-#ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
-#endif
-#pragma omp parallel
+#pragma omp parallel num_threads(oracle_threads(nthreads))
     {
         double *ts = (double *)malloc(sizeof(double) * nb);
         piece_t *pc = (piece_t *)malloc(sizeof(piece_t) * maxp);
@@ -512,10 +521,7 @@ int or_render_preview(const or_vdi_t *v, const float *camN, int w, int h, double
     ocam_init(&cN, camN, w, h, aspect);
     if (!pix) npix = (int64_t)w * h;
     int nb = max_breaks(v);
-#ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
-#endif
-#pragma omp parallel
+#pragma omp parallel num_threads(oracle_threads(nthreads))
     {
         double *ts = (double *)malloc(sizeof(double) * nb);
 #pragma omp for schedule(dynamic, 16)
@@ -587,10 +593,7 @@ int or_march(const or_vdi_t *v, const float *camN, int W, int H, int64_t npix, c
     ocam_init(&cO, v->cam, v->W, v->H, 0.0);
     ocam_init(&cN, camN, W, H, 0.0);
     const size_t plane = (size_t)v->W * v->H;
-#ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
-#endif
-#pragma omp parallel for schedule(dynamic, 1)
+#pragma omp parallel for schedule(dynamic, 1) num_threads(oracle_threads(nthreads))
     for (int64_t q = 0; q < npix; ++q) {
         int64_t id = pix[q];
         int px = (int)(id % W), py = (int)(id / W);
