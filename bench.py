@@ -59,6 +59,8 @@ def parse():
     p.add_argument("--profile-generation", action="store_true",
                    help="short run for rocprofv3: one 1 GiB copy, then two GPU generations of the 720p VDI "
                         "(1280x720, N_S=20, generating view 0 deg), the second the one to read")
+    p.add_argument("--profile-served", action="store_true",
+                   help="short run for rocprofv3: the served saturation trace (2000 requests) after a warm-up")
     return p.parse_args()
 
 
@@ -87,6 +89,10 @@ def main():
     stream = torch.cuda.current_stream()
     if args.profile_generation:
         profile_generation(torch, V)
+        return
+    if args.profile_served:
+        from tests import harness
+        harness.profile_saturation(log=log)
         return
 
     t = time.time()

@@ -165,11 +165,54 @@ def run_unbatched(handles, bases, trace):
     return lat, makespan
 
 
+def idle_overhead(srv, vdi: "V.Vdi", cam, size: int = 128, n: int = 200) -> dict:
+    """Fixed cost of one small request on an idle GPU: a size x size exact
+    frame submitted to the server (submission to the client seeing it done),
+    the same frame through vdi_render plus a stream synchronisation, and the
+    render kernel's own time (HIP events around vdi_render).  What the served
+    latency adds over the kernel is the per-request cost that a kernel
+    resident on the GPU, taking requests from a queue, could at most remove."""
+    import torch
+    out = torch.empty((size, size, 4), dtype=torch.float32, device="cuda")
+    s = torch.cuda.current_stream()
+    served, direct, kernel = [], [], []
+    with _no_gc():
+        for _ in range(n):
+            t0 = time.perf_counter()
+            t = srv.submit(vdi, cam, size, size, 1.0, 0.0, out)
+            assert t is not None, "small request rejected"
+            while not srv.poll(t):
+                time.sleep(0)
+            served.append(time.perf_counter() - t0)
+        torch.cuda.synchronize()
+        for _ in range(n):
+            t0 = time.perf_counter()
+            vdi.render(cam, size, size, 1.0, 0.0, out=out, stream=s)
+            s.synchronize()
+            direct.append(time.perf_counter() - t0)
+        for _ in range(n):
+            # The second render is launched while the first one runs, so the
+            # events around it time the kernel and not the host's preparation.
+            e1, e2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            vdi.render(cam, size, size, 1.0, 0.0, out=out, stream=s)
+            e1.record(s)
+            vdi.render(cam, size, size, 1.0, 0.0, out=out, stream=s)
+            e2.record(s)
+            e2.synchronize()
+            kernel.append(e1.elapsed_time(e2) * 1e-3)
+    med = lambda a: round(float(np.median(a)) * 1e3, 4)
+    return {"request": f"{size}x{size} exact, 1080p VDI, one at a time on an idle GPU, {n} each",
+            "served_p50_ms": med(served), "vdi_render_and_sync_p50_ms": med(direct), "kernel_p50_ms": med(kernel),
+            "served_minus_kernel_ms": round(med(served) - med(kernel), 4)}
+
+
 def serve_benchmark(n: int = 2000, rate: float = 600.0, budget: int = 64 * 2 ** 30, max_inflight: int = 256,
                     log: Callable = print) -> dict:
     """Open-loop latency at `rate` requests/s, then throughput at saturation
     (all n requests present at t = 0), served and one request at a time."""
     import torch
+
+    import inputs
     srcs = load_vdis(log=log)
     handles = [V.Vdi(s, store="f16") for _, _, s in srcs]
     bases = [b for _, b, _ in srcs]
@@ -201,10 +244,32 @@ def serve_benchmark(n: int = 2000, rate: float = 600.0, budget: int = 64 * 2 ** 
             "unbatched": {**_percentiles(ulat), "Mpixels_per_s": round(px / umake / 1e6, 1),
                           "requests_per_s": round(n / umake, 1)},
         }
+    out["idle_small_request"] = idle_overhead(srv, handles[2], inputs.orbit_camera(20.0, bases[2]))
+    log(f"idle small request: {out['idle_small_request']}")
     srv.close()
     for h in handles:
         h.close()
     return out
+
+
+def profile_saturation(n: int = 2000, budget: int = 64 * 2 ** 30, max_inflight: int = 256, log: Callable = print):
+    """The saturation trace, served only, after a warm-up of 64 requests (a
+    short run to record under a kernel trace)."""
+    import torch
+    srcs = load_vdis(log=log)
+    handles = [V.Vdi(s, store="f16") for _, _, s in srcs]
+    bases = [b for _, b, _ in srcs]
+    trace = make_trace(n)
+    trace = (trace[0] * 0.0, *trace[1:])
+    srv = Server(budget, max_inflight)
+    run_served(handles, bases, tuple(a[:64] for a in trace), budget, max_inflight, server=srv)
+    torch.cuda.synchronize()
+    time.sleep(0.05)   # a gap that marks the start of the timed trace in a kernel trace
+    lat, makespan, stats, _ = run_served(handles, bases, trace, budget, max_inflight, server=srv, log=log)
+    log(f"saturation served: {n} requests in {makespan:.3f}s, {stats['batches']} batches")
+    srv.close()
+    for h in handles:
+        h.close()
 
 
 def run_session(vdi: "V.Vdi", cams: Sequence, width: int, height: int, d_r: float, pace: Pace, out=None,
