@@ -11,6 +11,19 @@
 
 #include "vdi_internal.h"
 
+// Every global load of the per-ray code goes through VDI_LOAD(pointer,
+// stream), with stream 0 for counts, 1 for occupancy bits, 2 for depth pairs
+// and 3 for colours, and every main-loop iteration of an exact ray calls
+// VDI_STEP().  In the library they are a plain load and nothing; a host build
+// of the same code may define them to record what each ray reads, in order
+// (tests/host/reuse_host.hip).
+#ifndef VDI_LOAD
+#define VDI_LOAD(p, stream) (*(p))
+#endif
+#ifndef VDI_STEP
+#define VDI_STEP()
+#endif
+
 namespace vdi {
 
 // Per-ray functions are host-callable too, so the traversal can be stepped
@@ -90,8 +103,8 @@ template <int FMT>
 VDI_HD inline float4 load_rgba(const void *base, uint64_t idx, int fmt = FMT)
 {
     const int f = FMT >= 0 ? FMT : fmt;
-    if (FMT == VDI_F32 || (FMT < 0 && f == VDI_F32)) return reinterpret_cast<const float4 *>(base)[idx];
-    const uint2 u = reinterpret_cast<const uint2 *>(base)[idx];
+    if (FMT == VDI_F32 || (FMT < 0 && f == VDI_F32)) return VDI_LOAD(reinterpret_cast<const float4 *>(base) + idx, 3);
+    const uint2 u = VDI_LOAD(reinterpret_cast<const uint2 *>(base) + idx, 3);
     if (f == VDI_F16) {
         const __half2 rg = *reinterpret_cast<const __half2 *>(&u.x);
         const __half2 ba = *reinterpret_cast<const __half2 *>(&u.y);
@@ -209,15 +222,15 @@ VDI_HD inline int first_back_above(const float2 *__restrict__ dep, uint64_t stri
 {
     if constexpr (SEARCH == VDI_SEARCH_LINEAR) {
         int j = 0;
-        while (j < n && (double)dep[(uint64_t)j * stride + base].y <= z) ++j;
+        while (j < n && (double)VDI_LOAD(dep + ((uint64_t)j * stride + base), 2).y <= z) ++j;
         return j;
     }
     int lo = 0, hi = n;
     if constexpr (SEARCH == VDI_SEARCH_SEEDED) {
         if (p >= 0 && p < n) {
             // Both candidate back depths are fetched before either is compared.
-            const float b1 = dep[(uint64_t)p * stride + base].y;
-            const float b0 = p > 0 ? dep[(uint64_t)(p - 1) * stride + base].y : -__builtin_huge_valf();
+            const float b1 = VDI_LOAD(dep + ((uint64_t)p * stride + base), 2).y;
+            const float b0 = p > 0 ? VDI_LOAD(dep + ((uint64_t)(p - 1) * stride + base), 2).y : -__builtin_huge_valf();
             if ((double)b0 > z)
                 hi = p - 1;  // the answer is at most p-1
             else if ((double)b1 > z)
@@ -228,7 +241,7 @@ VDI_HD inline int first_back_above(const float2 *__restrict__ dep, uint64_t stri
     }
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if ((double)dep[(uint64_t)mid * stride + base].y > z)
+        if ((double)VDI_LOAD(dep + ((uint64_t)mid * stride + base), 2).y > z)
             hi = mid;
         else
             lo = mid + 1;
@@ -244,14 +257,14 @@ VDI_HD inline int last_front_below(const float2 *__restrict__ dep, uint64_t stri
 {
     if constexpr (SEARCH == VDI_SEARCH_LINEAR) {
         int j = n - 1;
-        while (j >= 0 && (double)dep[(uint64_t)j * stride + base].x >= z) --j;
+        while (j >= 0 && (double)VDI_LOAD(dep + ((uint64_t)j * stride + base), 2).x >= z) --j;
         return j;
     }
     int lo = 0, hi = n;  // search the first j with f_j >= z
     if constexpr (SEARCH == VDI_SEARCH_SEEDED) {
         if (p >= 0 && p < n) {
-            const float f1 = dep[(uint64_t)p * stride + base].x;
-            const float f2 = p + 1 < n ? dep[(uint64_t)(p + 1) * stride + base].x : __builtin_huge_valf();
+            const float f1 = VDI_LOAD(dep + ((uint64_t)p * stride + base), 2).x;
+            const float f2 = p + 1 < n ? VDI_LOAD(dep + ((uint64_t)(p + 1) * stride + base), 2).x : __builtin_huge_valf();
             if ((double)f1 >= z)
                 hi = p;
             else if ((double)f2 >= z)
@@ -262,7 +275,7 @@ VDI_HD inline int last_front_below(const float2 *__restrict__ dep, uint64_t stri
     }
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if ((double)dep[(uint64_t)mid * stride + base].x >= z)
+        if ((double)VDI_LOAD(dep + ((uint64_t)mid * stride + base), 2).x >= z)
             hi = mid;
         else
             lo = mid + 1;
@@ -326,7 +339,7 @@ VDI_HD inline int window_search(const float2 *__restrict__ dep, uint64_t stride,
         const float2 *w = dep + base + (uint64_t)w0 * stride;
         float2 b[kWin];
 #pragma unroll
-        for (int k = 0; k < kWin; ++k) b[k] = w[k * stride];
+        for (int k = 0; k < kWin; ++k) b[k] = VDI_LOAD(w + k * stride, 2);
         int cnt = 0;
 #pragma unroll
         for (int k = 0; k < kWin; ++k) cnt += below(b[k]) ? 1 : 0;
@@ -340,7 +353,7 @@ VDI_HD inline int window_search(const float2 *__restrict__ dep, uint64_t stride,
     if constexpr (!SPREAD) {
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
-            if (below(dep[base + (uint64_t)mid * stride]))
+            if (below(VDI_LOAD(dep + base + (uint64_t)mid * stride, 2)))
                 lo = mid + 1;
             else
                 hi = mid;
@@ -352,7 +365,7 @@ VDI_HD inline int window_search(const float2 *__restrict__ dep, uint64_t stride,
         const int span = hi - lo;
         float2 b[kWin];
 #pragma unroll
-        for (int k = 0; k < kWin; ++k) b[k] = dep[base + (uint64_t)(lo + ((k + 1) * span) / (kWin + 1)) * stride];
+        for (int k = 0; k < kWin; ++k) b[k] = VDI_LOAD(dep + base + (uint64_t)(lo + ((k + 1) * span) / (kWin + 1)) * stride, 2);
         int m = 0;
 #pragma unroll
         for (int k = 0; k < kWin; ++k) m += below(b[k]) ? 1 : 0;
@@ -367,7 +380,7 @@ VDI_HD inline int window_search(const float2 *__restrict__ dep, uint64_t stride,
         const float2 *w = dep + base + (uint64_t)lo * stride;
         float2 b[kWin];
 #pragma unroll
-        for (int k = 0; k < kWin; ++k) b[k] = w[(uint64_t)min(k, len - 1) * stride];
+        for (int k = 0; k < kWin; ++k) b[k] = VDI_LOAD(w + (uint64_t)min(k, len - 1) * stride, 2);
         int cnt = 0;
 #pragma unroll
         for (int k = 0; k < kWin; ++k) cnt += (k < len && below(b[k])) ? 1 : 0;
@@ -436,7 +449,7 @@ VDI_HD inline uint64_t slot_stride(const DevVDI &V)
 }
 
 // Depth pair of slot j of the list whose storage starts at lb (list_base).
-VDI_HD inline float2 depth_at(const DevVDI &V, int j, uint64_t lb) { return V.depth[(uint64_t)j * slot_stride(V) + lb]; }
+VDI_HD inline float2 depth_at(const DevVDI &V, int j, uint64_t lb) { return VDI_LOAD(V.depth + (uint64_t)j * slot_stride(V) + lb, 2); }
 
 // Composite the part of list (ix, iy) that a ray with dz/dt = Zp crosses
 // between parameters ta and tb (Sections 4.2, Eq. 2).  n is the list's count
@@ -600,7 +613,7 @@ VDI_HD bool do_list(const DevVDI &V, const Frame &F, int ix, int iy, int n, doub
 // (the exact walker needs no more than that from the count grid).
 VDI_HD inline bool cell_occupied(const DevVDI &V, int cell)
 {
-    return (V.gbits[(uint32_t)cell >> 5] >> ((uint32_t)cell & 31u)) & 1u;
+    return (VDI_LOAD(V.gbits + ((uint32_t)cell >> 5), 1) >> ((uint32_t)cell & 31u)) & 1u;
 }
 
 // ---------------------------------------------------------------------------
@@ -651,7 +664,7 @@ VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, in
     };
     locate(t);
     int p = -1;
-    int n = V.count[(uint64_t)iy * WO + ix];
+    int n = VDI_LOAD(V.count + (uint64_t)iy * WO + ix, 0);
     // Every iteration moves one list or jumps a grid cell; the cap only
     // guards against a loop that does not advance.
     const int max_iter = 4 * (WO + HO) + 4 * V.gnz + 64;
@@ -672,6 +685,7 @@ VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, in
     // located again and walks lists.
     bool cellmode = false;
     for (int it = 0; it < max_iter; ++it) {
+        VDI_STEP();
         if constexpr (ESS) {
             if (cellmode) {
                 const double te = fmin(fmin(tx, ty), fmin(tz, r.t1));
@@ -697,7 +711,7 @@ VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, in
                 if (cell_occupied(V, cell)) {
                     cellmode = false;
                     locate(t);
-                    n = V.count[(uint64_t)iy * WO + ix];
+                    n = VDI_LOAD(V.count + (uint64_t)iy * WO + ix, 0);
                     ccell = -1;
                 }
                 continue;
@@ -740,7 +754,7 @@ VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, in
         const bool stepx = tx <= ty;
         const int nx = stepx ? ix + sx : ix, ny = stepx ? iy : iy + sy;
         const bool more = tn < r.t1 && (unsigned)nx < (unsigned)WO && (unsigned)ny < (unsigned)HO;
-        const int n_next = more ? V.count[(uint64_t)ny * WO + nx] : 0;
+        const int n_next = more ? VDI_LOAD(V.count + (uint64_t)ny * WO + nx, 0) : 0;
         if (tn > t && do_list<FMT, SEARCH, COUNT>(V, F, ix, iy, n, t, tn, F.Z0, r.Zp, invZp, A, p, cnt)) break;
         if (!more) break;
         {
@@ -894,7 +908,7 @@ VDI_HD Accum trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, i
                 tn = fmin(fmin(fmin(tx, ty), tz), r.t1);
                 if (tn > t) {
                     const uint64_t cell = ((uint64_t)cz * V.GH + cy) * V.GW + cx;
-                    const uint32_t G = V.grid[cell];
+                    const uint32_t G = VDI_LOAD(V.grid + (cell), 1);
                     if constexpr (COUNT) F.touched_cells[cell] = 1;
                     if (G != 0u) {
                         const double dz = (double)s_gz[cz + 1] - (double)s_gz[cz];
@@ -904,7 +918,7 @@ VDI_HD Accum trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, i
                         h = (tn - t) / n;
                         q = 0;
                         sample_list(0, u, z, lx, ly);
-                        nl = V.count[(uint64_t)ly * WO + lx];
+                        nl = VDI_LOAD(V.count + ((uint64_t)ly * WO + lx), 0);
                         advance = false;
                     }
                 }
@@ -912,7 +926,7 @@ VDI_HD Accum trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, i
                 double un = 0.0, zn = 0.0;
                 int lxn = lx, lyn = ly;
                 if (q + 1 < n) sample_list(q + 1, un, zn, lxn, lyn);
-                const int nln = q + 1 < n ? (int)V.count[(uint64_t)lyn * WO + lxn] : 0;
+                const int nln = q + 1 < n ? (int)VDI_LOAD(V.count + ((uint64_t)lyn * WO + lxn), 0) : 0;
                 if constexpr (COUNT) {
                     F.touched_lists[(uint64_t)ly * WO + lx] = 1;
                     ++cnt->lists;
@@ -922,7 +936,7 @@ VDI_HD Accum trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, i
                     const uint64_t lb = list_base_xy(lx, ly, V.NS, WO);
                     const int j = first_back_above_win<true>(dep, stride, lb, nl, z, fwd ? win_start_fwd(p) : win_start_bwd(p));
                     if (j < nl) {
-                        const float2 fb = dep[(uint64_t)j * stride + lb];
+                        const float2 fb = VDI_LOAD(dep + ((uint64_t)j * stride + lb), 2);
                         p = j;
                         if ((double)fb.x <= z) {
                             const float4 c = load_rgba<FMT>(V.rgba, (uint64_t)j * stride + lb, V.fmt);
