@@ -130,15 +130,24 @@ def test_admission_by_budget_and_slots(handles):
         assert t2 is not None
         srv.drain()
         assert srv.poll(t1) and srv.poll(t2) and srv.stats()["completed"] == 2
+    # Slots: with one slot, a second request is rejected while the same long
+    # preview is in flight, whatever the budget, and admitted once it is done.
     with serve.Server(2 ** 34, max_inflight=1) as srv:
-        b = [torch.empty((128, 128, 4), dtype=torch.float32, device="cuda") for _ in range(2)]
-        t = srv.submit(handles[0], inputs.orbit_camera(5.0), 128, 128, 1.0, 0.0, b[0])
+        b = [torch.empty((720, 1280, 4), dtype=torch.float32, device="cuda"),
+             torch.empty((128, 128, 4), dtype=torch.float32, device="cuda")]
+        torch.cuda.synchronize()
+        t = srv.submit(handles[1], inputs.orbit_camera(40.0), 1280, 720, 1.0, 0.01, b[0])
+        assert t is not None
         t2 = srv.submit(handles[0], inputs.orbit_camera(5.0), 128, 128, 1.0, 0.0, b[1])
-        if t2 is None:
-            assert srv.stats()["rejected_slots"] >= 1
+        assert t2 is None and not srv.poll(t)
+        st = srv.stats()
+        assert st["rejected_slots"] == 1 and st["rejected_budget"] == 0 and st["inflight"] == 1
         srv.drain()
         assert srv.poll(t)
-        assert srv.stats()["completed"] >= 1
+        t2 = srv.submit(handles[0], inputs.orbit_camera(5.0), 128, 128, 1.0, 0.0, b[1])
+        assert t2 is not None
+        srv.drain()
+        assert srv.poll(t2) and srv.stats()["completed"] == 2
         srv.reset_stats()
         st = srv.stats()
         assert st["completed"] == 0 and st["submitted"] == 0 and st["batches"] == 0
