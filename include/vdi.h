@@ -165,6 +165,35 @@ int vdi_render(vdi_t v, const vdi_camera *cam_VN, int32_t width, int32_t height,
                float *out_rgba, void *hip_stream);
 
 /*
+ * Render n frames in one call, frame i being what vdi_render(vdis[i],
+ * &cams[i], widths[i], heights[i], D_I[i], D_R[i], outs[i], hip_stream)
+ * would write, bit for bit (Section 4; Eq. 2; Section 4.4).  The frames are
+ * independent: instead of one launch per frame, the tiles of all exact
+ * frames of one colour format form one launch, those of all preview frames
+ * another, and the upsampling of all downsampled frames a third, so the long
+ * rays at the end of one frame run beside the next frame's tiles.  Frames may
+ * name different VDIs, all resident on the device of hip_stream.
+ *   n              1 .. VDI_BATCH_MAX_FRAMES.
+ *   vdis, cams, widths, heights, D_I, D_R, outs
+ *                  host arrays of n entries; outs[i] are DEVICE pointers
+ *                  owned by the caller, laid out as for vdi_render, and must
+ *                  not overlap each other.
+ *   hip_stream     hipStream_t to run on (NULL: the null stream).
+ * Asynchronous with respect to the host.  The job tables travel to the
+ * device through pinned host memory of the library (a ring of 4 slots of
+ * VDI_BATCH_MAX_FRAMES jobs per device, allocated at the first call): a call
+ * waits only if the slot it takes is still being copied for a call 4 calls
+ * earlier.  Device job tables and low-res images are stream-ordered
+ * allocations of the library's pool, freed on hip_stream after the launches.
+ * Errors: VDI_ERR_ARG (null arrays, n out of range, any frame's arguments as
+ * for vdi_render, VDIs on different devices), VDI_ERR_OOM, VDI_ERR_HIP.  On
+ * an error nothing has been launched.
+ */
+#define VDI_BATCH_MAX_FRAMES 1024
+int vdi_render_batch(int32_t n, const vdi_t *vdis, const vdi_camera *cams, const int32_t *widths,
+                     const int32_t *heights, const float *D_I, const float *D_R, float *const *outs, void *hip_stream);
+
+/*
  * vdi_render for callers that cannot allocate device memory: code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
  * arguments, kernels and image as vdi_render (bit for bit), but it calls no

@@ -353,6 +353,220 @@ int submit(vdi_server_t s, vdi_t v, const vdi_camera *cam, int32_t W, int32_t H,
 }  // namespace
 }  // namespace vdi
 
+// ---------------------------------------------------------------------------
+// Many frames in one call on the caller's stream (vdi_render_batch): the same
+// batched launches as a server batch, without the scheduler.
+// ---------------------------------------------------------------------------
+namespace vdi {
+namespace {
+
+constexpr int kRingSlots = 4;
+// Blocks per launch of a batched render (far below 2^32 work-items).
+constexpr uint64_t kLaunchBlocks = 1ull << 24;
+
+// Pinned host job tables of one device, reused in turn once their copy to
+// the device has finished.
+struct JobRing {
+    std::mutex mu;
+    BatchJob *jobs[kRingSlots] = {};
+    UpsampleJob *up[kRingSlots] = {};
+    hipEvent_t copied[kRingSlots] = {};
+    int next = 0;
+    bool ready = false;
+};
+std::mutex g_rings_mu;
+std::map<int, JobRing *> g_rings;  // one per device, kept until the process ends
+
+hipError_t job_ring(int device, JobRing **out)
+{
+    JobRing *R;
+    {
+        std::lock_guard<std::mutex> lock(g_rings_mu);
+        JobRing *&r = g_rings[device];
+        if (!r) r = new (std::nothrow) JobRing();
+        if (!r) return hipErrorOutOfMemory;
+        R = r;
+    }
+    std::lock_guard<std::mutex> lock(R->mu);
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < kRingSlots && !R->ready && e == hipSuccess; ++k) {
+        if (!R->jobs[k]) e = hipHostMalloc((void **)&R->jobs[k], sizeof(BatchJob) * VDI_BATCH_MAX_FRAMES, 0);
+        if (e == hipSuccess && !R->up[k])
+            e = hipHostMalloc((void **)&R->up[k], sizeof(UpsampleJob) * VDI_BATCH_MAX_FRAMES, 0);
+        if (e == hipSuccess && !R->copied[k]) e = hipEventCreateWithFlags(&R->copied[k], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) R->ready = true;
+    *out = R;
+    return e;
+}
+
+struct BatchItem {
+    BatchJob job;
+    UpsampleJob up{};
+    int fmt = VDI_F32;
+    bool preview = false, down = false;
+    size_t lo_bytes = 0;
+};
+
+// One launch: jobs [start, start + count) of the device table, nblocks blocks.
+struct Launch {
+    int start, count;
+    uint32_t nblocks;
+    int fmt;
+    bool preview;
+};
+
+int render_batch(int32_t n, const vdi_t *vdis, const vdi_camera *cams, const int32_t *widths, const int32_t *heights,
+                 const float *D_I, const float *D_R, float *const *outs, hipStream_t st)
+{
+    if (n < 1 || n > VDI_BATCH_MAX_FRAMES)
+        return set_error(VDI_ERR_ARG, "n must be in [1, %d] (got %d)", VDI_BATCH_MAX_FRAMES, n);
+    if (!vdis || !cams || !widths || !heights || !D_I || !D_R || !outs) return set_error(VDI_ERR_ARG, "null array");
+    std::vector<BatchItem> items((size_t)n);
+    int device = -1;
+    for (int i = 0; i < n; ++i) {
+        int rc = check_render_args(vdis[i], &cams[i], widths[i], heights[i], D_I[i], D_R[i], outs[i]);
+        if (rc) return set_error(rc, "frame %d: %s", i, vdi_last_error());
+        if (i == 0) device = vdis[0]->device;
+        else if (vdis[i]->device != device)
+            return set_error(VDI_ERR_ARG, "frame %d renders a VDI of device %d, frame 0 one of device %d", i,
+                             vdis[i]->device, device);
+        int32_t w, h;
+        lowres_size(widths[i], heights[i], D_I[i], &w, &h);
+        BatchItem &it = items[(size_t)i];
+        const VdiSet S = current(vdis[i]);
+        rc = make_frame(S, cams[i], w, h, (double)widths[i] / (double)heights[i], it.job.F);
+        if (rc) return set_error(rc, "frame %d: %s", i, vdi_last_error());
+        it.job.V = S.dev;
+        it.job.F.DR = D_R[i];
+        it.job.F.ess = 1;
+        it.job.F.search = VDI_SEARCH_WINDOW;
+        it.fmt = S.dev.fmt;
+        it.preview = D_R[i] > 0.0f;
+        it.down = (w != widths[i] || h != heights[i]);
+        it.job.ntiles = it.preview ? preview_tiles(w, h) : exact_tiles(w, h);
+        if (it.down) {
+            // Rounded up to a power of two (at least 1 MiB), as for vdi_render.
+            it.lo_bytes = (size_t)1 << 20;
+            while (it.lo_bytes < (size_t)w * h * sizeof(float4)) it.lo_bytes <<= 1;
+            it.up = UpsampleJob{nullptr, reinterpret_cast<float4 *>(outs[i]), w, h, widths[i], heights[i], 0,
+                                upsample_tiles(widths[i], heights[i])};
+        } else {
+            it.job.F.out = reinterpret_cast<float4 *>(outs[i]);
+        }
+    }
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) return hip_error(e, "hipSetDevice");
+    hipMemPool_t pool = nullptr;
+    e = library_pool(device, &pool);
+    if (e != hipSuccess) return hip_error(e, "memory pool");
+    // Stream-ordered allocations: low-res images, then the device job tables.
+    std::vector<void *> allocs;
+    auto release = [&]() {
+        for (void *p : allocs) (void)hipFreeAsync(p, st);
+    };
+    for (BatchItem &it : items) {
+        if (!it.down) continue;
+        void *lo = nullptr;
+        e = hipMallocFromPoolAsync(&lo, it.lo_bytes, pool, st);
+        if (e != hipSuccess) {
+            release();
+            return hip_error(e, "preview scratch");
+        }
+        allocs.push_back(lo);
+        it.job.F.out = static_cast<float4 *>(lo);
+        it.up.lo = static_cast<float4 *>(lo);
+    }
+    BatchJob *d_jobs = nullptr;
+    UpsampleJob *d_up = nullptr;
+    e = hipMallocFromPoolAsync((void **)&d_jobs, sizeof(BatchJob) * (size_t)n, pool, st);
+    if (e == hipSuccess) {
+        allocs.push_back(d_jobs);
+        e = hipMallocFromPoolAsync((void **)&d_up, sizeof(UpsampleJob) * (size_t)n, pool, st);
+        if (e == hipSuccess) allocs.push_back(d_up);
+    }
+    if (e != hipSuccess) {
+        release();
+        return hip_error(e, "job tables");
+    }
+    JobRing *R = nullptr;
+    e = job_ring(device, &R);
+    if (e != hipSuccess) {
+        release();
+        return hip_error(e, "pinned job tables");
+    }
+    // Job tables: one group per (mode, format), cut into launches of at most
+    // kLaunchBlocks blocks; a job starts at a multiple of the XCD count.
+    std::vector<Launch> launches, up_launches;
+    {
+        std::lock_guard<std::mutex> lock(R->mu);
+        const int k = R->next;
+        R->next = (k + 1) % kRingSlots;
+        e = hipEventSynchronize(R->copied[k]);
+        int nj = 0, nu = 0;
+        for (int p = 0; p < 2 && e == hipSuccess; ++p)
+            for (int f = 0; f < 3; ++f) {
+                uint64_t t = 0;
+                int start = nj;
+                for (const BatchItem &it : items) {
+                    if (it.preview != (p == 1) || it.fmt != f) continue;
+                    if (nj > start && align_up(t) + it.job.ntiles > kLaunchBlocks) {
+                        launches.push_back({start, nj - start, (uint32_t)t, f, p == 1});
+                        start = nj;
+                        t = 0;
+                    }
+                    t = align_up(t);
+                    R->jobs[k][nj] = it.job;
+                    R->jobs[k][nj].tile0 = (uint32_t)t;
+                    t += it.job.ntiles;
+                    ++nj;
+                }
+                if (nj > start) launches.push_back({start, nj - start, (uint32_t)t, f, p == 1});
+            }
+        uint64_t tu = 0;
+        int ustart = 0;
+        for (const BatchItem &it : items) {
+            if (!it.down) continue;
+            if (nu > ustart && align_up(tu) + it.up.ntiles > kLaunchBlocks) {
+                up_launches.push_back({ustart, nu - ustart, (uint32_t)tu, 0, false});
+                ustart = nu;
+                tu = 0;
+            }
+            tu = align_up(tu);
+            R->up[k][nu] = it.up;
+            R->up[k][nu].tile0 = (uint32_t)tu;
+            tu += it.up.ntiles;
+            ++nu;
+        }
+        if (nu > ustart) up_launches.push_back({ustart, nu - ustart, (uint32_t)tu, 0, false});
+        if (e == hipSuccess) e = hipMemcpyAsync(d_jobs, R->jobs[k], sizeof(BatchJob) * nj, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && nu)
+            e = hipMemcpyAsync(d_up, R->up[k], sizeof(UpsampleJob) * nu, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipEventRecord(R->copied[k], st);
+    }
+    for (const Launch &L : launches) {
+        if (e != hipSuccess) break;
+        e = launch_batch_render(d_jobs + L.start, L.count, L.nblocks, L.fmt, L.preview, st);
+    }
+    for (const Launch &L : up_launches) {
+        if (e != hipSuccess) break;
+        e = launch_batch_upsample(d_up + L.start, L.count, L.nblocks, st);
+    }
+    release();
+    if (e != hipSuccess) return hip_error(e, "batched render");
+    for (int i = 0; i < n; ++i) {
+        bool seen = false;
+        for (int j = 0; j < i && !seen; ++j) seen = vdis[j] == vdis[i];
+        if (seen) continue;
+        e = note_use(vdis[i], st);
+        if (e != hipSuccess) return hip_error(e, "render event");
+    }
+    return VDI_OK;
+}
+
+}  // namespace
+}  // namespace vdi
+
 extern "C" {
 
 int vdi_server_create(uint64_t hbm_budget_bytes, int32_t max_inflight, int32_t streams, vdi_server_t *out)
@@ -416,6 +630,12 @@ int vdi_server_submit_paced(vdi_server_t s, vdi_t v, const vdi_camera *cam, int3
     const int rc = vdi::submit(s, v, cam, W, H, D_I, D_R, out, ticket, session);
     if (rc == VDI_OK) *D_I_used = D_I;
     return rc;
+}
+
+int vdi_render_batch(int32_t n, const vdi_t *vdis, const vdi_camera *cams, const int32_t *widths,
+                     const int32_t *heights, const float *D_I, const float *D_R, float *const *outs, void *hip_stream)
+{
+    return vdi::render_batch(n, vdis, cams, widths, heights, D_I, D_R, outs, static_cast<hipStream_t>(hip_stream));
 }
 
 int vdi_server_poll(vdi_server_t s, uint64_t ticket, int *done)

@@ -830,31 +830,68 @@ VDI_HD Accum trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, i
             else
                 tz = cz > 0 ? ((double)s_gz[cz] - F.Z0) * invZp : inf;
         };
-        // Parameter at which the walk enters the cell holding the ray at
-        // parameter u: the latest crossing of the cell's faces behind the ray
-        // (the walk computes the same crossings, in the same way, as it leaves
-        // the cells before).  A face counts if it is crossed before the cell's
-        // exit: one with no crossing on the ray's valid branch was not crossed
-        // to get there, and u itself may lie a rounding error before a face
-        // that the cell lookup already puts behind it.
+        // The cell the walk is in at parameter u, and the parameter at which
+        // the walk enters it.  The walk moves between cells at face crossings
+        // computed by line_t (list-grid lines) and from the slice depths, so
+        // its cell at u is, axis by axis, the one whose entry face is crossed
+        // at or before u and whose exit face after u, with those crossings.
+        // Point location (which divides a position instead) gives the first
+        // guess, right but for a rounding error near a face; each axis is then
+        // moved until its faces bracket u.  The entry is the latest of the
+        // three entry crossings.  A face the walk never crosses (no grid line
+        // there, or a line beyond the vanishing point: +inf from the crossing
+        // functions) counts as crossed at -inf where it is the entry.
+        auto x_face = [&](int m) -> double {
+            return (m > 0 && m < WO) ? line_t(m, V.dcx, F.X0, r.Xp, F.Z0, r.Zp) : inf;
+        };
+        auto y_face = [&](int m) -> double {
+            return (m > 0 && m < HO) ? line_t(m, V.dcy, F.Y0, r.Yp, F.Z0, r.Zp) : inf;
+        };
+        auto z_face = [&](int c) -> double {  // slice boundary c, 0 < c < gnz
+            return (c > 0 && c < V.gnz) ? ((double)s_gz[c] - F.Z0) * invZp : inf;
+        };
+        auto enter = [&](double tf) -> double { return tf == inf ? -inf : tf; };
         auto entry_at = [&](double u) -> double {
             locate(u);
-            const double exit_t = fmin(fmin(tx, ty), fmin(tz, r.t1));
             double te = r.t0;
-            auto take = [&](double tf) {
-                if (tf < exit_t) te = fmax(te, tf);
-            };
             if (sx != 0) {
-                const int m = sx > 0 ? cx * k : (cx + 1) * k;
-                if (m > 0 && m < WO) take(line_t(m, V.dcx, F.X0, r.Xp, F.Z0, r.Zp));
+                for (int g = 0; g < 4; ++g) {
+                    const int mi = sx > 0 ? cx * k : (cx + 1) * k, mo = sx > 0 ? (cx + 1) * k : cx * k;
+                    const double ti = enter(x_face(mi)), to = x_face(mo);
+                    if (to <= u && (unsigned)(cx + sx) < (unsigned)V.GW) cx += sx;
+                    else if (ti > u && (unsigned)(cx - sx) < (unsigned)V.GW) cx -= sx;
+                    else break;
+                }
+                const int mi = sx > 0 ? cx * k : (cx + 1) * k;
+                te = fmax(te, enter(x_face(mi)));
+                mx = sx > 0 ? min((cx + 1) * k, WO) : cx * k;
+                tx = x_face(mx);
             }
             if (sy != 0) {
-                const int m = sy > 0 ? cy * k : (cy + 1) * k;
-                if (m > 0 && m < HO) take(line_t(m, V.dcy, F.Y0, r.Yp, F.Z0, r.Zp));
+                for (int g = 0; g < 4; ++g) {
+                    const int mi = sy > 0 ? cy * k : (cy + 1) * k, mo = sy > 0 ? (cy + 1) * k : cy * k;
+                    const double ti = enter(y_face(mi)), to = y_face(mo);
+                    if (to <= u && (unsigned)(cy + sy) < (unsigned)V.GH) cy += sy;
+                    else if (ti > u && (unsigned)(cy - sy) < (unsigned)V.GH) cy -= sy;
+                    else break;
+                }
+                const int mi = sy > 0 ? cy * k : (cy + 1) * k;
+                te = fmax(te, enter(y_face(mi)));
+                my = sy > 0 ? min((cy + 1) * k, HO) : cy * k;
+                ty = y_face(my);
             }
             if (!flat) {
-                const int c = fwd ? cz : cz + 1;
-                if (c > 0 && c < V.gnz) take(((double)s_gz[c] - F.Z0) * invZp);
+                const int dz = fwd ? 1 : -1;
+                for (int g = 0; g < 4; ++g) {
+                    const int ci = fwd ? cz : cz + 1, co = fwd ? cz + 1 : cz;
+                    const double ti = enter(z_face(ci)), to = z_face(co);
+                    if (to <= u && (unsigned)(cz + dz) < (unsigned)V.gnz) cz += dz;
+                    else if (ti > u && (unsigned)(cz - dz) < (unsigned)V.gnz) cz -= dz;
+                    else break;
+                }
+                const int ci = fwd ? cz : cz + 1;
+                te = fmax(te, enter(z_face(ci)));
+                tz = z_face(fwd ? cz + 1 : cz);
             }
             return te;
         };

@@ -31,7 +31,8 @@ EXPORTS = ("vdi_create", "vdi_render", "vdi_render_ex", "vdi_render_counters", "
            "vdi_server_submit", "vdi_server_poll", "vdi_server_drain", "vdi_server_get_stats",
            "vdi_server_reset_stats", "vdi_server_destroy", "vdi_replace_begin", "vdi_replace_poll",
            "vdi_pace_create", "vdi_pace_update", "vdi_pace_destroy", "vdi_generate", "vdi_dvr",
-           "vdi_image_quality", "vdi_render_noalloc", "vdi_preview_counters", "vdi_server_submit_paced")
+           "vdi_image_quality", "vdi_render_noalloc", "vdi_preview_counters", "vdi_server_submit_paced",
+           "vdi_render_batch")
 
 VOXEL = {"f32": 0, "u16": 1}
 TF = {"ramp": 0, "knots4": 1}
@@ -108,6 +109,7 @@ def lib() -> ctypes.CDLL:
         L.vdi_create.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(P)]
         L.vdi_render.argtypes = [P, ctypes.POINTER(Camera), I32, I32, F, F, P, P]
         L.vdi_render_noalloc.argtypes = [P, ctypes.POINTER(Camera), I32, I32, F, F, P, P]
+        L.vdi_render_batch.argtypes = [I32, P, P, P, P, P, P, P, P]
         L.vdi_render_ex.argtypes = [P, ctypes.POINTER(Camera), I32, I32, F, F, ctypes.POINTER(Opts), P, P]
         L.vdi_render_counters.argtypes = [P, ctypes.POINTER(Camera), I32, I32, ctypes.POINTER(Opts), P, P, P, P, P]
         L.vdi_preview_counters.argtypes = [P, ctypes.POINTER(Camera), I32, I32, F, F, P, P, P, P, P, P]
@@ -165,6 +167,31 @@ def lowres_size(width: int, height: int, d_i: float):
     w, h = ctypes.c_int32(), ctypes.c_int32()
     _check(lib().vdi_lowres_size(width, height, d_i, ctypes.byref(w), ctypes.byref(h)))
     return w.value, h.value
+
+
+def render_batch(frames, stream=None):
+    """Render several frames in one call (vdi_render_batch).  `frames` is a
+    sequence of (vdi, cam, width, height, d_i, d_r, out) with `out` a
+    contiguous float32 CUDA tensor of height*width*4 elements each; the
+    frames run on `stream` (default: torch's current stream)."""
+    import torch
+    n = len(frames)
+    if n == 0:
+        return
+    vdis = (ctypes.c_void_p * n)()
+    cams = (Camera * n)()
+    ws, hs = (ctypes.c_int32 * n)(), (ctypes.c_int32 * n)()
+    dis, drs = (ctypes.c_float * n)(), (ctypes.c_float * n)()
+    outs = (ctypes.c_void_p * n)()
+    for i, (v, cam, width, height, d_i, d_r, out) in enumerate(frames):
+        if out.dtype != torch.float32 or not out.is_cuda or not out.is_contiguous() or \
+                out.numel() < height * width * 4:
+            raise ValueError(f"frame {i}: out must be a contiguous float32 CUDA tensor with height*width*4 elements")
+        vdis[i] = v.handle
+        cams[i] = camera(cam)
+        ws[i], hs[i], dis[i], drs[i] = width, height, d_i, d_r
+        outs[i] = out.data_ptr()
+    _check(lib().vdi_render_batch(n, vdis, cams, ws, hs, dis, drs, outs, _stream_handle(stream)))
 
 
 def plane_bytes(width: int, height: int, ns: int, fmt: str = "f32") -> int:

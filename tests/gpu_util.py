@@ -77,3 +77,25 @@ def nonempty_stratum(img, n, seed=0):
     if len(idx) <= n:
         return idx
     return np.random.default_rng(seed).choice(idx, n, replace=False)
+
+
+def oracle_check(src, rgba, cam, W, H, d_i, d_r, img, n=1500, seed=0, min_ok=0.9):
+    """A rendered image against the oracle on sampled pixels (a stratum of them
+    non-empty).  Exact frames and D_I = 1 previews pixel by pixel (preview
+    ties against every consistent resolution); downsampled previews on the
+    pixels whose four low-res texels rest on no tie (at least a fraction
+    min_ok of the sample).  Returns the number of non-empty pixels compared."""
+    img = img.reshape(-1, 4).astype(np.float64)
+    pix = np.unique(np.concatenate([sample_pixels(W, H, n, seed=seed),
+                                    nonempty_stratum(img.reshape(H, W, 4), n // 2, seed=seed)]))
+    if d_r > 0 and d_i == 1.0:
+        err, _, ref = preview_errors(img[pix], src, cam, W, H, d_r, pix, rgba=rgba)
+        ok = np.ones(len(pix), bool)
+    else:
+        import oracle
+        ref, flags = oracle.render_points(src, cam, W, H, d_i, d_r, pix, rgba=rgba)
+        ok = flags == 0
+        err = np.abs(img[pix] - ref).max(axis=1)
+    assert ok.mean() > min_ok, float(ok.mean())
+    assert err[ok].max() <= TOL, (d_i, d_r, float(err[ok].max()))
+    return int((ok & (ref[:, 3] > 0)).sum())

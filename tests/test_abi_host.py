@@ -58,6 +58,26 @@ def test_render_rejects_bad_arguments_before_any_device_work():
     assert lib.vdi_render(fake, ctypes.byref(cam), 4, 4, 1.0, 0.0, None, None) == V.VDI_ERR_ARG
 
 
+def test_render_batch_rejects_bad_arguments_before_any_device_work():
+    lib = V.lib()
+    n = 2
+    vdis = (ctypes.c_void_p * n)(None, None)
+    cams = (V.Camera * n)()
+    ws, hs = (ctypes.c_int32 * n)(4, 4), (ctypes.c_int32 * n)(4, 4)
+    dis, drs = (ctypes.c_float * n)(1.0, 1.0), (ctypes.c_float * n)(0.0, 0.0)
+    outs = (ctypes.c_void_p * n)(16, 4096)
+    for bad_n in (0, -1, 1025):
+        assert lib.vdi_render_batch(bad_n, vdis, cams, ws, hs, dis, drs, outs, None) == V.VDI_ERR_ARG
+    assert lib.vdi_render_batch(n, None, cams, ws, hs, dis, drs, outs, None) == V.VDI_ERR_ARG
+    assert lib.vdi_render_batch(n, vdis, cams, ws, hs, dis, drs, None, None) == V.VDI_ERR_ARG
+    assert lib.vdi_render_batch(n, vdis, cams, ws, hs, dis, drs, outs, None) == V.VDI_ERR_ARG
+    assert "frame 0" in V.last_error() and "null" in V.last_error()
+    vdis[0] = 1   # never dereferenced: frame 0's other arguments are checked first
+    ws[0] = 0
+    assert lib.vdi_render_batch(n, vdis, cams, ws, hs, dis, drs, outs, None) == V.VDI_ERR_ARG
+    assert "frame 0" in V.last_error()
+
+
 def test_create_rejects_bad_descriptors_before_any_device_work():
     lib = V.lib()
     h = ctypes.c_void_p()

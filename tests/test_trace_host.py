@@ -141,3 +141,42 @@ def test_preview_ties_resolved_one_way(host, tiny, d_i):
         pos = [k for k, b in enumerate(oracle.TIE_BIASES) if b[0] == 1 and b[1] == 1]
         err_pos, _ = tie_aware_errors(img, ref, flags, var[pos])
         assert err_pos.max() <= TOL, (parts, err_pos.max())
+
+
+# Rays whose equal-parameter cut lands on a corner of the count grid, where a
+# list-grid line and a depth-slice face are crossed at the same parameter up
+# to rounding: the lanes must take up the walk exactly where the previous one
+# leaves it.  (yaw, width, height, D_R) of frames where cells were lost between
+# two lanes when a lane's start came from point location alone.
+CORNER_CASES = [(-36.37798448780438, 97, 61, 0.5), (161.61972297759553, 109, 16, 1.0),
+                (-125.89939191785794, 97, 44, 0.25), (122.87422066045798, 25, 55, 0.5),
+                (31.004303332583817, 97, 51, 0.25)]
+
+
+@pytest.mark.parametrize("yaw,w,h,d_r", CORNER_CASES)
+def test_preview_split_rays_at_grid_corners(host, tiny, yaw, w, h, d_r):
+    cam = inputs.orbit_camera(yaw)
+    whole = render(host, tiny, cam, w, h, preview=True, d_r=d_r, parts=1)
+    ref, flags = oracle.render_preview(tiny, cam, w, h, d_r)
+    assert np.abs(whole - ref)[flags == 0].max() <= TOL
+    for parts in (2, 4, 8):
+        img = render(host, tiny, cam, w, h, preview=True, d_r=d_r, parts=parts)
+        # only early termination differs between the blocks and the whole ray
+        assert np.abs(img - whole).max() <= 1.1e-5, parts
+
+
+def test_preview_split_rays_random_views(host, tiny):
+    """Seeded views in all directions, sizes and D_R: every split of every
+    ray takes exactly the whole ray's samples."""
+    rng = np.random.default_rng(20)
+    rv = synth.random_vdi(30, 20, 9, seed=12)
+    for case in range(16):
+        src = tiny if case % 2 else rv
+        yaw = float(rng.uniform(-180.0, 180.0))
+        w, h = int(rng.integers(20, 90)), int(rng.integers(15, 60))
+        d_r = float((0.25, 0.5, 1.0, 2.0)[case % 4])
+        cam = inputs.orbit_camera(yaw)
+        whole = render(host, src, cam, w, h, preview=True, d_r=d_r, parts=1)
+        for parts in (2, 8):
+            img = render(host, src, cam, w, h, preview=True, d_r=d_r, parts=parts)
+            assert np.abs(img - whole).max() <= 1.1e-5, (case, yaw, w, h, d_r, parts)
