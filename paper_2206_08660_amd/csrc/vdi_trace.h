@@ -814,11 +814,15 @@ VDI_HD Accum trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, i
         double t = r.t0;
         int cx, cy, cz, mx, my;
         double tx, ty, tz;
-        auto locate = [&](double tt) {
+        // Cell of the point at parameter tt (point location).
+        auto cell_at = [&](double tt) {
             const double z = F.Z0 + tt * r.Zp;
             cx = (int)((float)cell_of((F.X0 + tt * r.Xp) / z, WO, sx) * V.inv_gk);
             cy = (int)((float)cell_of((F.Y0 + tt * r.Yp) / z, HO, sy) * V.inv_gk);
             cz = slice_of(s_gz, V.gnz, z, fwd);
+        };
+        auto locate = [&](double tt) {
+            cell_at(tt);
             mx = sx > 0 ? min((cx + 1) * k, WO) : cx * k;
             my = sy > 0 ? min((cy + 1) * k, HO) : cy * k;
             tx = (sx != 0 && mx > 0 && mx < WO) ? line_t(mx, V.dcx, F.X0, r.Xp, F.Z0, r.Zp) : inf;
@@ -852,46 +856,81 @@ VDI_HD Accum trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, i
         };
         auto enter = [&](double tf) -> double { return tf == inf ? -inf : tf; };
         auto entry_at = [&](double u) -> double {
-            locate(u);
+            cell_at(u);
             double te = r.t0;
+            // Each crossing is solved once: moving on, a cell's exit face is
+            // the next cell's entry face, and moving back the other way round.
             if (sx != 0) {
+                auto in_m = [&](int c) { return sx > 0 ? c * k : (c + 1) * k; };
+                auto out_m = [&](int c) { return sx > 0 ? min((c + 1) * k, WO) : c * k; };
+                double ti = enter(x_face(in_m(cx))), to = x_face(out_m(cx));
+#pragma nounroll
                 for (int g = 0; g < 4; ++g) {
-                    const int mi = sx > 0 ? cx * k : (cx + 1) * k, mo = sx > 0 ? (cx + 1) * k : cx * k;
-                    const double ti = enter(x_face(mi)), to = x_face(mo);
-                    if (to <= u && (unsigned)(cx + sx) < (unsigned)V.GW) cx += sx;
-                    else if (ti > u && (unsigned)(cx - sx) < (unsigned)V.GW) cx -= sx;
-                    else break;
+                    if (to <= u && (unsigned)(cx + sx) < (unsigned)V.GW) {
+                        cx += sx;
+                        ti = to;
+                        to = x_face(out_m(cx));
+                    } else if (ti > u && (unsigned)(cx - sx) < (unsigned)V.GW) {
+                        cx -= sx;
+                        to = ti;
+                        ti = enter(x_face(in_m(cx)));
+                    } else {
+                        break;
+                    }
                 }
-                const int mi = sx > 0 ? cx * k : (cx + 1) * k;
-                te = fmax(te, enter(x_face(mi)));
-                mx = sx > 0 ? min((cx + 1) * k, WO) : cx * k;
-                tx = x_face(mx);
+                te = fmax(te, ti);
+                mx = out_m(cx);
+                tx = to;
+            } else {
+                tx = inf;
             }
             if (sy != 0) {
+                auto in_m = [&](int c) { return sy > 0 ? c * k : (c + 1) * k; };
+                auto out_m = [&](int c) { return sy > 0 ? min((c + 1) * k, HO) : c * k; };
+                double ti = enter(y_face(in_m(cy))), to = y_face(out_m(cy));
+#pragma nounroll
                 for (int g = 0; g < 4; ++g) {
-                    const int mi = sy > 0 ? cy * k : (cy + 1) * k, mo = sy > 0 ? (cy + 1) * k : cy * k;
-                    const double ti = enter(y_face(mi)), to = y_face(mo);
-                    if (to <= u && (unsigned)(cy + sy) < (unsigned)V.GH) cy += sy;
-                    else if (ti > u && (unsigned)(cy - sy) < (unsigned)V.GH) cy -= sy;
-                    else break;
+                    if (to <= u && (unsigned)(cy + sy) < (unsigned)V.GH) {
+                        cy += sy;
+                        ti = to;
+                        to = y_face(out_m(cy));
+                    } else if (ti > u && (unsigned)(cy - sy) < (unsigned)V.GH) {
+                        cy -= sy;
+                        to = ti;
+                        ti = enter(y_face(in_m(cy)));
+                    } else {
+                        break;
+                    }
                 }
-                const int mi = sy > 0 ? cy * k : (cy + 1) * k;
-                te = fmax(te, enter(y_face(mi)));
-                my = sy > 0 ? min((cy + 1) * k, HO) : cy * k;
-                ty = y_face(my);
+                te = fmax(te, ti);
+                my = out_m(cy);
+                ty = to;
+            } else {
+                ty = inf;
             }
             if (!flat) {
                 const int dz = fwd ? 1 : -1;
+                auto in_c = [&](int c) { return fwd ? c : c + 1; };
+                auto out_c = [&](int c) { return fwd ? c + 1 : c; };
+                double ti = enter(z_face(in_c(cz))), to = z_face(out_c(cz));
+#pragma nounroll
                 for (int g = 0; g < 4; ++g) {
-                    const int ci = fwd ? cz : cz + 1, co = fwd ? cz + 1 : cz;
-                    const double ti = enter(z_face(ci)), to = z_face(co);
-                    if (to <= u && (unsigned)(cz + dz) < (unsigned)V.gnz) cz += dz;
-                    else if (ti > u && (unsigned)(cz - dz) < (unsigned)V.gnz) cz -= dz;
-                    else break;
+                    if (to <= u && (unsigned)(cz + dz) < (unsigned)V.gnz) {
+                        cz += dz;
+                        ti = to;
+                        to = z_face(out_c(cz));
+                    } else if (ti > u && (unsigned)(cz - dz) < (unsigned)V.gnz) {
+                        cz -= dz;
+                        to = ti;
+                        ti = enter(z_face(in_c(cz)));
+                    } else {
+                        break;
+                    }
                 }
-                const int ci = fwd ? cz : cz + 1;
-                te = fmax(te, enter(z_face(ci)));
-                tz = z_face(fwd ? cz + 1 : cz);
+                te = fmax(te, ti);
+                tz = to;
+            } else {
+                tz = inf;
             }
             return te;
         };
@@ -900,14 +939,18 @@ VDI_HD Accum trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, i
         // to the entry of the cell it falls in, so the lanes need not walk the
         // cells before their own.
         double t_stop = inf;
-        if (parts > 1) {
+        if (parts > 1 && part > 0) {
+            // One call site for both cuts (the next lane's start, where this
+            // lane stops, then this lane's own start), so the code is inlined once.
             const double span = r.t1 - r.t0;
-            if (part + 1 < parts) t_stop = entry_at(r.t0 + span * (part + 1) / parts);
-            if (part > 0)
-                t = entry_at(r.t0 + span * part / parts);
-            else
-                locate(t);
+#pragma nounroll
+            for (int w = part + 1 < parts ? 0 : 1; w < 2; ++w) {
+                const double te = entry_at(r.t0 + span * (w == 0 ? part + 1 : part) / parts);
+                if (w == 0) t_stop = te;
+                else t = te;
+            }
         } else {
+            if (parts > 1) t_stop = entry_at(r.t0 + (r.t1 - r.t0) / parts);
             locate(t);
         }
         int p = -1;
