@@ -171,6 +171,12 @@ def main():
     reps = max(3, min(args.steps, 10))
     evs = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in renders]
            for _ in range(reps)]
+    # One untimed pass first: measured, the first frame-by-frame pass after
+    # the batched steps runs its D_I = 2 frames about 30% slower than the
+    # passes after it (exact frames are not affected).
+    for (th, di, dr) in renders:
+        h.render(cams[th], W, H, di, dr, out=out)
+    torch.cuda.synchronize()
     t1 = time.perf_counter()
     for i in range(reps):
         for k, (th, di, dr) in enumerate(renders):
