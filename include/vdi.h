@@ -453,9 +453,11 @@ int vdi_image_quality(const float *image, const float *reference, int32_t width,
  * Serving (continuous batching; a build addition, the paper's client renders
  * one request at a time, Section 5).  A server renders requests for any
  * number of resident VDIs.  Requests are admitted while request slots and the
- * device-memory budget allow, and queued.  A scheduler thread owned by the
- * server launches everything queued as one batch as soon as one of its
- * streams is free: one kernel launch per (mode, colour format) group covers
+ * device-memory budget allow, and queued.  Everything queued is launched as
+ * one batch as soon as one of the server's streams is free: by the
+ * submitting thread within vdi_server_submit if a stream is free then,
+ * otherwise by a scheduler thread owned by the server.  One kernel launch
+ * per (mode, colour format) group covers
  * the tiles of all the group's requests, whatever their resolution,
  * viewpoint and preview level, and one more upsamples those with D_I > 1.
  * With two or more streams the next batches start while earlier ones
@@ -493,7 +495,9 @@ int vdi_server_create(uint64_t hbm_budget_bytes, int32_t max_inflight, int32_t s
  * the free slots right now (nothing is queued; submit again later).  `out` is
  * a device pointer the caller keeps alive until the request is done.  The
  * server's streams do not wait for other streams: the VDI and `out` must be
- * ready (their writers finished) when the request is submitted.
+ * ready (their writers finished) when the request is submitted.  If one of
+ * the server's streams is free, the call launches the queued requests itself
+ * (on the server's device, restoring the caller's current device after).
  */
 int vdi_server_submit(vdi_server_t s, vdi_t v, const vdi_camera *cam_VN, int32_t width, int32_t height, float D_I,
                       float D_R, float *out, uint64_t *ticket);
@@ -515,6 +519,8 @@ int vdi_server_submit_paced(vdi_server_t s, vdi_t v, const vdi_camera *cam_VN, i
                             vdi_pace_t session, float D_R, float *out_rgba, uint64_t *ticket, float *D_I_used);
 
 /* *done = 1 once the request's image is complete and visible to later work.
+ * A call that finds the request's batch finished retires that batch itself,
+ * without waiting for the scheduler thread.
  * A failed batch (a HIP error) makes this and every later call return VDI_ERR_HIP. */
 int vdi_server_poll(vdi_server_t s, uint64_t ticket, int *done);
 

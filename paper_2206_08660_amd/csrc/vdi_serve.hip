@@ -2,14 +2,16 @@
 // addition; the paper's client renders one request at a time, Section 5).
 //
 // Requests are admitted while request slots and the device-memory budget
-// allow, and queued.  A scheduler thread launches everything queued as one
-// batch as soon as one of the server's streams is free: one launch per
+// allow, and queued.  Everything queued is launched as one batch as soon as
+// one of the server's streams is free, by the submitting thread if a stream
+// is free when it submits, otherwise by a scheduler thread: one launch per
 // (mode, colour format) group renders the tiles of all of the group's
 // requests (k_render_batch), and one more upsamples those with D_I > 1
 // (k_upsample_batch).  With two or more streams the next batch starts while
 // the previous one drains, so the tail of one batch is filled with the next
 // one's tiles and the GPU does not idle between requests.  A request is done
-// when its batch is.
+// when its batch is; the scheduler thread, or a poll of one of its tickets,
+// retires a batch once its completion event has passed.
 //
 // Each batch's job table is copied to device memory before its launches and
 // stays unchanged until they finish, so the kernels read it like kernel
@@ -239,8 +241,17 @@ void run_scheduler(vdi_server_s *s)
                 }
         if (retired || s->err) s->progress.notify_all();
         if (s->stop && !busy && (s->queue.empty() || s->err)) return;
-        if (busy) s->wake.wait_for(lk, std::chrono::microseconds(20));
-        else s->wake.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+        if (busy) {
+            s->wake.wait_for(lk, std::chrono::microseconds(20));
+        } else {
+            // Also woken by a batch that a submitter launched itself.
+            s->wake.wait(lk, [&] {
+                if (s->stop || (!s->queue.empty() && !s->err)) return true;
+                for (const Lane &L : s->lanes)
+                    if (L.busy) return true;
+                return false;
+            });
+        }
     }
 }
 
@@ -346,6 +357,17 @@ int submit(vdi_server_t s, vdi_t v, const vdi_camera *cam, int32_t W, int32_t H,
     s->st.peak_inflight = std::max(s->st.peak_inflight, s->st.inflight);
     s->st.bytes_in_flight += bytes;
     s->st.peak_bytes_in_flight = std::max(s->st.peak_bytes_in_flight, s->st.bytes_in_flight);
+    // A free stream: the submitter launches the queue itself, so that a
+    // request on an idle server does not wait for the scheduler thread to
+    // wake up; the scheduler then only watches the batch for completion.
+    for (Lane &L : s->lanes) {
+        if (L.busy || s->err) continue;
+        int prev = -1;
+        if (hipGetDevice(&prev) == hipSuccess && prev != s->device) (void)hipSetDevice(s->device);
+        launch_batch(s, L);
+        if (prev >= 0 && prev != s->device) (void)hipSetDevice(prev);
+        break;
+    }
     s->wake.notify_one();
     *ticket = t;
     return VDI_OK;
@@ -643,6 +665,24 @@ int vdi_server_poll(vdi_server_t s, uint64_t ticket, int *done)
     if (!s || !done) return vdi::set_error(VDI_ERR_ARG, "null argument");
     std::lock_guard<std::mutex> lock(s->mu);
     if (ticket == 0 || ticket >= s->next_ticket) return vdi::set_error(VDI_ERR_ARG, "unknown ticket");
+    if (s->requests.count(ticket) && !s->err) {
+        // Retire the ticket's batch here if it has finished, rather than at
+        // the scheduler's next look at it.
+        for (vdi::Lane &L : s->lanes) {
+            if (!L.busy || std::find(L.tickets.begin(), L.tickets.end(), ticket) == L.tickets.end()) continue;
+            const hipError_t q = hipEventQuery(L.done);
+            if (q == hipSuccess) {
+                vdi::finish_batch(s, L);
+                s->progress.notify_all();
+                s->wake.notify_one();
+            } else if (q != hipErrorNotReady) {
+                vdi::fail(s, q, "batch");
+                L.busy = false;
+                s->progress.notify_all();
+            }
+            break;
+        }
+    }
     *done = s->requests.count(ticket) ? 0 : 1;
     if (!*done && s->err) return vdi::report(s);
     return VDI_OK;
