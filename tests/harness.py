@@ -176,6 +176,8 @@ def idle_overhead(srv, vdi: "V.Vdi", cam, size: int = 128, n: int = 200) -> dict
     out = torch.empty((size, size, 4), dtype=torch.float32, device="cuda")
     s = torch.cuda.current_stream()
     served, direct, kernel = [], [], []
+    # The three are interleaved, one of each per round, so that clock and
+    # power changes over the run affect them alike.
     with _no_gc():
         for _ in range(n):
             t0 = time.perf_counter()
@@ -184,13 +186,10 @@ def idle_overhead(srv, vdi: "V.Vdi", cam, size: int = 128, n: int = 200) -> dict
             while not srv.poll(t):
                 time.sleep(0)
             served.append(time.perf_counter() - t0)
-        torch.cuda.synchronize()
-        for _ in range(n):
             t0 = time.perf_counter()
             vdi.render(cam, size, size, 1.0, 0.0, out=out, stream=s)
             s.synchronize()
             direct.append(time.perf_counter() - t0)
-        for _ in range(n):
             # The second render is launched while the first one runs, so the
             # events around it time the kernel and not the host's preparation.
             e1, e2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -201,7 +200,7 @@ def idle_overhead(srv, vdi: "V.Vdi", cam, size: int = 128, n: int = 200) -> dict
             e2.synchronize()
             kernel.append(e1.elapsed_time(e2) * 1e-3)
     med = lambda a: round(float(np.median(a)) * 1e3, 4)
-    return {"request": f"{size}x{size} exact, 1080p VDI, one at a time on an idle GPU, {n} each",
+    return {"request": f"{size}x{size} exact, 1080p VDI, one at a time on an idle GPU, {n} rounds of the three",
             "served_p50_ms": med(served), "vdi_render_and_sync_p50_ms": med(direct), "kernel_p50_ms": med(kernel),
             "served_minus_kernel_ms": round(med(served) - med(kernel), 4)}
 
