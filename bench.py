@@ -703,6 +703,10 @@ def cpu_baseline_leg(src, cams, per, precision, np, torch, V):
     the accuracy of the FP32/FP16/BF16 GPU frames on the same sample."""
     import oracle
     rng = np.random.default_rng(1234)
+    # The count grid once, untimed, as vdi_create builds it once outside the
+    # timed step (the oracle would otherwise rebuild it for every preview
+    # call, and the extrapolation would multiply that by the sample's inverse).
+    grid = oracle.count_grid(src)
     frac = {1.0: 0.10, 2.0: 0.10, 4.0: 0.10}
     t_frames = 0.0
     n_px = 0
@@ -731,7 +735,7 @@ def cpu_baseline_leg(src, cams, per, precision, np, torch, V):
                 n = max(64, int(frac[di] * w * hh))
                 tex = np.sort(rng.choice(w * hh, size=n, replace=False))
                 t = time.perf_counter()
-                oracle.render_preview(src, cams[th], w, hh, dr, pixels=tex, aspect=W / H)
+                oracle.render_preview(src, cams[th], w, hh, dr, pixels=tex, aspect=W / H, grid=grid)
                 dt = time.perf_counter() - t
                 t_frames += dt / (n / (w * hh))
             n_px += n
