@@ -256,6 +256,7 @@ def main():
     # written and read back by the upsampling, the output written) against
     # the whole render (preview kernel + upsampling), warm.
     preview_roof = {}
+    preview_bytes_total = {}
     for (di, dr) in MODES:
         if dr == 0.0:
             continue
@@ -270,6 +271,7 @@ def main():
             samples += int(st[..., 0].sum(dtype=torch.int64).item())
             pms += per[(th, di, dr)]
             del lo_img, tl, ts, tc, st
+        preview_bytes_total[(di, dr)] = pb
         preview_roof[f"D_I={di:g},D_R={dr:g}"] = {
             "algorithmic_MB_per_frame": round(pb / len(ANGLES) / 1e6, 2), "ms_per_frame": round(pms / len(ANGLES), 4),
             "achieved_GBs": round(pb / (pms / 1e3) / 1e9, 1), "frac": round(pb / (pms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -328,6 +330,12 @@ def main():
                      "copy_kernel_GBs": round(copy_gbs, 1),
                      "frac_of_copy_kernel": round(achieved / copy_gbs, 4)},
         "preview_roofline": preview_roof,
+        # The whole timed step: the algorithmic bytes of its 30 frames (exact
+        # and preview, as above) over the step time, the two streams together.
+        "step_roofline": {"algorithmic_MB_per_step": round((total_b + sum(preview_bytes_total.values())) / 1e6, 1),
+                          "achieved_GBs": round((total_b + sum(preview_bytes_total.values())) / (ms_step / 1e3) / 1e9, 1),
+                          "frac": round((total_b + sum(preview_bytes_total.values())) / (ms_step / 1e3) / 1e9
+                                        / HBM_PEAK_GBS, 4)},
         "exact_only": {"Mpixels_per_s": round(exact_mpix, 1), "frames_per_s": round(len(ANGLES) / total_s, 1)},
         "one_stream": {"ms_per_step": round(seq_ms_step, 4),
                        "Mpixels_per_s": round(len(renders) * W * H / seq_ms_step / 1e3, 1),
