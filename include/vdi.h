@@ -186,8 +186,9 @@ int vdi_render(vdi_t v, const vdi_camera *cam_VN, int32_t width, int32_t height,
  * earlier.  Device job tables and low-res images are stream-ordered
  * allocations of the library's pool, freed on hip_stream after the launches.
  * Errors: VDI_ERR_ARG (null arrays, n out of range, any frame's arguments as
- * for vdi_render, VDIs on different devices), VDI_ERR_OOM, VDI_ERR_HIP.  On
- * an error nothing has been launched.
+ * for vdi_render, VDIs on different devices; nothing has been launched, and
+ * the message names the first bad frame), VDI_ERR_OOM, VDI_ERR_HIP (some of
+ * the frames may have been launched).
  */
 #define VDI_BATCH_MAX_FRAMES 1024
 int vdi_render_batch(int32_t n, const vdi_t *vdis, const vdi_camera *cams, const int32_t *widths,
