@@ -715,7 +715,7 @@ def cpu_baseline_leg(src, cams, per, precision, np, torch, V):
     # timed step (the oracle would otherwise rebuild it for every preview
     # call, and the extrapolation would multiply that by the sample's inverse).
     grid = oracle.count_grid(src)
-    frac = {1.0: 0.10, 2.0: 0.10, 4.0: 0.10}
+    frac = {1.0: 0.25, 2.0: 0.25, 4.0: 0.25}
     t_frames = 0.0
     n_px = 0
     errs = {"f32": [], "f16": [], "bf16": []}
@@ -790,7 +790,7 @@ def cpu_baseline_leg(src, cams, per, precision, np, torch, V):
     log(f"cpu baseline: {mpix:.4f} Mpixels/s extrapolated (exact frames {mpix_exact:.4f}), {n_px} rays in {cpu_s:.1f}s "
         f"on {oracle.threads()} threads ({cpu_model}); one thread, exact: {mpix_1:.4f} Mpixels/s")
     return {"value": round(mpix, 5), "unit": "Mpixels/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"{n_px} random rays of the 30 frames of one step (10% of each exact frame's pixels, 10% of "
+            "sample": f"{n_px} random rays of the 30 frames of one step (25% of each exact frame's pixels, 25% of "
                       f"each preview frame's low-res ray grid), frame time extrapolated per frame; upsampling not "
                       f"timed",
             "exact_frames_Mpixels_per_s": round(mpix_exact, 5),
