@@ -491,6 +491,34 @@ typedef struct {
 int vdi_server_create(uint64_t hbm_budget_bytes, int32_t max_inflight, int32_t streams, vdi_server_t *out);
 
 /*
+ * Create a server whose requests are rendered by one persistent kernel
+ * instead of batched launches (same submit, poll, drain, stats and destroy
+ * calls, same admission, same images).  The kernel stays resident while
+ * requests come: every workgroup (one wavefront) takes the next render or
+ * upsampling tile of the requests published to it, from a device-memory
+ * queue that the server fills by two copies per request (the job record,
+ * then the job count) on a stream of its own; a request is done when the
+ * kernel has set its flag in host memory, after its results were written
+ * through to device memory.  A launch serves one colour format and up to
+ * 8192 requests, and takes requests only while no VDI has been created,
+ * destroyed or replaced since it started (it reads VDIs through caches that
+ * nothing invalidates while it runs).  The server ends a launch once the
+ * requests published to it are done and the next request cannot be
+ * published to it, or after 20 ms without requests, and starts a new one
+ * for the next request.  While a launch is resident it holds
+ * waves_per_simd wavefronts on every SIMD (0: as many as fit, 6), which
+ * other kernels on the device then do not get.  A workgroup that waits
+ * about 1.8 s for work flags the launch as failed (the server then reports
+ * VDI_ERR_HIP).
+ *   hbm_budget_bytes, max_inflight  as in vdi_server_create.
+ *   waves_per_simd    0..16 (values above what fits take what fits).
+ * Returns VDI_ERR_ARG for arguments out of range and VDI_ERR_HIP / VDI_ERR_OOM
+ * when a stream, event, queue or the scheduler thread cannot be created.
+ */
+int vdi_server_create_persistent(uint64_t hbm_budget_bytes, int32_t max_inflight, int32_t waves_per_simd,
+                                 vdi_server_t *out);
+
+/*
  * Submit a render request (same arguments as vdi_render).  Returns VDI_OK with
  * *ticket set, or VDI_ERR_BUDGET when the request does not fit the budget or
  * the free slots right now (nothing is queued; submit again later).  `out` is

@@ -17,6 +17,9 @@
 
 #include "vdi_internal.h"
 
+namespace vdi {
+std::atomic<uint64_t> g_mem_epoch{0};
+}
 
 namespace {
 
@@ -699,6 +702,7 @@ int vdi_create(const vdi_desc *d, vdi_t *out)
         return rc;
     }
     v->set_bytes = set_bytes_of(d);
+    vdi::g_mem_epoch.fetch_add(1);
     *out = v;
     return VDI_OK;
 }
@@ -769,6 +773,7 @@ int vdi_replace_poll(vdi_t v, int32_t *swapped)
     v->enqueued = false;
     if (q != hipSuccess) return hip_fail(q, "replacement upload");
     std::swap(v->cur, v->back);
+    vdi::g_mem_epoch.fetch_add(1);
     *swapped = 1;
     return VDI_OK;
 }
@@ -893,9 +898,11 @@ int vdi_destroy(vdi_t v)
     if (e != hipSuccess) {
         const int rc = hip_fail(e, "waiting for work on the VDI before destroy");
         free_vdi(v);
+        vdi::g_mem_epoch.fetch_add(1);
         return rc;
     }
     free_vdi(v);
+    vdi::g_mem_epoch.fetch_add(1);
     return VDI_OK;
 }
 

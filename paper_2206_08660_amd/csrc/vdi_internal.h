@@ -167,6 +167,39 @@ struct UpsampleJob {
     uint32_t tile0, ntiles;    // blocks of 256 threads, 64 x 4 output pixels each
 };
 
+// Persistent served launch (vdi_server_create_persistent).  The launch's
+// workgroups take tiles from per-XCD counters until the host stops them.
+// The host publishes a job by writing its record, then the new job count,
+// into coherent host memory (PHost); workgroup 0 of the launch copies new
+// records into device memory and then publishes the count there (PQueue).
+struct alignas(128) PCounter {
+    unsigned long long v;
+    unsigned long long pad[15];  // one 128-byte line per counter
+};
+struct PHost {
+    PCounter tail;         // jobs written by the host
+    PCounter stop;         // nonzero: the launch is to end
+};
+struct PQueue {
+    PCounter next[kXcds];  // tiles taken by the workgroups of XCD x: its k-th is global tile k * kXcds + x
+    PCounter tail;         // jobs whose records are in device memory
+    PCounter stop;         // nonzero: leave once no published tile is left to take
+    PCounter fault;        // nonzero: a workgroup gave up waiting (spin limit); the launch failed
+    PCounter started;      // workgroups that have started
+    PCounter exited;       // workgroups that have left
+};
+// One published request.  Global tiles [R.tile0, R.tile0 + R.ntiles) render
+// it (on the low-res grid when D_I > 1), then, when U.ntiles > 0, tiles
+// [U.tile0, U.tile0 + U.ntiles) upsample it (64 x 4 output pixels each).
+struct alignas(256) PJob {
+    BatchJob R;
+    UpsampleJob U;
+    uint32_t end;     // global tile after the job's last (the next job starts at or after it)
+    uint32_t slot;    // position in the launch's job table: its counters and completion flag
+    int32_t preview;  // D_R > 0
+    int32_t pad;
+};
+
 }  // namespace vdi
 
 namespace vdi {
@@ -229,6 +262,12 @@ double pace_feed(vdi_pace_s *p, double frame_ms);
 // The controller's current D_I.
 double pace_d_i(vdi_pace_s *p);
 
+// Count of changes to the device memory VDIs occupy (a VDI created or
+// destroyed, a replacement swapped in).  A persistent served launch reads
+// VDIs through caches that nothing invalidates while it runs, so it only
+// takes requests while this count is what it was at its start.
+extern std::atomic<uint64_t> g_mem_epoch;
+
 // Host helpers shared by the render and serving entry points (vdi_api.hip).
 // Each returns VDI_OK or an error code after recording the reason.
 int set_error(int code, const char *fmt, ...);
@@ -264,5 +303,16 @@ hipError_t launch_scatter_slots(const void *src, int32_t fmt_in, void *dst, int3
 hipError_t launch_batch_render(const BatchJob *jobs, int32_t njobs, uint32_t nblocks, int32_t fmt, bool preview,
                                hipStream_t stream);
 hipError_t launch_batch_upsample(const UpsampleJob *jobs, int32_t njobs, uint32_t nblocks, hipStream_t stream);
+// Persistent served launch of `blocks` workgroups (see PHost, PQueue; jobs
+// gets the records of host_jobs), for VDIs whose colour is stored in format fmt: done[4 * slot] counts a job's finished render tiles,
+// done[4 * slot + 1] its upsampling tiles, done[4 * slot + 2] its render tiles taken; host_done[slot] (host memory) is
+// set once the job's output is in device memory.  A workgroup that waits
+// longer than about spin_limit sleeps of ~1-4 us for a tile to be published,
+// or for a job's render tiles before upsampling it, sets q->fault and leaves.
+hipError_t launch_persist(int32_t fmt, const PHost *ctl, const PJob *host_jobs, PQueue *q, PJob *jobs, uint32_t *done,
+                          uint32_t *host_done, uint32_t blocks, uint32_t spin_limit, hipStream_t stream);
+// Workgroups of the persistent kernel that can be resident on the device at
+// `waves` per SIMD (at most its occupancy), or 0 on error.
+uint32_t persist_blocks(int device, int waves);
 
 }  // namespace vdi

@@ -63,10 +63,28 @@ __global__ __launch_bounds__(kBlock) VDI_EXACT_OCC void k_render_exact(DevVDI V,
     }
 }
 
+// Store of an output pixel: plain, or (WT) written through to device memory
+// as two relaxed system-scope atomic stores of 8 bytes, for the persistent
+// kernel, whose results are read by other workgroups and by the host with no
+// kernel boundary in between (no dirty line is left in an XCD's L2).
+template <bool WT>
+__device__ __forceinline__ void store_px(float4 *p, float4 v)
+{
+    if constexpr (WT) {
+        auto *u = reinterpret_cast<unsigned long long *>(p);
+        const unsigned long long lo = (unsigned long long)__float_as_uint(v.y) << 32 | __float_as_uint(v.x);
+        const unsigned long long hi = (unsigned long long)__float_as_uint(v.w) << 32 | __float_as_uint(v.z);
+        __hip_atomic_store(u, lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(u + 1, hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    } else {
+        *p = v;
+    }
+}
+
 // One preview tile (preview_tile_dims): tw x th rays, F.parts adjacent lanes
 // per ray.  Lanes outside the image take part in the combination with an
 // empty result.
-template <int FMT, bool COUNT = false>
+template <int FMT, bool COUNT = false, bool WT = false>
 __device__ __forceinline__ void preview_tile(const DevVDI &V, const Frame &F, const float *s_gz, int tile_index)
 {
     const int parts = F.parts;
@@ -82,7 +100,7 @@ __device__ __forceinline__ void preview_tile(const DevVDI &V, const Frame &F, co
     Counters cnt = {0, 0};
     if (in) a = trace_preview<FMT, COUNT>(V, F, s_gz, px, py, lane % parts, parts, &cnt);
     a = combine_parts(a, parts, lane);
-    if (in && lane % parts == 0) F.out[(uint64_t)py * F.W + px] = to_rgba(a);
+    if (in && lane % parts == 0) store_px<WT>(&F.out[(uint64_t)py * F.W + px], to_rgba(a));
     if constexpr (COUNT) {
         if (in && F.ray_stats) {
             atomicAdd(&F.ray_stats[2 * ((uint64_t)py * F.W + px)], cnt.lists);
@@ -150,6 +168,206 @@ __global__ __launch_bounds__(256) void k_upsample_batch(const UpsampleJob *__res
     const int y = (int)(local / (uint32_t)tiles_x) * 4 + (int)(threadIdx.x >> 6);
     if (x >= J.W || y >= J.H) return;
     J.out[(uint64_t)y * J.W + x] = upsample_px(J.lo, J.w, J.h, J.W, J.H, x, y);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent served launch (served form; see PQueue).  Every workgroup (one
+// wavefront) loops: it takes the next tile of its XCD group (global tiles
+// x, x + 8, x + 16, ... for blockIdx.x % 8 == x, so a tile lands on the XCD
+// it would get in a launch of its own), finds the published job that holds
+// it, waiting while the tile lies beyond the published jobs, and renders or
+// upsamples it exactly as k_render_batch / k_upsample_batch would.
+//
+// Coherence without kernel boundaries, and without L2 write-back or
+// invalidation per tile.  Host-written words (the job count, the stop flag)
+// are read with system-scope atomic loads.  A job record is read only after
+// the job count covering it has been seen, and its lines are never read
+// before (records are 256-byte aligned and written once per launch; the
+// launch starts with invalidated caches), so no cache holds an old copy.
+// The VDIs are not written while a launch reads them (the host ends the
+// launch before a VDI is created, destroyed or replaced).  Results are
+// written through to memory (store_px<true>); after its stores have
+// completed (s_waitcnt) lane 0 counts the tile in the job's device counter,
+// and the workgroup that finishes a job's last tile sets its flag in host
+// memory.  Upsampling tiles wait for the job's render counter and read the
+// low-res texels with system-scope atomic loads.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float4 load_px_coherent(const float4 *p)
+{
+    auto *u = reinterpret_cast<unsigned long long *>(const_cast<float4 *>(p));
+    const unsigned long long lo = __hip_atomic_load(u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    const unsigned long long hi = __hip_atomic_load(u + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    return make_float4(__uint_as_float((uint32_t)lo), __uint_as_float((uint32_t)(lo >> 32)),
+                       __uint_as_float((uint32_t)hi), __uint_as_float((uint32_t)(hi >> 32)));
+}
+
+__device__ __forceinline__ unsigned long long load_host_word(unsigned long long *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Sleep of a waiting wavefront: short at first, then about 3 us.
+__device__ __forceinline__ void nap(uint32_t spins)
+{
+    if (spins < 64) __builtin_amdgcn_s_sleep(2);
+    else __builtin_amdgcn_s_sleep(127);
+}
+
+// Field `end` of job record j, read past the caches.
+__device__ __forceinline__ uint32_t job_end(const PJob *jobs, uint32_t j)
+{
+    return __hip_atomic_load(const_cast<uint32_t *>(&jobs[j].end), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Workgroup 0 of a persistent launch: copies the records the host has
+// written into device memory (written through), then publishes their count
+// to the other workgroups; passes the host's stop on.
+__device__ __forceinline__ void persist_mirror(const PHost *ctl, const PJob *host_jobs, PQueue *q, PJob *jobs,
+                                               uint32_t spin_limit)
+{
+    const int lane = (int)threadIdx.x;
+    uint32_t have = 0;
+    for (uint32_t spins = 0;; ++spins) {
+        const uint32_t t = (uint32_t)load_host_word(const_cast<unsigned long long *>(&ctl->tail.v));
+        if (t > have) {
+            for (uint32_t j = have; j < t; ++j) {
+                auto *src = reinterpret_cast<unsigned long long *>(const_cast<PJob *>(host_jobs + j));
+                auto *dst = reinterpret_cast<unsigned long long *>(jobs + j);
+                for (int i = lane; i < (int)(sizeof(PJob) / 8); i += kBlock)
+                    __hip_atomic_store(dst + i, __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+            __builtin_amdgcn_s_waitcnt(0);  // the records are in device memory
+            __syncthreads();
+            if (lane == 0) __hip_atomic_store(&q->tail.v, (unsigned long long)t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            have = t;
+            spins = 0;
+            continue;
+        }
+        const bool stop = load_host_word(const_cast<unsigned long long *>(&ctl->stop.v)) != 0;
+        if (stop || spins >= spin_limit) {
+            if (lane == 0) {
+                if (!stop) __hip_atomic_store(&q->fault.v, 3ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_store(&q->stop.v, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_fetch_add(&q->exited.v, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+            return;
+        }
+        nap(spins);
+    }
+}
+
+template <int FMT>
+__global__ __launch_bounds__(kBlock) VDI_EXACT_OCC void k_persist(const PHost *ctl, const PJob *host_jobs, PQueue *q,
+                                                                  PJob *jobs, uint32_t *done, uint32_t *host_done,
+                                                                  uint32_t spin_limit)
+{
+    __shared__ float s_gz[VDI_MAX_GRID_NZ + 1];
+    __shared__ PJob s_job;  // the record of job `cur`, copied past the caches
+    const int lane = (int)threadIdx.x;
+    if (blockIdx.x == 0) {
+        if (lane == 0) __hip_atomic_fetch_add(&q->started.v, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        persist_mirror(ctl, host_jobs, q, jobs, spin_limit);
+        return;
+    }
+    const uint32_t x = blockIdx.x % kXcds;
+    uint32_t j = 0;            // the jobs before j end at or before every tile this workgroup has still to take
+    uint32_t cur = 0xffffffffu;
+    if (lane == 0) __hip_atomic_fetch_add(&q->started.v, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    for (;;) {
+        unsigned long long k = 0;
+        if (lane == 0) k = __hip_atomic_fetch_add(&q->next[x].v, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        const uint32_t khi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)__shfl((int)(uint32_t)(k >> 32), 0));
+        const uint32_t klo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)__shfl((int)(uint32_t)k, 0));
+        const unsigned long long g = (((unsigned long long)khi << 32) | klo) * kXcds + x;
+        // The published job holding tile g; wait while there is none.
+        for (uint32_t spins = 0;; ++spins) {
+            const uint32_t tail = (uint32_t)load_host_word(&q->tail.v);
+            while (j < tail && g >= job_end(jobs, j)) ++j;
+            if (j < tail) break;
+            if (load_host_word(&q->stop.v) || spins >= spin_limit) {
+                if (lane == 0) {
+                    if (spins >= spin_limit)
+                        __hip_atomic_store(&q->fault.v, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    __hip_atomic_fetch_add(&q->exited.v, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                }
+                return;
+            }
+            nap(spins);
+        }
+        if (j != cur) {
+            // A job this workgroup has not worked on: its record into LDS.
+            auto *src = reinterpret_cast<unsigned long long *>(const_cast<PJob *>(jobs + j));
+            auto *dst = reinterpret_cast<unsigned long long *>(&s_job);
+            for (int i = lane; i < (int)(sizeof(PJob) / 8); i += kBlock)
+                dst[i] = __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __syncthreads();
+            cur = j;
+        }
+        const PJob &J = s_job;
+        const uint32_t slot = J.slot;
+        if (g < J.R.tile0) continue;  // alignment gap before the job
+        if (g < (unsigned long long)J.R.tile0 + J.R.ntiles) {
+            const uint32_t local = (uint32_t)(g - J.R.tile0);
+            if (lane == 0) __hip_atomic_fetch_add(&done[4 * slot + 2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            for (int i = lane; i <= J.R.V.gnz; i += kBlock) s_gz[i] = J.R.V.gz[i];
+            __syncthreads();
+            if (J.preview) {
+                preview_tile<FMT, false, true>(J.R.V, J.R.F, s_gz, (int)local);
+            } else {
+                const int tiles_x = (J.R.F.W + kXTileW - 1) / kXTileW, tiles_y = (J.R.F.H + kXTileH - 1) / kXTileH;
+                const int tile = xcd_tile((int)local, tiles_x, tiles_y, kXBandRows);
+                const int px = (tile % tiles_x) * kXTileW + (lane % kXTileW);
+                const int py = (tile / tiles_x) * kXTileH + (lane / kXTileW);
+                if (px < J.R.F.W && py < J.R.F.H) {
+                    Counters cnt = {0, 0};
+                    store_px<true>(&J.R.F.out[(uint64_t)py * J.R.F.W + px],
+                                   trace_exact<FMT, VDI_SEARCH_WINDOW, true, false>(J.R.V, J.R.F, s_gz, px, py, cnt));
+                }
+            }
+            __builtin_amdgcn_s_waitcnt(0);  // this wavefront's stores have completed
+            __syncthreads();                // and s_gz is free for the next tile
+            if (lane == 0) {
+                const uint32_t n = __hip_atomic_fetch_add(&done[4 * slot], 1u, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_SYSTEM) + 1u;
+                if (n == J.R.ntiles && J.U.ntiles == 0)
+                    __hip_atomic_store(&host_done[slot], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+            continue;
+        }
+        if (g < J.U.tile0) continue;  // alignment gap before the upsampling tiles
+        // Upsampling tile: once every render tile of the job is done.
+        for (uint32_t spins = 0;; ++spins) {
+            if (__hip_atomic_load(&done[4 * slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) >= J.R.ntiles) break;
+            if (spins >= spin_limit) {
+                if (lane == 0) {
+                    __hip_atomic_store(&q->fault.v, 2ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    __hip_atomic_fetch_add(&q->exited.v, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                }
+                return;
+            }
+            nap(spins);
+        }
+        const uint32_t local = (uint32_t)(g - J.U.tile0);
+        const UpsampleJob &U = J.U;
+        const int tiles_x = (U.W + 63) / 64;
+        const int px = (int)(local % (uint32_t)tiles_x) * 64 + lane;
+        for (int r = 0; r < 4; ++r) {
+            const int py = (int)(local / (uint32_t)tiles_x) * 4 + r;
+            if (px < U.W && py < U.H) {
+                const float4 *lo = U.lo;
+                store_px<true>(&U.out[(uint64_t)py * U.W + px],
+                               upsample_px_by([lo](uint64_t i) { return load_px_coherent(lo + i); }, U.w, U.h, U.W,
+                                              U.H, px, py));
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        if (lane == 0) {
+            const uint32_t n = __hip_atomic_fetch_add(&done[4 * slot + 1], 1u, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_SYSTEM) + 1u;
+            if (n == U.ntiles) __hip_atomic_store(&host_done[slot], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -358,6 +576,28 @@ hipError_t launch_grid_bits(const DevVDI &v, uint32_t *bits, hipStream_t s)
     const uint32_t words = (ncells + 31u) / 32u;
     k_grid_bits<<<dim3((words + 255u) / 256u), 256, 0, s>>>(v.grid, bits, ncells);
     return hipGetLastError();
+}
+
+hipError_t launch_persist(int32_t fmt, const PHost *ctl, const PJob *host_jobs, PQueue *q, PJob *jobs, uint32_t *done,
+                          uint32_t *host_done, uint32_t blocks, uint32_t spin_limit, hipStream_t s)
+{
+    if (fmt == VDI_F32)
+        k_persist<VDI_F32><<<dim3(blocks), kBlock, 0, s>>>(ctl, host_jobs, q, jobs, done, host_done, spin_limit);
+    else if (fmt == VDI_F16)
+        k_persist<VDI_F16><<<dim3(blocks), kBlock, 0, s>>>(ctl, host_jobs, q, jobs, done, host_done, spin_limit);
+    else
+        k_persist<VDI_BF16><<<dim3(blocks), kBlock, 0, s>>>(ctl, host_jobs, q, jobs, done, host_done, spin_limit);
+    return hipGetLastError();
+}
+
+uint32_t persist_blocks(int device, int waves)
+{
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persist<VDI_F32>, kBlock, 0) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+    const int simd_waves = per_cu / 4;  // four SIMDs per CU, one wavefront per workgroup
+    const int w = waves > 0 && waves < simd_waves ? waves : simd_waves;
+    return (uint32_t)(w * 4 * cus);
 }
 
 hipError_t launch_scatter_slots(const void *src, int32_t fmt_in, void *dst, int32_t fmt_store, bool depth, uint64_t n,

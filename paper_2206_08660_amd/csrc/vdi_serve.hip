@@ -67,6 +67,7 @@ struct Request {
     UpsampleJob up{};
     uint64_t bytes = 0, lowres_bytes = 0;
     float4 *lowres = nullptr;
+    uint32_t slot = 0;  // persistent engine: the request's position in its launch's job table
 };
 
 // One stream and the buffers of the batch running on it.
@@ -77,6 +78,38 @@ struct Lane {
     UpsampleJob *h_up = nullptr, *d_up = nullptr;
     std::vector<uint64_t> tickets;
     bool busy = false;
+};
+
+// Persistent engine (vdi_server_create_persistent): one resident launch of
+// k_persist takes the tiles of every request published to it.  A request is
+// published by writing its job record and then the new job count to
+// coherent host memory, from which the launch's first workgroup copies it
+// to device memory; the launch flags it done in host memory.  A launch serves
+// one colour format and up to kPersistJobs requests, and only while no VDI
+// has been created, destroyed or replaced since it started; otherwise, and
+// after kPersistIdle with nothing to do, the host stops it once its
+// published requests are done, and the next request starts a new one.
+constexpr uint32_t kPersistJobs = 8192;
+constexpr auto kPersistIdle = std::chrono::milliseconds(20);
+// Sleeps (about 3.4 us each) a workgroup waits for work before it gives up
+// and flags the launch as failed: far beyond kPersistIdle.
+constexpr uint32_t kPersistSpins = 1u << 19;
+struct Persist {
+    hipStream_t kstream = nullptr;                     // the launches
+    hipEvent_t end = nullptr;
+    PQueue *d_q = nullptr;
+    PJob *d_jobs = nullptr, *h_jobs = nullptr;          // kPersistJobs records, device / coherent host
+    PHost *h_ctl = nullptr;                            // job count and stop word (coherent host memory)
+    uint32_t *d_done = nullptr;                        // 4 * kPersistJobs tile counters
+    uint32_t *h_done = nullptr;                        // kPersistJobs completion flags (coherent host memory)
+    uint32_t blocks = 0;
+    bool running = false, ending = false;
+    int32_t fmt = VDI_F32;                             // colour format of the running launch
+    uint32_t used = 0;                                 // jobs published to it
+    uint64_t tiles = 0;                                // global tiles given out by it
+    uint64_t mem_epoch = 0;                            // g_mem_epoch at its start
+    std::vector<uint64_t> published;                   // its tickets not yet retired
+    std::chrono::steady_clock::time_point idle_since;
 };
 
 // Workgroups of an exact render of w x h rays.
@@ -97,6 +130,7 @@ struct vdi_server_s {
     uint64_t budget = 0;
     int max_inflight = 0;
     std::vector<vdi::Lane> lanes;
+    vdi::Persist *P = nullptr;                             // persistent engine (else batched launches on lanes)
     std::deque<uint64_t> queue;                            // admitted, not yet launched (FIFO)
     std::unordered_map<uint64_t, vdi::Request> requests;   // ticket -> request, until done
     std::multimap<uint64_t, float4 *> free_lowres;         // bytes -> pooled preview scratch
@@ -186,10 +220,10 @@ void launch_batch(vdi_server_s *s, Lane &L)
     if (e != hipSuccess) fail(s, e, "batch launch");
 }
 
-// Retire the requests of lane L's finished batch (lock held).
-void finish_batch(vdi_server_s *s, Lane &L)
+// Retire a finished request (lock held).
+void finish_request(vdi_server_s *s, uint64_t tk)
 {
-    for (uint64_t tk : L.tickets) {
+    {
         auto it = s->requests.find(tk);
         Request &r = it->second;
         if (r.lowres) s->free_lowres.emplace(r.lowres_bytes, r.lowres);
@@ -207,8 +241,166 @@ void finish_batch(vdi_server_s *s, Lane &L)
         s->st.completed++;
         s->requests.erase(it);
     }
+}
+
+// Retire the requests of lane L's finished batch (lock held).
+void finish_batch(vdi_server_s *s, Lane &L)
+{
+    for (uint64_t tk : L.tickets) finish_request(s, tk);
     L.tickets.clear();
     L.busy = false;
+}
+
+// ---------------------------------------------------------------------------
+// Persistent engine (lock held in all of these)
+// ---------------------------------------------------------------------------
+// Start a launch for colour format fmt: clear its queue and counters on the
+// launch stream, let the feed stream copy only after that, launch.
+void persist_launch(vdi_server_s *s, int32_t fmt)
+{
+    Persist &P = *s->P;
+    // No launch is running: the host words can be cleared directly.
+    memset(P.h_done, 0, sizeof(uint32_t) * kPersistJobs);
+    __atomic_store_n(&P.h_ctl->tail.v, 0ull, __ATOMIC_RELEASE);
+    __atomic_store_n(&P.h_ctl->stop.v, 0ull, __ATOMIC_RELEASE);
+    hipError_t e = hipMemsetAsync(P.d_q, 0, sizeof(PQueue), P.kstream);
+    if (e == hipSuccess) e = hipMemsetAsync(P.d_done, 0, sizeof(uint32_t) * 4 * kPersistJobs, P.kstream);
+    if (e == hipSuccess)
+        e = launch_persist(fmt, P.h_ctl, P.h_jobs, P.d_q, P.d_jobs, P.d_done, P.h_done, P.blocks, kPersistSpins,
+                           P.kstream);
+    if (e == hipSuccess) e = hipEventRecord(P.end, P.kstream);
+    if (e != hipSuccess) {
+        fail(s, e, "persistent launch");
+        return;
+    }
+    P.running = true;
+    P.ending = false;
+    P.fmt = fmt;
+    P.used = 0;
+    P.tiles = 0;
+    P.mem_epoch = g_mem_epoch.load();
+    P.idle_since = std::chrono::steady_clock::now();
+    s->st.batches++;
+}
+
+// Publish queued requests to the running launch, starting one if none runs;
+// a request the launch cannot take marks it to be ended.
+void persist_pump(vdi_server_s *s)
+{
+    Persist &P = *s->P;
+    while (!s->queue.empty() && !s->err && !P.ending) {
+        const uint64_t tk = s->queue.front();
+        Request &r = s->requests.at(tk);
+        if (!P.running) persist_launch(s, r.fmt);
+        if (s->err) return;
+        const uint64_t t0 = align_up(P.tiles);
+        const uint64_t u0 = align_up(t0 + r.job.ntiles);
+        const uint64_t end = r.down ? u0 + r.up.ntiles : t0 + r.job.ntiles;
+        if (r.fmt != P.fmt || P.used >= kPersistJobs || end >= (1ull << 31) || g_mem_epoch.load() != P.mem_epoch) {
+            P.ending = true;
+            return;
+        }
+        const uint32_t j = P.used++;
+        r.slot = j;
+        r.job.tile0 = (uint32_t)t0;
+        PJob &J = P.h_jobs[j];
+        J.R = r.job;
+        J.U = r.up;
+        J.U.tile0 = (uint32_t)u0;
+        if (!r.down) J.U.ntiles = 0;
+        J.end = (uint32_t)end;
+        J.slot = j;
+        J.preview = r.preview ? 1 : 0;
+        J.pad = 0;
+        P.tiles = end;
+        // The record is written before the count that publishes it (x86 keeps store order).
+        __atomic_store_n(&P.h_ctl->tail.v, (unsigned long long)(j + 1), __ATOMIC_RELEASE);
+        s->queue.pop_front();
+        P.published.push_back(tk);
+        s->st.queued = (int32_t)s->queue.size();
+    }
+}
+
+// Retire published requests whose flag the launch has set; true if any.
+bool persist_retire(vdi_server_s *s)
+{
+    Persist &P = *s->P;
+    bool any = false;
+    for (size_t i = 0; i < P.published.size();) {
+        const uint64_t tk = P.published[i];
+        if (__atomic_load_n(&P.h_done[s->requests.at(tk).slot], __ATOMIC_ACQUIRE) != 0u) {
+            finish_request(s, tk);
+            P.published[i] = P.published.back();
+            P.published.pop_back();
+            any = true;
+        } else {
+            ++i;
+        }
+    }
+    if (any || !P.published.empty() || !s->queue.empty()) P.idle_since = std::chrono::steady_clock::now();
+    return any;
+}
+
+// State of an ended launch that left requests unfinished: its fault word,
+// job count and tile counters, and the tile counts and flags of the first
+// unfinished requests.
+std::string persist_diagnose(vdi_server_s *s)
+{
+    Persist &P = *s->P;
+    PQueue q{};
+    std::string d;
+    if (hipMemcpy(&q, P.d_q, sizeof q, hipMemcpyDeviceToHost) != hipSuccess) return "(queue unreadable)";
+    char buf[256];
+    snprintf(buf, sizeof buf, "fault %llu, workgroups %u started %llu exited %llu, jobs %llu/%u published, tiles given %llu; taken per XCD:",
+             q.fault.v, P.blocks, q.started.v, q.exited.v, q.tail.v, P.used, (unsigned long long)P.tiles);
+    d += buf;
+    for (int x = 0; x < kXcds; ++x) d += " " + std::to_string(q.next[x].v);
+    for (size_t i = 0; i < P.published.size() && i < 3; ++i) {
+        const Request &r = s->requests.at(P.published[i]);
+        uint32_t c[4] = {0, 0, 0, 0};
+        (void)hipMemcpy(c, P.d_done + 4 * r.slot, sizeof c, hipMemcpyDeviceToHost);
+        const PJob &J = P.h_jobs[r.slot];
+        snprintf(buf, sizeof buf, "; slot %u: render %u/%u (taken %u) from tile %u, upsample %u/%u from %u, end %u, flag %u",
+                 r.slot, c[0], J.R.ntiles, c[2], J.R.tile0, c[1], J.U.ntiles, J.U.tile0, J.end,
+                 __atomic_load_n(&P.h_done[r.slot], __ATOMIC_ACQUIRE));
+        d += buf;
+    }
+    return d;
+}
+
+// Write the stop word and wait for the launch to end; *fault gets its fault word.
+hipError_t persist_halt(vdi_server_s *s, unsigned long long *fault)
+{
+    Persist &P = *s->P;
+    __atomic_store_n(&P.h_ctl->stop.v, 1ull, __ATOMIC_RELEASE);
+    hipError_t e = hipEventSynchronize(P.end);
+    *fault = 0;
+    if (e == hipSuccess) e = hipMemcpy(fault, &P.d_q->fault.v, sizeof *fault, hipMemcpyDeviceToHost);
+    P.running = false;
+    P.ending = false;
+    return e;
+}
+
+// Stop the running launch when it has nothing left in flight and must end
+// (it cannot take the next request, the server stops, or it has idled for
+// kPersistIdle); also notice a launch that ended by itself (a fault).
+void persist_check_end(vdi_server_s *s)
+{
+    Persist &P = *s->P;
+    if (!P.running || s->err) return;
+    if (!P.published.empty()) {
+        if (hipEventQuery(P.end) == hipSuccess) {
+            const std::string d = "persistent launch ended with work in flight (" + persist_diagnose(s) + ")";
+            fail(s, hipErrorLaunchFailure, d.c_str());
+        }
+        return;
+    }
+    const bool idle = s->queue.empty() && std::chrono::steady_clock::now() - P.idle_since > kPersistIdle;
+    if (!P.ending && !s->stop && !idle) return;
+    unsigned long long fault = 0;
+    const hipError_t e = persist_halt(s, &fault);
+    if (e != hipSuccess) fail(s, e, "stopping the persistent launch");
+    else if (fault) fail(s, hipErrorLaunchTimeOut, "persistent launch gave up waiting for work");
 }
 
 void run_scheduler(vdi_server_s *s)
@@ -218,6 +410,29 @@ void run_scheduler(vdi_server_s *s)
     // slack of 50 us on top, which an idle-GPU request pays once or twice.
     (void)prctl(PR_SET_TIMERSLACK, 1UL, 0UL, 0UL, 0UL);
     std::unique_lock<std::mutex> lk(s->mu);
+    while (s->P) {
+        Persist &P = *s->P;
+        bool retired = false;
+        if (!s->err) {
+            retired = persist_retire(s);
+            persist_pump(s);
+            persist_check_end(s);
+            persist_pump(s);  // into a new launch, if the last one ended for the next request
+        }
+        if (s->err && P.running) {
+            unsigned long long fault = 0;
+            (void)persist_halt(s, &fault);
+        }
+        if (retired || s->err) s->progress.notify_all();
+        if (s->stop && !P.running && (s->queue.empty() || s->err)) return;
+        if (s->err) {
+            s->wake.wait(lk, [&] { return s->stop; });
+            continue;
+        }
+        if (!P.published.empty() || !s->queue.empty()) s->wake.wait_for(lk, std::chrono::microseconds(20));
+        else if (P.running || s->stop) s->wake.wait_for(lk, std::chrono::milliseconds(2));
+        else s->wake.wait(lk, [&] { return s->stop || !s->queue.empty() || !P.published.empty() || P.running; });
+    }
     for (;;) {
         bool busy = false, retired = false;
         for (Lane &L : s->lanes) {
@@ -266,6 +481,19 @@ void release(vdi_server_s *s)
         if (L.h_up) (void)hipHostFree(L.h_up);
         if (L.d_jobs) (void)hipFree(L.d_jobs);
         if (L.d_up) (void)hipFree(L.d_up);
+    }
+    if (s->P) {
+        vdi::Persist &P = *s->P;
+        if (P.kstream) (void)hipStreamSynchronize(P.kstream);
+        if (P.end) (void)hipEventDestroy(P.end);
+        if (P.kstream) (void)hipStreamDestroy(P.kstream);
+        if (P.d_q) (void)hipFree(P.d_q);
+        if (P.d_jobs) (void)hipFree(P.d_jobs);
+        if (P.d_done) (void)hipFree(P.d_done);
+        if (P.h_jobs) (void)hipHostFree(P.h_jobs);
+        if (P.h_ctl) (void)hipHostFree(P.h_ctl);
+        if (P.h_done) (void)hipHostFree(P.h_done);
+        delete s->P;
     }
     for (float4 *p : s->all_lowres) (void)hipFree(p);
     // Requests never retired (the server failed): their VDIs are not read any more.
@@ -357,6 +585,13 @@ int submit(vdi_server_t s, vdi_t v, const vdi_camera *cam, int32_t W, int32_t H,
     s->st.peak_inflight = std::max(s->st.peak_inflight, s->st.inflight);
     s->st.bytes_in_flight += bytes;
     s->st.peak_bytes_in_flight = std::max(s->st.peak_bytes_in_flight, s->st.bytes_in_flight);
+    // Persistent engine: the submitter publishes the request itself.
+    if (s->P) {
+        int prev = -1;
+        if (hipGetDevice(&prev) == hipSuccess && prev != s->device) (void)hipSetDevice(s->device);
+        vdi::persist_pump(s);
+        if (prev >= 0 && prev != s->device) (void)hipSetDevice(prev);
+    }
     // A free stream: the submitter launches the queue itself, so that a
     // request on an idle server does not wait for the scheduler thread to
     // wake up; the scheduler then only watches the batch for completion.
@@ -591,6 +826,63 @@ int render_batch(int32_t n, const vdi_t *vdis, const vdi_camera *cams, const int
 
 extern "C" {
 
+int vdi_server_create_persistent(uint64_t hbm_budget_bytes, int32_t max_inflight, int32_t waves_per_simd,
+                                 vdi_server_t *out)
+{
+    if (!out) return vdi::set_error(VDI_ERR_ARG, "null output");
+    *out = nullptr;
+    if (hbm_budget_bytes == 0) return vdi::set_error(VDI_ERR_ARG, "hbm_budget_bytes must be > 0");
+    if (max_inflight < 1 || max_inflight > vdi::kMaxSlots)
+        return vdi::set_error(VDI_ERR_ARG, "max_inflight must be in [1, %d]", vdi::kMaxSlots);
+    if (waves_per_simd < 0 || waves_per_simd > 16) return vdi::set_error(VDI_ERR_ARG, "waves_per_simd must be in [0, 16]");
+    vdi_server_s *s = new (std::nothrow) vdi_server_s();
+    if (!s) return vdi::set_error(VDI_ERR_OOM, "host allocation");
+    hipError_t e = hipGetDevice(&s->device);
+    if (e != hipSuccess) {
+        delete s;
+        return vdi::hip_error(e, "hipGetDevice");
+    }
+    s->budget = hbm_budget_bytes;
+    s->max_inflight = max_inflight;
+    s->P = new (std::nothrow) vdi::Persist();
+    if (!s->P) {
+        delete s;
+        return vdi::set_error(VDI_ERR_OOM, "host allocation");
+    }
+    vdi::Persist &P = *s->P;
+    const char *what = "streams";
+    e = hipStreamCreateWithFlags(&P.kstream, hipStreamNonBlocking);
+    if (e == hipSuccess) what = "event", e = hipEventCreateWithFlags(&P.end, hipEventDisableTiming);
+    if (e == hipSuccess) what = "job queue", e = hipMalloc((void **)&P.d_q, sizeof(vdi::PQueue));
+    if (e == hipSuccess) e = hipMalloc((void **)&P.d_jobs, sizeof(vdi::PJob) * vdi::kPersistJobs);
+    if (e == hipSuccess) e = hipMalloc((void **)&P.d_done, sizeof(uint32_t) * 4 * vdi::kPersistJobs);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&P.h_jobs, sizeof(vdi::PJob) * vdi::kPersistJobs, hipHostMallocCoherent);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&P.h_ctl, sizeof(vdi::PHost), hipHostMallocCoherent);
+    if (e == hipSuccess)
+        what = "completion flags",
+        e = hipHostMalloc((void **)&P.h_done, sizeof(uint32_t) * vdi::kPersistJobs, hipHostMallocCoherent);
+    if (e == hipSuccess) {
+        memset(P.h_ctl, 0, sizeof(vdi::PHost));
+        // Workgroup 0 copies the records; the others take tiles.
+        P.blocks = vdi::persist_blocks(s->device, waves_per_simd);
+        if (P.blocks == 0) what = "occupancy query", e = hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) {
+        const int rc = vdi::hip_error(e, what);
+        vdi::release(s);
+        return rc;
+    }
+    try {
+        s->scheduler = std::thread(vdi::run_scheduler, s);
+    } catch (...) {
+        vdi::release(s);
+        return vdi::set_error(VDI_ERR_OOM, "scheduler thread");
+    }
+    *out = s;
+    return VDI_OK;
+}
+
 int vdi_server_create(uint64_t hbm_budget_bytes, int32_t max_inflight, int32_t streams, vdi_server_t *out)
 {
     if (!out) return vdi::set_error(VDI_ERR_ARG, "null output");
@@ -665,7 +957,12 @@ int vdi_server_poll(vdi_server_t s, uint64_t ticket, int *done)
     if (!s || !done) return vdi::set_error(VDI_ERR_ARG, "null argument");
     std::lock_guard<std::mutex> lock(s->mu);
     if (ticket == 0 || ticket >= s->next_ticket) return vdi::set_error(VDI_ERR_ARG, "unknown ticket");
-    if (s->requests.count(ticket) && !s->err) {
+    if (s->P && s->requests.count(ticket) && !s->err) {
+        if (vdi::persist_retire(s)) {
+            s->progress.notify_all();
+            s->wake.notify_one();
+        }
+    } else if (s->requests.count(ticket) && !s->err) {
         // Retire the ticket's batch here if it has finished, rather than at
         // the scheduler's next look at it.
         for (vdi::Lane &L : s->lanes) {

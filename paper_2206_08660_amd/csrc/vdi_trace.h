@@ -1089,7 +1089,9 @@ VDI_HD inline float4 to_rgba(const Accum &A) { return make_float4(A.r, A.g, A.b,
 // Bilinear upsampling of one output pixel (x, y) of a W x H image from a
 // w x h image, half-pixel centres, clamped (Section 4.4, Fig. 7 caption).
 // ---------------------------------------------------------------------------
-VDI_HD inline float4 upsample_px(const float4 *__restrict__ lo, int w, int h, int W, int H, int x, int y)
+// `texel(i)` gives texel i of the low-res image (row-major).
+template <typename Texel>
+VDI_HD inline float4 upsample_px_by(const Texel &texel, int w, int h, int W, int H, int x, int y)
 {
     double sx = (x + 0.5) * (double)w / W - 0.5, sy = (y + 0.5) * (double)h / H - 0.5;
     sx = fmin(fmax(sx, 0.0), (double)(w - 1));
@@ -1097,8 +1099,8 @@ VDI_HD inline float4 upsample_px(const float4 *__restrict__ lo, int w, int h, in
     const int x0 = (int)sx, y0 = (int)sy;
     const int x1 = min(x0 + 1, w - 1), y1 = min(y0 + 1, h - 1);
     const float fx = (float)(sx - x0), fy = (float)(sy - y0);
-    const float4 a = lo[(uint64_t)y0 * w + x0], b = lo[(uint64_t)y0 * w + x1];
-    const float4 c = lo[(uint64_t)y1 * w + x0], d = lo[(uint64_t)y1 * w + x1];
+    const float4 a = texel((uint64_t)y0 * w + x0), b = texel((uint64_t)y0 * w + x1);
+    const float4 c = texel((uint64_t)y1 * w + x0), d = texel((uint64_t)y1 * w + x1);
     // Explicit fused multiply-adds: the result does not depend on how a
     // compiler contracts the expression in the kernel it is inlined into.
     auto mix = [&](float pa, float pb, float pc, float pd) {
@@ -1107,6 +1109,11 @@ VDI_HD inline float4 upsample_px(const float4 *__restrict__ lo, int w, int h, in
     };
     return make_float4(mix(a.x, b.x, c.x, d.x), mix(a.y, b.y, c.y, d.y), mix(a.z, b.z, c.z, d.z),
                        mix(a.w, b.w, c.w, d.w));
+}
+
+VDI_HD inline float4 upsample_px(const float4 *__restrict__ lo, int w, int h, int W, int H, int x, int y)
+{
+    return upsample_px_by([lo](uint64_t i) { return lo[i]; }, w, h, W, H, x, y);
 }
 
 }  // namespace vdi

@@ -10,11 +10,18 @@ from . import vdi as V
 
 
 class Server:
-    """A continuous-batching server on the current device."""
+    """A continuous-batching server on the current device: batched launches
+    (vdi_server_create), or one persistent kernel when `persistent` is set
+    (vdi_server_create_persistent; `waves_per_simd` 0 = as many as fit)."""
 
-    def __init__(self, budget_bytes: int, max_inflight: int = 64, streams: int = 0):
+    def __init__(self, budget_bytes: int, max_inflight: int = 64, streams: int = 0, persistent: bool = False,
+                 waves_per_simd: int = 0):
         h = ctypes.c_void_p()
-        V._check(V.lib().vdi_server_create(int(budget_bytes), int(max_inflight), int(streams), ctypes.byref(h)))
+        if persistent:
+            V._check(V.lib().vdi_server_create_persistent(int(budget_bytes), int(max_inflight), int(waves_per_simd),
+                                                          ctypes.byref(h)))
+        else:
+            V._check(V.lib().vdi_server_create(int(budget_bytes), int(max_inflight), int(streams), ctypes.byref(h)))
         self._h = h
 
     def submit(self, vdi: "V.Vdi", cam, width: int, height: int, d_i: float, d_r: float, out) -> Optional[int]:

@@ -32,7 +32,7 @@ EXPORTS = ("vdi_create", "vdi_render", "vdi_render_ex", "vdi_render_counters", "
            "vdi_server_reset_stats", "vdi_server_destroy", "vdi_replace_begin", "vdi_replace_poll",
            "vdi_pace_create", "vdi_pace_update", "vdi_pace_destroy", "vdi_generate", "vdi_dvr",
            "vdi_image_quality", "vdi_render_noalloc", "vdi_preview_counters", "vdi_server_submit_paced",
-           "vdi_render_batch")
+           "vdi_render_batch", "vdi_server_create_persistent")
 
 VOXEL = {"f32": 0, "u16": 1}
 TF = {"ramp": 0, "knots4": 1}
@@ -126,6 +126,7 @@ def lib() -> ctypes.CDLL:
         L.vdi_plane_bytes.restype = ctypes.c_uint64
         L.vdi_last_error.restype = ctypes.c_char_p
         L.vdi_server_create.argtypes = [ctypes.c_uint64, I32, I32, ctypes.POINTER(P)]
+        L.vdi_server_create_persistent.argtypes = [ctypes.c_uint64, I32, I32, ctypes.POINTER(P)]
         L.vdi_server_submit.argtypes = [P, P, ctypes.POINTER(Camera), I32, I32, F, F, P,
                                         ctypes.POINTER(ctypes.c_uint64)]
         L.vdi_server_submit_paced.argtypes = [P, P, ctypes.POINTER(Camera), I32, I32, P, F, P,

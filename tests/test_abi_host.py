@@ -122,6 +122,19 @@ def test_server_create_rejects_bad_arguments_before_any_device_work():
     assert lib.vdi_server_destroy(None) == V.VDI_OK
 
 
+def test_persistent_server_create_rejects_bad_arguments_before_any_device_work():
+    lib = V.lib()
+    h = ctypes.c_void_p()
+    assert lib.vdi_server_create_persistent(1 << 30, 4, 0, None) == V.VDI_ERR_ARG
+    assert lib.vdi_server_create_persistent(0, 4, 0, ctypes.byref(h)) == V.VDI_ERR_ARG
+    assert lib.vdi_server_create_persistent(1 << 30, 0, 0, ctypes.byref(h)) == V.VDI_ERR_ARG
+    assert lib.vdi_server_create_persistent(1 << 30, 4097, 0, ctypes.byref(h)) == V.VDI_ERR_ARG
+    assert lib.vdi_server_create_persistent(1 << 30, 4, -1, ctypes.byref(h)) == V.VDI_ERR_ARG
+    assert lib.vdi_server_create_persistent(1 << 30, 4, 17, ctypes.byref(h)) == V.VDI_ERR_ARG
+    assert "waves_per_simd" in V.last_error()
+    assert h.value is None
+
+
 def test_replace_rejects_null_arguments_before_any_device_work():
     lib = V.lib()
     d = V.Desc()
