@@ -506,7 +506,7 @@ int vdi_server_create(uint64_t hbm_budget_bytes, int32_t max_inflight, int32_t s
  * requests published to it are done and the next request cannot be
  * published to it, or after 20 ms without requests, and starts a new one
  * for the next request.  While a launch is resident it holds
- * waves_per_simd wavefronts on every SIMD (0: as many as fit, 6), which
+ * waves_per_simd wavefronts on every SIMD (0: as many as fit, 5), which
  * other kernels on the device then do not get.  A workgroup that waits
  * about 1.8 s for work flags the launch as failed (the server then reports
  * VDI_ERR_HIP).

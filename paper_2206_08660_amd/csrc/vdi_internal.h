@@ -188,6 +188,15 @@ struct PQueue {
     PCounter started;      // workgroups that have started
     PCounter exited;       // workgroups that have left
 };
+// Completion counters of one job in the persistent launch's table: word
+// done_word(part, x) counts the finished tiles of XCD group x (x < kXcds) of
+// part 0 (render) or 1 (upsampling), done_word(part, kXcds) the groups that
+// have finished that part; every counter on a 128-byte line of its own.
+constexpr int kDoneWords = 2 * (kXcds + 1) * 32;
+__host__ __device__ inline int done_word(int part, int x) { return (part * (kXcds + 1) + x) * 32; }
+// Tiles of XCD group x among n tiles from a multiple of kXcds.
+__host__ __device__ inline uint32_t group_tiles(uint32_t n, uint32_t x) { return n / kXcds + (x < n % kXcds ? 1u : 0u); }
+
 // One published request.  Global tiles [R.tile0, R.tile0 + R.ntiles) render
 // it (on the low-res grid when D_I > 1), then, when U.ntiles > 0, tiles
 // [U.tile0, U.tile0 + U.ntiles) upsample it (64 x 4 output pixels each).
@@ -304,11 +313,12 @@ hipError_t launch_batch_render(const BatchJob *jobs, int32_t njobs, uint32_t nbl
                                hipStream_t stream);
 hipError_t launch_batch_upsample(const UpsampleJob *jobs, int32_t njobs, uint32_t nblocks, hipStream_t stream);
 // Persistent served launch of `blocks` workgroups (see PHost, PQueue; jobs
-// gets the records of host_jobs), for VDIs whose colour is stored in format fmt: done[4 * slot] counts a job's finished render tiles,
-// done[4 * slot + 1] its upsampling tiles, done[4 * slot + 2] its render tiles taken; host_done[slot] (host memory) is
-// set once the job's output is in device memory.  A workgroup that waits
-// longer than about spin_limit sleeps of ~1-4 us for a tile to be published,
-// or for a job's render tiles before upsampling it, sets q->fault and leaves.
+// gets the records of host_jobs), for VDIs whose colour is stored in format
+// fmt.  done + kDoneWords * slot holds a job's completion counters
+// (done_word); host_done[slot] (host memory) is set once the job's output is
+// in device memory.  A workgroup that waits longer than about spin_limit
+// sleeps of ~27 us for a tile to be published, or for a job's render tiles
+// before upsampling it, sets q->fault and leaves.
 hipError_t launch_persist(int32_t fmt, const PHost *ctl, const PJob *host_jobs, PQueue *q, PJob *jobs, uint32_t *done,
                           uint32_t *host_done, uint32_t blocks, uint32_t spin_limit, hipStream_t stream);
 // Workgroups of the persistent kernel that can be resident on the device at

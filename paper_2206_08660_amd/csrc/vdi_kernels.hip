@@ -177,46 +177,60 @@ __global__ __launch_bounds__(256) void k_upsample_batch(const UpsampleJob *__res
 // it would get in a launch of its own), finds the published job that holds
 // it, waiting while the tile lies beyond the published jobs, and renders or
 // upsamples it exactly as k_render_batch / k_upsample_batch would.
+// Workgroup 0 takes no tiles: it publishes the jobs the host writes.
 //
 // Coherence without kernel boundaries, and without L2 write-back or
-// invalidation per tile.  Host-written words (the job count, the stop flag)
-// are read with system-scope atomic loads.  A job record is read only after
-// the job count covering it has been seen, and its lines are never read
-// before (records are 256-byte aligned and written once per launch; the
-// launch starts with invalidated caches), so no cache holds an old copy.
-// The VDIs are not written while a launch reads them (the host ends the
-// launch before a VDI is created, destroyed or replaced).  Results are
-// written through to memory (store_px<true>); after its stores have
-// completed (s_waitcnt) lane 0 counts the tile in the job's device counter,
-// and the workgroup that finishes a job's last tile sets its flag in host
-// memory.  Upsampling tiles wait for the job's render counter and read the
-// low-res texels with system-scope atomic loads.
+// invalidation per tile.  The host writes a job's record, then the job
+// count, to coherent host memory; workgroup 0 copies new records into
+// device memory with stores written through to memory and only then
+// publishes their count there (persist_mirror).  Every word another agent
+// or workgroup writes during the launch (counts, stop word, records, tile
+// counters) is read with system-scope atomic loads, which no cache answers
+// with an old copy.  A job record is read with plain (scalar) loads, but
+// only once its count is published, that is once it is in memory, and no
+// cache holds its lines before: records are 256-byte aligned, written once
+// per launch, and the launch starts with invalidated caches.  (Two copies on
+// one stream, record then count, were not seen in that order by all XCDs
+// while the launch filled the device: hence the mirror.)  The
+// VDIs are not written while a launch reads them: the host ends the launch
+// before a VDI is created, destroyed or replaced.  Results are written
+// through to memory (store_px<true>); after its stores have completed
+// (s_waitcnt) lane 0 counts the tile in the job's counter, and the
+// workgroup that finishes a job's last tile sets its flag in host memory.
+// Upsampling tiles wait until every XCD group has finished the job's render
+// tiles, then read the low-res texels through the caches: the server gives
+// each request of a launch a low-res image in memory that no cache has held
+// during the launch.  A job's tiles are counted per XCD group, each counter
+// on a line of its own, so that its tiles do not all update one word.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float4 load_px_coherent(const float4 *p)
-{
-    auto *u = reinterpret_cast<unsigned long long *>(const_cast<float4 *>(p));
-    const unsigned long long lo = __hip_atomic_load(u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    const unsigned long long hi = __hip_atomic_load(u + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    return make_float4(__uint_as_float((uint32_t)lo), __uint_as_float((uint32_t)(lo >> 32)),
-                       __uint_as_float((uint32_t)hi), __uint_as_float((uint32_t)(hi >> 32)));
-}
-
 __device__ __forceinline__ unsigned long long load_host_word(unsigned long long *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// Sleep of a waiting wavefront: short at first, then about 3 us.
-__device__ __forceinline__ void nap(uint32_t spins)
+// Count a finished tile of XCD group x in part `part` of a job with n tiles
+// in that part (counters D, see done_word); true for the tile that finishes
+// the part, whose last group counts itself in the part's group count.
+__device__ __forceinline__ bool tile_done(uint32_t *D, int part, uint32_t x, uint32_t n)
 {
-    if (spins < 64) __builtin_amdgcn_s_sleep(2);
-    else __builtin_amdgcn_s_sleep(127);
+    const uint32_t c = __hip_atomic_fetch_add(&D[done_word(part, (int)x)], 1u, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_SYSTEM) + 1u;
+    if (c != group_tiles(n, x)) return false;
+    const uint32_t groups = n < (uint32_t)kXcds ? n : (uint32_t)kXcds;
+    return __hip_atomic_fetch_add(&D[done_word(part, kXcds)], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) + 1u ==
+           groups;
 }
 
-// Field `end` of job record j, read past the caches.
-__device__ __forceinline__ uint32_t job_end(const PJob *jobs, uint32_t j)
+// Sleep of a waiting wavefront: short at first, then about 27 us, so that
+// thousands of idle wavefronts polling a word in memory do not load the
+// memory system the working ones use.
+__device__ __forceinline__ void nap(uint32_t spins)
 {
-    return __hip_atomic_load(const_cast<uint32_t *>(&jobs[j].end), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (spins < 64) {
+        __builtin_amdgcn_s_sleep(2);
+    } else {
+        for (int i = 0; i < 8; ++i) __builtin_amdgcn_s_sleep(127);
+    }
 }
 
 // Workgroup 0 of a persistent launch: copies the records the host has
@@ -257,22 +271,29 @@ __device__ __forceinline__ void persist_mirror(const PHost *ctl, const PJob *hos
     }
 }
 
+// Compiled for 5 wavefronts per SIMD (96 VGPRs): with both walkers in one
+// loop it spilled 18-48 VGPRs per lane at 6.
+#define VDI_PERSIST_OCC __attribute__((amdgpu_waves_per_eu(5)))
+
+// `mirror_jobs` and `jobs` are the same table: workgroup 0 writes it through
+// the first, the others only read it through the second (scalar loads of a
+// record that no cache holds before it is published).
 template <int FMT>
-__global__ __launch_bounds__(kBlock) VDI_EXACT_OCC void k_persist(const PHost *ctl, const PJob *host_jobs, PQueue *q,
-                                                                  PJob *jobs, uint32_t *done, uint32_t *host_done,
+__global__ __launch_bounds__(kBlock) VDI_PERSIST_OCC void k_persist(const PHost *ctl, const PJob *host_jobs, PQueue *q,
+                                                                  PJob *mirror_jobs, const PJob *__restrict__ jobs,
+                                                                  uint32_t *done, uint32_t *host_done,
                                                                   uint32_t spin_limit)
 {
     __shared__ float s_gz[VDI_MAX_GRID_NZ + 1];
-    __shared__ PJob s_job;  // the record of job `cur`, copied past the caches
     const int lane = (int)threadIdx.x;
     if (blockIdx.x == 0) {
         if (lane == 0) __hip_atomic_fetch_add(&q->started.v, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        persist_mirror(ctl, host_jobs, q, jobs, spin_limit);
+        persist_mirror(ctl, host_jobs, q, mirror_jobs, spin_limit);
         return;
     }
     const uint32_t x = blockIdx.x % kXcds;
     uint32_t j = 0;            // the jobs before j end at or before every tile this workgroup has still to take
-    uint32_t cur = 0xffffffffu;
+    uint32_t tail = 0;         // jobs known to be published
     if (lane == 0) __hip_atomic_fetch_add(&q->started.v, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     for (;;) {
         unsigned long long k = 0;
@@ -280,10 +301,13 @@ __global__ __launch_bounds__(kBlock) VDI_EXACT_OCC void k_persist(const PHost *c
         const uint32_t khi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)__shfl((int)(uint32_t)(k >> 32), 0));
         const uint32_t klo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)__shfl((int)(uint32_t)k, 0));
         const unsigned long long g = (((unsigned long long)khi << 32) | klo) * kXcds + x;
-        // The published job holding tile g; wait while there is none.
+        // The published job holding tile g; wait while there is none (the
+        // job count is read only when g lies beyond the jobs known).
         for (uint32_t spins = 0;; ++spins) {
-            const uint32_t tail = (uint32_t)load_host_word(&q->tail.v);
-            while (j < tail && g >= job_end(jobs, j)) ++j;
+            while (j < tail && g >= jobs[j].end) ++j;
+            if (j < tail) break;
+            tail = (uint32_t)load_host_word(&q->tail.v);
+            while (j < tail && g >= jobs[j].end) ++j;
             if (j < tail) break;
             if (load_host_word(&q->stop.v) || spins >= spin_limit) {
                 if (lane == 0) {
@@ -295,21 +319,11 @@ __global__ __launch_bounds__(kBlock) VDI_EXACT_OCC void k_persist(const PHost *c
             }
             nap(spins);
         }
-        if (j != cur) {
-            // A job this workgroup has not worked on: its record into LDS.
-            auto *src = reinterpret_cast<unsigned long long *>(const_cast<PJob *>(jobs + j));
-            auto *dst = reinterpret_cast<unsigned long long *>(&s_job);
-            for (int i = lane; i < (int)(sizeof(PJob) / 8); i += kBlock)
-                dst[i] = __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            __syncthreads();
-            cur = j;
-        }
-        const PJob &J = s_job;
+        const PJob &J = jobs[j];
         const uint32_t slot = J.slot;
         if (g < J.R.tile0) continue;  // alignment gap before the job
         if (g < (unsigned long long)J.R.tile0 + J.R.ntiles) {
             const uint32_t local = (uint32_t)(g - J.R.tile0);
-            if (lane == 0) __hip_atomic_fetch_add(&done[4 * slot + 2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             for (int i = lane; i <= J.R.V.gnz; i += kBlock) s_gz[i] = J.R.V.gz[i];
             __syncthreads();
             if (J.preview) {
@@ -327,18 +341,17 @@ __global__ __launch_bounds__(kBlock) VDI_EXACT_OCC void k_persist(const PHost *c
             }
             __builtin_amdgcn_s_waitcnt(0);  // this wavefront's stores have completed
             __syncthreads();                // and s_gz is free for the next tile
-            if (lane == 0) {
-                const uint32_t n = __hip_atomic_fetch_add(&done[4 * slot], 1u, __ATOMIC_RELAXED,
-                                                          __HIP_MEMORY_SCOPE_SYSTEM) + 1u;
-                if (n == J.R.ntiles && J.U.ntiles == 0)
-                    __hip_atomic_store(&host_done[slot], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            }
+            if (lane == 0 && tile_done(done + (size_t)kDoneWords * slot, 0, x, J.R.ntiles) && J.U.ntiles == 0)
+                __hip_atomic_store(&host_done[slot], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             continue;
         }
         if (g < J.U.tile0) continue;  // alignment gap before the upsampling tiles
         // Upsampling tile: once every render tile of the job is done.
+        const uint32_t groups = J.R.ntiles < (uint32_t)kXcds ? J.R.ntiles : (uint32_t)kXcds;
         for (uint32_t spins = 0;; ++spins) {
-            if (__hip_atomic_load(&done[4 * slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) >= J.R.ntiles) break;
+            if (__hip_atomic_load(&done[(size_t)kDoneWords * slot + done_word(0, kXcds)], __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_SYSTEM) >= groups)
+                break;
             if (spins >= spin_limit) {
                 if (lane == 0) {
                     __hip_atomic_store(&q->fault.v, 2ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -354,19 +367,13 @@ __global__ __launch_bounds__(kBlock) VDI_EXACT_OCC void k_persist(const PHost *c
         const int px = (int)(local % (uint32_t)tiles_x) * 64 + lane;
         for (int r = 0; r < 4; ++r) {
             const int py = (int)(local / (uint32_t)tiles_x) * 4 + r;
-            if (px < U.W && py < U.H) {
-                const float4 *lo = U.lo;
-                store_px<true>(&U.out[(uint64_t)py * U.W + px],
-                               upsample_px_by([lo](uint64_t i) { return load_px_coherent(lo + i); }, U.w, U.h, U.W,
-                                              U.H, px, py));
-            }
+            // The low-res image lies in memory no cache has held in this launch.
+            if (px < U.W && py < U.H)
+                store_px<true>(&U.out[(uint64_t)py * U.W + px], upsample_px(U.lo, U.w, U.h, U.W, U.H, px, py));
         }
         __builtin_amdgcn_s_waitcnt(0);
-        if (lane == 0) {
-            const uint32_t n = __hip_atomic_fetch_add(&done[4 * slot + 1], 1u, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_SYSTEM) + 1u;
-            if (n == U.ntiles) __hip_atomic_store(&host_done[slot], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        }
+        if (lane == 0 && tile_done(done + (size_t)kDoneWords * slot, 1, x, U.ntiles))
+            __hip_atomic_store(&host_done[slot], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
@@ -582,11 +589,11 @@ hipError_t launch_persist(int32_t fmt, const PHost *ctl, const PJob *host_jobs, 
                           uint32_t *host_done, uint32_t blocks, uint32_t spin_limit, hipStream_t s)
 {
     if (fmt == VDI_F32)
-        k_persist<VDI_F32><<<dim3(blocks), kBlock, 0, s>>>(ctl, host_jobs, q, jobs, done, host_done, spin_limit);
+        k_persist<VDI_F32><<<dim3(blocks), kBlock, 0, s>>>(ctl, host_jobs, q, jobs, jobs, done, host_done, spin_limit);
     else if (fmt == VDI_F16)
-        k_persist<VDI_F16><<<dim3(blocks), kBlock, 0, s>>>(ctl, host_jobs, q, jobs, done, host_done, spin_limit);
+        k_persist<VDI_F16><<<dim3(blocks), kBlock, 0, s>>>(ctl, host_jobs, q, jobs, jobs, done, host_done, spin_limit);
     else
-        k_persist<VDI_BF16><<<dim3(blocks), kBlock, 0, s>>>(ctl, host_jobs, q, jobs, done, host_done, spin_limit);
+        k_persist<VDI_BF16><<<dim3(blocks), kBlock, 0, s>>>(ctl, host_jobs, q, jobs, jobs, done, host_done, spin_limit);
     return hipGetLastError();
 }
 

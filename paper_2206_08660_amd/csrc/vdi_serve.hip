@@ -90,17 +90,28 @@ struct Lane {
 // after kPersistIdle with nothing to do, the host stops it once its
 // published requests are done, and the next request starts a new one.
 constexpr uint32_t kPersistJobs = 8192;
+// Low-res images of a launch's D_I > 1 requests are carved in turn from one
+// device buffer that is reused only by the next launch, so that upsampling
+// tiles can read them through the caches (no cache holds an older copy of a
+// line within a launch).  A request that does not fit ends the launch.
+constexpr uint64_t kPersistLowresBytes = 2ull << 30;
+// Completion counters: per job and part (render, upsampling), one counter per
+// XCD group (the tiles k * kXcds + x of XCD x), each on a 128-byte line of
+// its own, and one count of finished groups: the tiles of a job do not all
+// update one word.
 constexpr auto kPersistIdle = std::chrono::milliseconds(20);
-// Sleeps (about 3.4 us each) a workgroup waits for work before it gives up
-// and flags the launch as failed: far beyond kPersistIdle.
-constexpr uint32_t kPersistSpins = 1u << 19;
+// Sleeps (about 27 us each) a workgroup waits for work before it gives up
+// and flags the launch as failed (about 1.8 s): far beyond kPersistIdle.
+constexpr uint32_t kPersistSpins = 1u << 16;
 struct Persist {
     hipStream_t kstream = nullptr;                     // the launches
     hipEvent_t end = nullptr;
     PQueue *d_q = nullptr;
     PJob *d_jobs = nullptr, *h_jobs = nullptr;          // kPersistJobs records, device / coherent host
     PHost *h_ctl = nullptr;                            // job count and stop word (coherent host memory)
-    uint32_t *d_done = nullptr;                        // 4 * kPersistJobs tile counters
+    uint32_t *d_done = nullptr;                        // kPersistJobs * kDoneWords tile counters
+    float4 *d_lowres = nullptr;                        // kPersistLowresBytes of low-res images
+    uint64_t lowres_used = 0;                          // bytes of it given out in this launch
     uint32_t *h_done = nullptr;                        // kPersistJobs completion flags (coherent host memory)
     uint32_t blocks = 0;
     bool running = false, ending = false;
@@ -264,7 +275,7 @@ void persist_launch(vdi_server_s *s, int32_t fmt)
     __atomic_store_n(&P.h_ctl->tail.v, 0ull, __ATOMIC_RELEASE);
     __atomic_store_n(&P.h_ctl->stop.v, 0ull, __ATOMIC_RELEASE);
     hipError_t e = hipMemsetAsync(P.d_q, 0, sizeof(PQueue), P.kstream);
-    if (e == hipSuccess) e = hipMemsetAsync(P.d_done, 0, sizeof(uint32_t) * 4 * kPersistJobs, P.kstream);
+    if (e == hipSuccess) e = hipMemsetAsync(P.d_done, 0, sizeof(uint32_t) * kDoneWords * kPersistJobs, P.kstream);
     if (e == hipSuccess)
         e = launch_persist(fmt, P.h_ctl, P.h_jobs, P.d_q, P.d_jobs, P.d_done, P.h_done, P.blocks, kPersistSpins,
                            P.kstream);
@@ -278,6 +289,7 @@ void persist_launch(vdi_server_s *s, int32_t fmt)
     P.fmt = fmt;
     P.used = 0;
     P.tiles = 0;
+    P.lowres_used = 0;
     P.mem_epoch = g_mem_epoch.load();
     P.idle_since = std::chrono::steady_clock::now();
     s->st.batches++;
@@ -296,13 +308,20 @@ void persist_pump(vdi_server_s *s)
         const uint64_t t0 = align_up(P.tiles);
         const uint64_t u0 = align_up(t0 + r.job.ntiles);
         const uint64_t end = r.down ? u0 + r.up.ntiles : t0 + r.job.ntiles;
-        if (r.fmt != P.fmt || P.used >= kPersistJobs || end >= (1ull << 31) || g_mem_epoch.load() != P.mem_epoch) {
+        const uint64_t lowres = (r.lowres_bytes + 255) / 256 * 256;
+        if (r.fmt != P.fmt || P.used >= kPersistJobs || end >= (1ull << 31) || g_mem_epoch.load() != P.mem_epoch ||
+            P.lowres_used + lowres > kPersistLowresBytes) {
             P.ending = true;
             return;
         }
         const uint32_t j = P.used++;
         r.slot = j;
         r.job.tile0 = (uint32_t)t0;
+        if (r.down) {
+            r.job.F.out = P.d_lowres + P.lowres_used / sizeof(float4);
+            r.up.lo = r.job.F.out;
+            P.lowres_used += lowres;
+        }
         PJob &J = P.h_jobs[j];
         J.R = r.job;
         J.U = r.up;
@@ -357,11 +376,15 @@ std::string persist_diagnose(vdi_server_s *s)
     for (int x = 0; x < kXcds; ++x) d += " " + std::to_string(q.next[x].v);
     for (size_t i = 0; i < P.published.size() && i < 3; ++i) {
         const Request &r = s->requests.at(P.published[i]);
-        uint32_t c[4] = {0, 0, 0, 0};
-        (void)hipMemcpy(c, P.d_done + 4 * r.slot, sizeof c, hipMemcpyDeviceToHost);
+        std::vector<uint32_t> c(kDoneWords);
+        (void)hipMemcpy(c.data(), P.d_done + (size_t)kDoneWords * r.slot, sizeof(uint32_t) * kDoneWords,
+                        hipMemcpyDeviceToHost);
+        uint32_t rt = 0, ut = 0;
+        for (int x = 0; x < kXcds; ++x) rt += c[done_word(0, x)], ut += c[done_word(1, x)];
         const PJob &J = P.h_jobs[r.slot];
-        snprintf(buf, sizeof buf, "; slot %u: render %u/%u (taken %u) from tile %u, upsample %u/%u from %u, end %u, flag %u",
-                 r.slot, c[0], J.R.ntiles, c[2], J.R.tile0, c[1], J.U.ntiles, J.U.tile0, J.end,
+        snprintf(buf, sizeof buf, "; slot %u: render %u/%u (groups %u) from tile %u, upsample %u/%u (groups %u) from %u, end %u, flag %u",
+                 r.slot, rt, J.R.ntiles, c[done_word(0, kXcds)], J.R.tile0, ut, J.U.ntiles, c[done_word(1, kXcds)],
+                 J.U.tile0, J.end,
                  __atomic_load_n(&P.h_done[r.slot], __ATOMIC_ACQUIRE));
         d += buf;
     }
@@ -490,6 +513,7 @@ void release(vdi_server_s *s)
         if (P.d_q) (void)hipFree(P.d_q);
         if (P.d_jobs) (void)hipFree(P.d_jobs);
         if (P.d_done) (void)hipFree(P.d_done);
+        if (P.d_lowres) (void)hipFree(P.d_lowres);
         if (P.h_jobs) (void)hipHostFree(P.h_jobs);
         if (P.h_ctl) (void)hipHostFree(P.h_ctl);
         if (P.h_done) (void)hipHostFree(P.h_done);
@@ -533,7 +557,10 @@ int submit(vdi_server_t s, vdi_t v, const vdi_camera *cam, int32_t W, int32_t H,
                               (unsigned long long)bytes, (unsigned long long)s->st.bytes_in_flight,
                               (unsigned long long)s->budget);
     }
-    if (down) {
+    if (down && s->P && lowres_bytes > vdi::kPersistLowresBytes)
+        return vdi::set_error(VDI_ERR_ARG, "low-res image of %llu bytes exceeds the persistent server's %llu",
+                              (unsigned long long)lowres_bytes, (unsigned long long)vdi::kPersistLowresBytes);
+    if (down && !s->P) {
         auto it = s->free_lowres.find(lowres_bytes);
         if (it != s->free_lowres.end()) {
             r.lowres = it->second;
@@ -855,7 +882,8 @@ int vdi_server_create_persistent(uint64_t hbm_budget_bytes, int32_t max_inflight
     if (e == hipSuccess) what = "event", e = hipEventCreateWithFlags(&P.end, hipEventDisableTiming);
     if (e == hipSuccess) what = "job queue", e = hipMalloc((void **)&P.d_q, sizeof(vdi::PQueue));
     if (e == hipSuccess) e = hipMalloc((void **)&P.d_jobs, sizeof(vdi::PJob) * vdi::kPersistJobs);
-    if (e == hipSuccess) e = hipMalloc((void **)&P.d_done, sizeof(uint32_t) * 4 * vdi::kPersistJobs);
+    if (e == hipSuccess) e = hipMalloc((void **)&P.d_done, sizeof(uint32_t) * vdi::kDoneWords * vdi::kPersistJobs);
+    if (e == hipSuccess) what = "low-res images", e = hipMalloc((void **)&P.d_lowres, vdi::kPersistLowresBytes);
     if (e == hipSuccess)
         e = hipHostMalloc((void **)&P.h_jobs, sizeof(vdi::PJob) * vdi::kPersistJobs, hipHostMallocCoherent);
     if (e == hipSuccess) e = hipHostMalloc((void **)&P.h_ctl, sizeof(vdi::PHost), hipHostMallocCoherent);

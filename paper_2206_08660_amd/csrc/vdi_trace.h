@@ -29,6 +29,12 @@ namespace vdi {
 // Per-ray functions are host-callable too, so the traversal can be stepped
 // through on the CPU with the same code.
 #define VDI_HD __host__ __device__
+// The per-ray walkers are inlined into every kernel: called out of line, a
+// walker takes the frame and VDI constants through a pointer in vector
+// registers and a stack frame of over 200 bytes per lane (the batched
+// kernels lost half their speed that way once the persistent kernel added
+// call sites and the inliner stopped inlining them).
+#define VDI_HDI __host__ __device__ __forceinline__
 
 // Arithmetic helpers: native gfx950 instructions on the device (overloaded
 // on the compilation target), the plain formulas on the host.  The FP64
@@ -460,7 +466,7 @@ VDI_HD inline float2 depth_at(const DevVDI &V, int j, uint64_t lb) { return VDI_
 // each colour load overlapping the following depth load.  p is updated;
 // returns true once the ray has terminated.
 template <int FMT, int SEARCH, bool COUNT>
-VDI_HD bool do_list(const DevVDI &V, const Frame &F, int ix, int iy, int n, double ta, double tb, double Z0,
+VDI_HDI bool do_list(const DevVDI &V, const Frame &F, int ix, int iy, int n, double ta, double tb, double Z0,
                     double Zp, double invZp, Accum &A, int &p, Counters &cnt)
 {
     const uint64_t li = (uint64_t)iy * V.WO + ix;
@@ -625,7 +631,7 @@ VDI_HD inline bool cell_occupied(const DevVDI &V, int cell)
 // current one; with ESS on it crosses grid cells of count 0 in one step
 // (Section 4.3), keeping the current cell and depth slice from step to step.
 template <int FMT, int SEARCH, bool ESS, bool COUNT>
-VDI_HD float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, int px, int py, Counters &cnt)
+VDI_HDI float4 trace_exact(const DevVDI &V, const Frame &F, const float *s_gz, int px, int py, Counters &cnt)
 {
     Accum A = {0.0f, 0.0f, 0.0f, 1.0f};
     Ray r;
@@ -794,7 +800,7 @@ constexpr double kTieShift = 1e-9;
 // supersegment it composited (touched_slots), counted in cnt as samples
 // (lists) and pieces.
 template <int FMT, bool COUNT = false>
-VDI_HD Accum trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, int px, int py, int part = 0,
+VDI_HDI Accum trace_preview(const DevVDI &V, const Frame &F, const float *s_gz, int px, int py, int part = 0,
                            int parts = 1, Counters *cnt = nullptr)
 {
     Accum A = {0.0f, 0.0f, 0.0f, 1.0f};

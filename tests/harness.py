@@ -246,8 +246,75 @@ def serve_benchmark(n: int = 2000, rate: float = 600.0, budget: int = 64 * 2 ** 
     out["idle_small_request"] = idle_overhead(srv, handles[2], inputs.orbit_camera(20.0, bases[2]))
     log(f"idle small request: {out['idle_small_request']}")
     srv.close()
+    out["persistent"] = persistent_benchmark(handles, bases, trace, budget, max_inflight, px, log=log)
     for h in handles:
         h.close()
+    return out
+
+
+def persistent_benchmark(handles, bases, trace, budget: int, max_inflight: int, px: int, log: Callable = print):
+    """The same traces served by one persistent kernel (vdi_server_create_persistent),
+    and the idle small request through it."""
+    import torch
+
+    import inputs
+    n = len(trace[0])
+    srv = Server(budget, max_inflight, persistent=True)
+    warm = tuple(a[:64] for a in trace)
+    run_served(handles, bases, (warm[0] * 0.0, *warm[1:]), budget, max_inflight, server=srv)
+    torch.cuda.synchronize()
+    out = {"engine": "one persistent kernel (vdi_server_create_persistent), full occupancy; the same traces"}
+    for name, tr in ((f"poisson_{600:g}_per_s", trace), ("saturation", (trace[0] * 0.0, *trace[1:]))):
+        lat, makespan, stats, _ = run_served(handles, bases, tr, budget, max_inflight, server=srv, log=log)
+        log(f"{name} persistent: {n} requests in {makespan:.2f}s, p50 {np.percentile(lat, 50)*1e3:.2f} ms, "
+            f"p99 {np.percentile(lat, 99)*1e3:.2f} ms, {stats['batches']} launches")
+        out[name] = {**_percentiles(lat), "Mpixels_per_s": round(px / makespan / 1e6, 1),
+                     "requests_per_s": round(n / makespan, 1), "launches": stats["batches"],
+                     "peak_inflight": stats["peak_inflight"]}
+    # One small request at a time on an otherwise idle GPU (the launch stays resident between them).
+    cam = inputs.orbit_camera(20.0, bases[2])
+    o = torch.empty((128, 128, 4), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    served = []
+    with _no_gc():
+        for _ in range(200):
+            t0 = time.perf_counter()
+            t = srv.submit(handles[2], cam, 128, 128, 1.0, 0.0, o)
+            assert t is not None, "small request rejected"
+            while not srv.poll(t):
+                time.sleep(0)
+            served.append(time.perf_counter() - t0)
+    out["idle_small_request_p50_ms"] = round(float(np.median(served)) * 1e3, 4)
+    log(f"idle small request, persistent: {out['idle_small_request_p50_ms']} ms")
+    # Each output of the mix alone on an idle GPU (1080p VDI at 20 deg):
+    # through the persistent launch, then (after it has ended) vdi_render + sync.
+    single = {}
+    for k, (W, H, di, dr) in enumerate(OUTPUTS):
+        buf = torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        ts = []
+        with _no_gc():
+            for _ in range(30):
+                t0 = time.perf_counter()
+                t = srv.submit(handles[2], cam, W, H, di, dr, buf)
+                while not srv.poll(t):
+                    time.sleep(0)
+                ts.append(time.perf_counter() - t0)
+        single[f"{W}x{H},D_I={di:g},D_R={dr:g}"] = {"persistent_ms": round(float(np.median(ts[5:])) * 1e3, 4)}
+    srv.close()
+    s = torch.cuda.current_stream()
+    for k, (W, H, di, dr) in enumerate(OUTPUTS):
+        buf = torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
+        ts = []
+        with _no_gc():
+            for _ in range(30):
+                t0 = time.perf_counter()
+                handles[2].render(cam, W, H, di, dr, out=buf, stream=s)
+                s.synchronize()
+                ts.append(time.perf_counter() - t0)
+        single[f"{W}x{H},D_I={di:g},D_R={dr:g}"]["vdi_render_and_sync_ms"] = round(float(np.median(ts[5:])) * 1e3, 4)
+    out["single_requests_idle"] = single
+    log(f"single requests, persistent vs direct: {single}")
     return out
 
 
