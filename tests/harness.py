@@ -263,7 +263,7 @@ def persistent_benchmark(handles, bases, trace, budget: int, max_inflight: int, 
     warm = tuple(a[:64] for a in trace)
     run_served(handles, bases, (warm[0] * 0.0, *warm[1:]), budget, max_inflight, server=srv)
     torch.cuda.synchronize()
-    out = {"engine": "one persistent kernel (vdi_server_create_persistent), full occupancy; the same traces"}
+    out = {"engine": "one persistent kernel (vdi_server_create_persistent), 5 wavefronts per SIMD; the same traces"}
     for name, tr in ((f"poisson_{600:g}_per_s", trace), ("saturation", (trace[0] * 0.0, *trace[1:]))):
         lat, makespan, stats, _ = run_served(handles, bases, tr, budget, max_inflight, server=srv, log=log)
         log(f"{name} persistent: {n} requests in {makespan:.2f}s, p50 {np.percentile(lat, 50)*1e3:.2f} ms, "
