@@ -194,3 +194,38 @@ def test_new_vdi_and_idle_restart(sources, handles):
     rgba = oracle.dequant_f16(sources[0].rgba)
     ne = oracle_check(sources[0], rgba, cam, 128, 128, 1.0, 0.0, a.cpu().numpy(), seed=1)
     assert ne >= 100, ne
+
+
+def test_replacement_swap_starts_a_new_launch(sources):
+    """A VDI (BF16 colour) replaced while a launch is resident: the request
+    before the swap renders the old VDI, the one after it the new VDI,
+    bit-identical to a fresh vdi_create of it, in a new launch (the launch
+    reads VDIs through caches nothing invalidates while it runs)."""
+    from paper_2206_08660_amd import serve
+    from paper_2206_08660_amd import vdi as V
+    b = inputs.load_workload("tiny", base_deg=40.0)
+    cam = inputs.orbit_camera(12.0)
+    with V.Vdi(b, store="bf16") as hb:
+        want_b = hb.render(cam, 96, 80)
+        torch.cuda.synchronize()
+    with V.Vdi(sources[0], store="bf16") as h:
+        want_a = h.render(cam, 96, 80, d_i=2.0, d_r=2.0)
+        torch.cuda.synchronize()
+        o1 = torch.empty((80, 96, 4), dtype=torch.float32, device="cuda")
+        o2 = torch.empty((80, 96, 4), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        with serve.Server(2 ** 34, max_inflight=16, persistent=True) as srv:
+            t = srv.submit(h, cam, 96, 80, 2.0, 2.0, o1)
+            srv.drain()
+            assert srv.poll(t) and srv.stats()["batches"] == 1
+            h.replace_begin(b)
+            t0 = time.time()
+            while not h.replace_poll():
+                assert time.time() - t0 < 20.0, "replacement did not complete"
+                time.sleep(0.001)
+            t = srv.submit(h, cam, 96, 80, 1.0, 0.0, o2)
+            srv.drain()
+            assert srv.poll(t) and srv.stats()["batches"] == 2
+    assert torch.equal(o1, want_a) and torch.equal(o2, want_b)
+    ne = oracle_check(b, oracle.dequant_bf16(b.rgba), cam, 96, 80, 1.0, 0.0, o2.cpu().numpy(), seed=2)
+    assert ne >= 100, ne
