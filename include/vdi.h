@@ -507,7 +507,10 @@ int vdi_server_create(uint64_t hbm_budget_bytes, int32_t max_inflight, int32_t s
  * published to it, or after 20 ms without requests, and starts a new one
  * for the next request.  While a launch is resident it holds
  * waves_per_simd wavefronts on every SIMD (0: as many as fit, 5), which
- * other kernels on the device then do not get.  A workgroup that waits
+ * other kernels on the device then do not get, and work on a stream that
+ * the runtime maps to the launch's hardware queue (a process has four by
+ * default) waits until the launch ends: at the latest 20 ms after the
+ * server runs out of requests.  A workgroup that waits
  * about 1.8 s for work flags the launch as failed (the server then reports
  * VDI_ERR_HIP).
  *   hbm_budget_bytes, max_inflight  as in vdi_server_create.
