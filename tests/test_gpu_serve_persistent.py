@@ -229,3 +229,32 @@ def test_replacement_swap_starts_a_new_launch(sources):
     assert torch.equal(o1, want_a) and torch.equal(o2, want_b)
     ne = oracle_check(b, oracle.dequant_bf16(b.rgba), cam, 96, 80, 1.0, 0.0, o2.cpu().numpy(), seed=2)
     assert ne >= 100, ne
+
+
+def test_1080p_requests_through_both_engines():
+    """Requests at the served workload's full size (1920 x 1080 frames of the
+    1080p VDI, N_S = 50, FP16 colour): exact and D_I = 2 / D_R = 2, through
+    the batched server and the persistent one, each equal to its vdi_render
+    and matching the oracle on the stored colours."""
+    from paper_2206_08660_amd import serve
+    from paper_2206_08660_amd import vdi as V
+    src = inputs.load_workload("1080p", keep_dvr=False)
+    reqs = [(20.0, 1.0, 0.0), (-25.0, 2.0, 2.0)]
+    with V.Vdi(src, store="f16") as h:
+        want = [h.render(inputs.orbit_camera(y), 1920, 1080, di, dr) for (y, di, dr) in reqs]
+        torch.cuda.synchronize()
+        for persistent in (False, True):
+            outs = [torch.empty((1080, 1920, 4), dtype=torch.float32, device="cuda") for _ in reqs]
+            torch.cuda.synchronize()
+            with serve.Server(2 ** 34, max_inflight=8, persistent=persistent) as srv:
+                ts = [srv.submit(h, inputs.orbit_camera(y), 1920, 1080, di, dr, o) for (y, di, dr), o in zip(reqs, outs)]
+                srv.drain()
+                assert all(t is not None and srv.poll(t) for t in ts)
+            for w, o in zip(want, outs):
+                assert torch.equal(w, o), persistent
+            say(f"[gpu] 1080p requests through the {'persistent' if persistent else 'batched'} server: equal to vdi_render")
+    rgba = oracle.dequant_f16(src.rgba)
+    for i, (y, di, dr) in enumerate(reqs):
+        ne = oracle_check(src, rgba, inputs.orbit_camera(y), 1920, 1080, di, dr, outs[i].cpu().numpy(), n=1200, seed=i)
+        say(f"[gpu] 1080p served request yaw {y}, D_I={di}, D_R={dr} vs oracle: {ne} non-empty pixels")
+        assert ne >= 300, ne
