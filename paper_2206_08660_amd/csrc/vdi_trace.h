@@ -335,9 +335,19 @@ VDI_HD inline int win_start_bwd(int p) { return p - kWin / 2; }
 // wavefronts wait on their slowest lane's search, gain from spreading (the
 // 1080p D_I = 2 and 4 sweeps: 3.83 -> 3.70 ms, 1.81 -> 1.74 ms); exact rays,
 // bound more by cache traffic, lose (9.75 -> 9.89 ms) and bisect.
-template <bool SPREAD, typename Below>
+// With `pair` (PICK = k: the pair of window slot J + k, k = 0 or -1): when
+// the answer lies inside the first window, *pair gets that slot's depth
+// pair from the window's registers and *have is set.  The exact walker takes
+// its first supersegment's (f, b) from there instead of loading it again
+// after the search: the window's lines hold both depths, the registers cost
+// no occupancy, and the list's first piece waits one round trip less (1080p
+// sweep 9.88 -> 9.80 ms, images bit-identical; VDI_WIN_PAIR=0 reloads it).
+#ifndef VDI_WIN_PAIR
+#define VDI_WIN_PAIR 1
+#endif
+template <bool SPREAD, int PICK = 0, typename Below>
 VDI_HD inline int window_search(const float2 *__restrict__ dep, uint64_t stride, uint64_t base, int n, int start,
-                                Below below)
+                                Below below, float2 *pair = nullptr, bool *have = nullptr)
 {
     int lo = 0, hi = n;  // J in [lo, hi]
     if (n >= kWin) {
@@ -355,6 +365,14 @@ VDI_HD inline int window_search(const float2 *__restrict__ dep, uint64_t stride,
             lo = w0 + kWin;
         else
             lo = hi = w0 + cnt;
+        if (pair) {
+            const int at = cnt + PICK;  // window slot of the answer
+            float2 d = b[0];
+#pragma unroll
+            for (int k = 1; k < kWin; ++k) d = at == k ? b[k] : d;
+            *pair = d;
+            *have = cnt > 0 && cnt < kWin;
+        }
     }
     if constexpr (!SPREAD) {
         while (lo < hi) {
@@ -399,20 +417,20 @@ VDI_HD inline int window_search(const float2 *__restrict__ dep, uint64_t stride,
 // `start`.
 template <bool SPREAD = false>
 VDI_HD inline int first_back_above_win(const float2 *__restrict__ dep, uint64_t stride, uint64_t base, int n, double z,
-                                       int start)
+                                       int start, float2 *pair = nullptr, bool *have = nullptr)
 {
     const float zb = float_below(z);  // b > z  <=>  b > zb
-    return window_search<SPREAD>(dep, stride, base, n, start, [zb](float2 d) { return d.y <= zb; });
+    return window_search<SPREAD, 0>(dep, stride, base, n, start, [zb](float2 d) { return d.y <= zb; }, pair, have);
 }
 
 // Largest j in [0, n) with f_j < z (-1 if none), window from `start`: one
 // less than the first j with f_j >= z, found as above.
 template <bool SPREAD = false>
 VDI_HD inline int last_front_below_win(const float2 *__restrict__ dep, uint64_t stride, uint64_t base, int n, double z,
-                                       int start)
+                                       int start, float2 *pair = nullptr, bool *have = nullptr)
 {
     const float za = float_above(z);  // f < z  <=>  f < za
-    return window_search<SPREAD>(dep, stride, base, n, start, [za](float2 d) { return d.x < za; }) - 1;
+    return window_search<SPREAD, -1>(dep, stride, base, n, start, [za](float2 d) { return d.x < za; }, pair, have) - 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -493,7 +511,10 @@ VDI_HDI bool do_list(const DevVDI &V, const Frame &F, int ix, int iy, int n, dou
         bool have = false;
         float2 d = make_float2(0.0f, 0.0f);
         if constexpr (SEARCH == VDI_SEARCH_WINDOW) {
-            j = first_back_above_win(dep, stride, lb, n, za, win_start_fwd(p));
+            if constexpr (VDI_WIN_PAIR != 0)
+                j = first_back_above_win(dep, stride, lb, n, za, win_start_fwd(p), &d, &have);
+            else
+                j = first_back_above_win(dep, stride, lb, n, za, win_start_fwd(p));
         } else if (SEARCH == VDI_SEARCH_SEEDED && p >= 0 && p < n) {
             const float2 dp = depth_at(V, p, lb);
             const float2 dq = p > 0 ? depth_at(V, p - 1, lb) : make_float2(-__builtin_huge_valf(), -__builtin_huge_valf());
@@ -550,7 +571,10 @@ VDI_HDI bool do_list(const DevVDI &V, const Frame &F, int ix, int iy, int n, dou
         bool have = false;
         float2 d = make_float2(0.0f, 0.0f);
         if constexpr (SEARCH == VDI_SEARCH_WINDOW) {
-            j = last_front_below_win(dep, stride, lb, n, za, win_start_bwd(p));
+            if constexpr (VDI_WIN_PAIR != 0)
+                j = last_front_below_win(dep, stride, lb, n, za, win_start_bwd(p), &d, &have);
+            else
+                j = last_front_below_win(dep, stride, lb, n, za, win_start_bwd(p));
         } else if (SEARCH == VDI_SEARCH_SEEDED && p >= 0 && p < n) {
             const float2 dp = depth_at(V, p, lb);
             const float2 dq = p + 1 < n ? depth_at(V, p + 1, lb) : make_float2(__builtin_huge_valf(), __builtin_huge_valf());
