@@ -451,8 +451,8 @@ int vdi_image_quality(const float *image, const float *reference, int32_t width,
                       double *psnr, void *stream);
 
 /* ------------------------------------------------------------------------
- * Serving (continuous batching; a build addition, the paper's client renders
- * one request at a time, Section 5).  A server renders requests for any
+ * Serving (continuous batching; not part of the paper's method, whose client
+ * renders one request at a time, Section 5).  A server renders requests for any
  * number of resident VDIs.  Requests are admitted while request slots and the
  * device-memory budget allow, and queued.  Everything queued is launched as
  * one batch as soon as one of the server's streams is free: by the

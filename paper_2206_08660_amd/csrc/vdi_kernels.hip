@@ -137,7 +137,7 @@ __device__ __forceinline__ const J &job_of(const J *__restrict__ jobs, int njobs
 }
 
 template <int FMT, bool PREVIEW>
-__global__ __launch_bounds__(kBlock) VDI_EXACT_OCC void k_render_batch(const BatchJob *__restrict__ jobs, int njobs)
+__device__ __forceinline__ void batch_tile(const BatchJob *__restrict__ jobs, int njobs)
 {
     __shared__ float s_gz[VDI_MAX_GRID_NZ + 1];
     const BatchJob &J = job_of(jobs, njobs, blockIdx.x);
@@ -156,6 +156,21 @@ __global__ __launch_bounds__(kBlock) VDI_EXACT_OCC void k_render_batch(const Bat
         Counters cnt = {0, 0};
         J.F.out[(uint64_t)py * J.F.W + px] = trace_exact<FMT, VDI_SEARCH_WINDOW, true, false>(J.V, J.F, s_gz, px, py, cnt);
     }
+}
+
+// Exact tiles at the exact kernel's occupancy (6 wavefronts per SIMD);
+// preview tiles at the preview kernel's (its registers, 5 wavefronts): held
+// to 80 VGPRs the preview loop spilled, and the benchmark step took
+// 9.95-10.09 ms against 9.74-9.83 ms.
+template <int FMT>
+__global__ __launch_bounds__(kBlock) VDI_EXACT_OCC void k_render_batch(const BatchJob *__restrict__ jobs, int njobs)
+{
+    batch_tile<FMT, false>(jobs, njobs);
+}
+template <int FMT>
+__global__ __launch_bounds__(kBlock) void k_render_batch_preview(const BatchJob *__restrict__ jobs, int njobs)
+{
+    batch_tile<FMT, true>(jobs, njobs);
 }
 
 __global__ __launch_bounds__(256) void k_upsample_batch(const UpsampleJob *__restrict__ jobs, int njobs)
@@ -550,15 +565,15 @@ hipError_t launch_batch_render(const BatchJob *jobs, int32_t njobs, uint32_t nbl
     const dim3 g(nblocks);
     if (preview) {
         switch (fmt) {
-        case VDI_F16: k_render_batch<VDI_F16, true><<<g, kBlock, 0, s>>>(jobs, njobs); break;
-        case VDI_BF16: k_render_batch<VDI_BF16, true><<<g, kBlock, 0, s>>>(jobs, njobs); break;
-        default: k_render_batch<VDI_F32, true><<<g, kBlock, 0, s>>>(jobs, njobs); break;
+        case VDI_F16: k_render_batch_preview<VDI_F16><<<g, kBlock, 0, s>>>(jobs, njobs); break;
+        case VDI_BF16: k_render_batch_preview<VDI_BF16><<<g, kBlock, 0, s>>>(jobs, njobs); break;
+        default: k_render_batch_preview<VDI_F32><<<g, kBlock, 0, s>>>(jobs, njobs); break;
         }
     } else {
         switch (fmt) {
-        case VDI_F16: k_render_batch<VDI_F16, false><<<g, kBlock, 0, s>>>(jobs, njobs); break;
-        case VDI_BF16: k_render_batch<VDI_BF16, false><<<g, kBlock, 0, s>>>(jobs, njobs); break;
-        default: k_render_batch<VDI_F32, false><<<g, kBlock, 0, s>>>(jobs, njobs); break;
+        case VDI_F16: k_render_batch<VDI_F16><<<g, kBlock, 0, s>>>(jobs, njobs); break;
+        case VDI_BF16: k_render_batch<VDI_BF16><<<g, kBlock, 0, s>>>(jobs, njobs); break;
+        default: k_render_batch<VDI_F32><<<g, kBlock, 0, s>>>(jobs, njobs); break;
         }
     }
     return hipGetLastError();

@@ -1,12 +1,14 @@
-// Served form of libvdi: continuous batching of render requests (build
-// addition; the paper's client renders one request at a time, Section 5).
+// Served form of libvdi: continuous batching of render requests (not part
+// of the paper's method, whose client renders one request at a time,
+// Section 5).
 //
 // Requests are admitted while request slots and the device-memory budget
 // allow, and queued.  Everything queued is launched as one batch as soon as
 // one of the server's streams is free, by the submitting thread if a stream
 // is free when it submits, otherwise by a scheduler thread: one launch per
 // (mode, colour format) group renders the tiles of all of the group's
-// requests (k_render_batch), and one more upsamples those with D_I > 1
+// requests (k_render_batch for exact tiles, k_render_batch_preview for
+// preview tiles), and one more upsamples those with D_I > 1
 // (k_upsample_batch).  With two or more streams the next batch starts while
 // the previous one drains, so the tail of one batch is filled with the next
 // one's tiles and the GPU does not idle between requests.  A request is done
