@@ -342,8 +342,20 @@ VDI_HD inline int win_start_bwd(int p) { return p - kWin / 2; }
 // after the search: the window's lines hold both depths, the registers cost
 // no occupancy, and the list's first piece waits one round trip less (1080p
 // sweep 9.88 -> 9.80 ms, images bit-identical; VDI_WIN_PAIR=0 reloads it).
+// Without SPREAD, an answer outside the first window is looked for next in
+// VDI_WIN2 further windows, each the kWin slots next to what is left on the
+// answer's side, and only then bisected (the pair, if asked for, comes from
+// the window that holds the answer).  Most answers a window misses lie just
+// past its end, and a wavefront waits for the slowest lane's search: one
+// more round trip for the lanes that missed instead of a bisection of up to
+// six (1080p sweep 9.85 -> 9.61 ms, benchmark step 9.67-9.74 -> 9.50-9.53
+// ms, images bit-identical; two further windows: 10.15 ms, VDI_WIN2=0:
+// bisection right after the first window).
 #ifndef VDI_WIN_PAIR
 #define VDI_WIN_PAIR 1
+#endif
+#ifndef VDI_WIN2
+#define VDI_WIN2 1
 #endif
 template <bool SPREAD, int PICK = 0, typename Below>
 VDI_HD inline int window_search(const float2 *__restrict__ dep, uint64_t stride, uint64_t base, int n, int start,
@@ -372,6 +384,36 @@ VDI_HD inline int window_search(const float2 *__restrict__ dep, uint64_t stride,
             for (int k = 1; k < kWin; ++k) d = at == k ? b[k] : d;
             *pair = d;
             *have = cnt > 0 && cnt < kWin;
+        }
+        if constexpr (!SPREAD && VDI_WIN2 != 0) {
+            const bool up = cnt == kWin;
+#pragma unroll
+            for (int e = 0; e < VDI_WIN2; ++e) {
+                if (lo >= hi) break;
+                // One more window next to the bracket, on the answer's side.
+                const int w1 = up ? min(lo, n - kWin) : max(0, hi - kWin);
+                const float2 *v = dep + base + (uint64_t)w1 * stride;
+                float2 c[kWin];
+#pragma unroll
+                for (int k = 0; k < kWin; ++k) c[k] = VDI_LOAD(v + k * stride, 2);
+                int c2 = 0;
+#pragma unroll
+                for (int k = 0; k < kWin; ++k) c2 += below(c[k]) ? 1 : 0;
+                if (c2 == 0)
+                    hi = min(hi, w1);
+                else if (c2 == kWin)
+                    lo = max(lo, w1 + kWin);
+                else
+                    lo = hi = w1 + c2;
+                if (pair && c2 > 0 && c2 < kWin) {
+                    const int at = c2 + PICK;
+                    float2 d = c[0];
+#pragma unroll
+                    for (int k = 1; k < kWin; ++k) d = at == k ? c[k] : d;
+                    *pair = d;
+                    *have = true;
+                }
+            }
         }
     }
     if constexpr (!SPREAD) {
