@@ -295,10 +295,15 @@ VDI_HD inline int last_front_below(const float2 *__restrict__ dep, uint64_t stri
 // p itself for only a third.  The back (forward rays) or front (backward rays)
 // depths of kWin slots around the seed are therefore loaded together, in one
 // round trip; being sorted, the number of them on the near side of z is the
-// answer's offset in the window.  Only an answer outside the window costs a
-// binary search of the rest of the list.  Every load is clamped into the list.
+// answer's offset in the window.  An answer outside the window is looked for
+// in the windows next to it, and only then in the rest of the list (below).
+// Every load is clamped into the list.  kWin = 4 with up to two further
+// windows: a miss costs a round trip more, a hit fewer lines than a window
+// of 8 (1080p benchmark step, 2 x 2 bricks, images bit-identical: 4 + 2
+// further windows 8.89-8.92 ms; 4 + 3 8.93-8.96; 5 + 2 8.96; 3 + 3 8.99;
+// 6 + 1 9.00-9.02; 8 + 1 9.35-9.42; 12 + 1 11.50).
 #ifndef VDI_WIN
-#define VDI_WIN 8
+#define VDI_WIN 4
 #endif
 constexpr int kWin = VDI_WIN;
 
@@ -342,20 +347,27 @@ VDI_HD inline int win_start_bwd(int p) { return p - kWin / 2; }
 // after the search: the window's lines hold both depths, the registers cost
 // no occupancy, and the list's first piece waits one round trip less (1080p
 // sweep 9.88 -> 9.80 ms, images bit-identical; VDI_WIN_PAIR=0 reloads it).
-// Without SPREAD, an answer outside the first window is looked for next in
-// VDI_WIN2 further windows, each the kWin slots next to what is left on the
-// answer's side, and only then bisected (the pair, if asked for, comes from
-// the window that holds the answer).  Most answers a window misses lie just
-// past its end, and a wavefront waits for the slowest lane's search: one
-// more round trip for the lanes that missed instead of a bisection of up to
-// six (1080p sweep 9.85 -> 9.61 ms, benchmark step 9.67-9.74 -> 9.50-9.53
-// ms, images bit-identical; two further windows: 10.15 ms, VDI_WIN2=0:
-// bisection right after the first window).
+// An answer outside the first window is looked for next in VDI_WIN2 (without
+// SPREAD) or VDI_WIN2_SPREAD (with it) further windows, each the kWin slots
+// next to what is left on the answer's side, and only then bisected or
+// spread over (the pair, if asked for, comes from the window that holds the
+// answer).  Most answers a window misses lie just past its end, and a
+// wavefront waits for the slowest lane's search: a round trip more for the
+// lanes that missed instead of a bisection of up to six, or of up to three
+// spread round trips.  With 8-slot windows, 1080p, images bit-identical:
+// exact sweep 9.85 -> 9.61 ms with one further window (two: 10.15 ms);
+// preview sweeps D_I = 2 3.78 -> 3.55 ms, D_I = 4 1.82 -> 1.75 ms (two:
+// 3.57, 1.77 ms); benchmark step 9.70 -> 9.51 ms with the exact one, 9.51
+// -> 9.35 ms with the preview's as well.  Smaller windows want more of them
+// (kWin, above).  Zero restores the search straight after the first window.
 #ifndef VDI_WIN_PAIR
 #define VDI_WIN_PAIR 1
 #endif
 #ifndef VDI_WIN2
-#define VDI_WIN2 1
+#define VDI_WIN2 2
+#endif
+#ifndef VDI_WIN2_SPREAD
+#define VDI_WIN2_SPREAD 2
 #endif
 template <bool SPREAD, int PICK = 0, typename Below>
 VDI_HD inline int window_search(const float2 *__restrict__ dep, uint64_t stride, uint64_t base, int n, int start,
@@ -385,10 +397,10 @@ VDI_HD inline int window_search(const float2 *__restrict__ dep, uint64_t stride,
             *pair = d;
             *have = cnt > 0 && cnt < kWin;
         }
-        if constexpr (!SPREAD && VDI_WIN2 != 0) {
+        if constexpr ((SPREAD ? VDI_WIN2_SPREAD : VDI_WIN2) != 0) {
             const bool up = cnt == kWin;
 #pragma unroll
-            for (int e = 0; e < VDI_WIN2; ++e) {
+            for (int e = 0; e < (SPREAD ? VDI_WIN2_SPREAD : VDI_WIN2); ++e) {
                 if (lo >= hi) break;
                 // One more window next to the bracket, on the answer's side.
                 const int w1 = up ? min(lo, n - kWin) : max(0, hi - kWin);
