@@ -51,7 +51,8 @@ extern "C" {
 #define VDI_SEARCH_SEEDED 0 /* seeded by the index found in the previous list (supplement Alg. S2) */
 #define VDI_SEARCH_BINARY 1 /* binary search over the whole list, from the middle */
 #define VDI_SEARCH_LINEAR 2 /* linear scan from the list's near end */
-#define VDI_SEARCH_WINDOW 3 /* seeded, with 8 slots around the seed compared at once (default) */
+#define VDI_SEARCH_WINDOW 3 /* seeded: 4 slots around the seed compared at once, then up to two
+                               windows of 4 next to them, then the rest (default) */
 
 #define VDI_MAX_SUPERSEGMENTS 255
 #define VDI_MAX_GRID_NZ 64
